@@ -1,0 +1,250 @@
+"""CPU FP64 oracle of the implicit HGKS on tetrahedral meshes (ctypes wrapper).
+
+TEST INFRASTRUCTURE ONLY.  Only `tests/`, `__graft_entry__.smoke()` and the
+`cpu_baseline` leg of `bench.py` may import this package.  The product library
+(`paper_2304_09485_amd`) never imports, links or executes it, and the two share
+no code: the oracle builds its own geometry, stencils, least-squares fits and
+gas-kinetic flux from the raw mesh arrays.
+
+Each C function in `hgks_oracle.cpp` names the passage of the paper it follows.
+Parity status of every function is listed in the design notes; all functions
+here are pinned by the `-m "not gpu"` tests in `tests/test_oracle_*.py`.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "hgks_oracle.cpp")
+_LIB = os.path.join(_HERE, "liborc.so")
+
+FARFIELD, SLIP, NOSLIP, SUP_IN, SUP_OUT = 0, 1, 2, 3, 4
+WENO, HWENO = 0, 1
+EULER, NS = 0, 1
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with g++ (plain C++17, FP64, no fast-math)."""
+    if force or not os.path.exists(_LIB):
+        cmd = ["g++", "-O2", "-std=c++17", "-fopenmp", "-fPIC", "-shared", "-o", _LIB, _SRC]
+        subprocess.run(cmd, check=True)
+    return _LIB
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build()
+        _lib = ctypes.CDLL(_LIB)
+        _declare(_lib)
+    return _lib
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("scheme", ctypes.c_int32), ("physics", ctypes.c_int32), ("weights", ctypes.c_int32),
+                ("krylov_dim", ctypes.c_int32), ("restarts", ctypes.c_int32),
+                ("jacobi_sweeps", ctypes.c_int32), ("gamma", ctypes.c_double), ("cfl", ctypes.c_double),
+                ("tau_eps", ctypes.c_double), ("tau_C", ctypes.c_double), ("gamma_lin", ctypes.c_double),
+                ("weno_eps", ctypes.c_double), ("mu", ctypes.c_double), ("prandtl", ctypes.c_double),
+                ("fd_sigma", ctypes.c_double)]
+
+
+class StepInfo(ctypes.Structure):
+    _fields_ = [("res", ctypes.c_double), ("gmres_rel", ctypes.c_double),
+                ("n_resid_evals", ctypes.c_int64), ("n_fallbacks", ctypes.c_int64)]
+
+
+_P = ctypes.POINTER
+_d = ctypes.c_double
+_i64 = ctypes.c_int64
+_i32 = ctypes.c_int32
+_vp = ctypes.c_void_p
+
+
+def _declare(L):
+    L.orc_create.restype = _vp
+    L.orc_create.argtypes = [_i64, _vp, _i64, _vp, _i64, _vp, _vp, _i32, _vp, _vp, _P(Options)]
+    L.orc_error.restype = ctypes.c_char_p
+    L.orc_destroy.argtypes = [_vp]
+    L.orc_set_threads.argtypes = [_i32]
+    L.orc_n_cells.argtypes = [_vp]
+    L.orc_n_cells.restype = _i64
+    L.orc_n_faces.argtypes = [_vp]
+    L.orc_n_faces.restype = _i64
+    L.orc_geometry.argtypes = [_vp, _vp, _vp, _vp]
+    L.orc_faces.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp]
+    L.orc_stencil.argtypes = [_vp, _i64, _i32, _vp, _i32]
+    L.orc_stencil.restype = _i32
+    L.orc_dt.argtypes = [_vp, _vp, _vp]
+    L.orc_residual.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp]
+    L.orc_residual.restype = _i64
+    L.orc_side_values.argtypes = [_vp, _vp, _vp, _i64, _i32, _vp]
+    L.orc_side_values.restype = _i32
+    L.orc_face_frame.argtypes = [_vp, _i64, _vp]
+    L.orc_gks_point.argtypes = [_vp, _vp, _vp, _vp, _vp, _d, _vp, _vp]
+    L.orc_moment.argtypes = [_d, _d, _d, _d, _d, _i32, _i32, _i32, _i32, _i32]
+    L.orc_moment.restype = _d
+    L.orc_slope_solve.argtypes = [_d, _d, _d, _d, _d, _vp, _vp]
+    L.orc_euler_jn.argtypes = [_d, _vp, _vp, _vp, _vp]
+    L.orc_diag.argtypes = [_vp, _vp, _vp, _vp]
+    L.orc_precond.argtypes = [_vp, _vp, _vp, _vp, _vp]
+    L.orc_jv.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, _d, _vp]
+    L.orc_jv.restype = _d
+    L.orc_implicit_step.argtypes = [_vp, _vp, _vp, _P(StepInfo)]
+    L.orc_implicit_step.restype = _i32
+    L.orc_res_norm.argtypes = [_vp, _vp]
+    L.orc_res_norm.restype = _d
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def default_options(**kw) -> Options:
+    o = Options(scheme=WENO, physics=EULER, weights=0, krylov_dim=10, restarts=3, jacobi_sweeps=2,
+                gamma=1.4, cfl=10.0, tau_eps=0.1, tau_C=1.0, gamma_lin=0.025, weno_eps=1e-8,
+                mu=0.0, prandtl=1.0, fd_sigma=0.0)
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+def set_threads(n: int) -> None:
+    _load().orc_set_threads(int(n))
+
+
+def moment(U, V, W, lam, K, half, a, b, c, d) -> float:
+    return _load().orc_moment(U, V, W, lam, K, half, a, b, c, d)
+
+
+def slope_solve(U, V, W, lam, K, rhs) -> np.ndarray:
+    r = _f64(rhs)
+    out = np.zeros(5)
+    _load().orc_slope_solve(U, V, W, lam, K, _ptr(r), _ptr(out))
+    return out
+
+
+def euler_jn(gamma, Q, n, x) -> np.ndarray:
+    Q, n, x = _f64(Q), _f64(n), _f64(x)
+    out = np.zeros(5)
+    _load().orc_euler_jn(gamma, _ptr(Q), _ptr(n), _ptr(x), _ptr(out))
+    return out
+
+
+class Oracle:
+    """One mesh + options + boundary kinds + free stream."""
+
+    def __init__(self, mesh, kinds: dict, prim, **opts):
+        L = _load()
+        self.opts = default_options(**opts)
+        xyz, tets, bf, bt = mesh.arrays()
+        n_tags = int(max(max(kinds.keys()), int(bt.max()) if len(bt) else 0)) + 1
+        kot = np.full(n_tags, FARFIELD, dtype=np.int32)
+        for t, k in kinds.items():
+            kot[t] = k
+        self._keep = (xyz, tets, bf, bt, kot)
+        self.prim = _f64(prim)
+        self.h = L.orc_create(len(xyz), _ptr(xyz), len(tets), _ptr(tets), len(bf), _ptr(bf), _ptr(bt),
+                              n_tags, _ptr(kot), _ptr(self.prim), ctypes.byref(self.opts))
+        if not self.h:
+            raise ValueError("oracle: bad mesh: " + L.orc_error().decode())
+        self.N = int(L.orc_n_cells(self.h))
+        self.F = int(L.orc_n_faces(self.h))
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            _load().orc_destroy(self.h)
+            self.h = None
+
+    def geometry(self):
+        vol, cen, m2 = np.zeros(self.N), np.zeros((3, self.N)), np.zeros((6, self.N))
+        _load().orc_geometry(self.h, _ptr(vol), _ptr(cen), _ptr(m2))
+        return vol, cen, m2
+
+    def faces(self):
+        F = self.F
+        L_, R_ = np.zeros(F, np.int32), np.zeros(F, np.int32)
+        S, n, gp = np.zeros(F), np.zeros((3, F)), np.zeros((9, F))
+        _load().orc_faces(self.h, _ptr(L_), _ptr(R_), _ptr(S), _ptr(n), _ptr(gp))
+        return L_, R_, S, n, gp
+
+    def stencil(self, cell: int, which: int = 0):
+        buf = np.zeros(64, np.int32)
+        n = _load().orc_stencil(self.h, cell, which, _ptr(buf), 64)
+        return buf[:n].copy()
+
+    def dt(self, Q):
+        Q = _f64(Q)
+        out = np.zeros(self.N)
+        _load().orc_dt(self.h, _ptr(Q), _ptr(out))
+        return out
+
+    def residual(self, Q, G=None, dt=None, want_grad=False):
+        Q = _f64(Q)
+        G = None if G is None else _f64(G)
+        dt = None if dt is None else _f64(dt)
+        R = np.zeros((5, self.N))
+        Gn = np.zeros((15, self.N)) if want_grad else None
+        fb = _load().orc_residual(self.h, _ptr(Q), _ptr(G), _ptr(dt), _ptr(R), _ptr(Gn))
+        return (R, Gn, int(fb)) if want_grad else R
+
+    def side_values(self, Q, f, side, G=None):
+        Q = _f64(Q)
+        G = None if G is None else _f64(G)
+        out = np.zeros((3, 4, 5))
+        fb = _load().orc_side_values(self.h, _ptr(Q), _ptr(G), int(f), int(side), _ptr(out))
+        return out, int(fb)
+
+    def face_frame(self, f):
+        out = np.zeros(9)
+        _load().orc_face_frame(self.h, int(f), _ptr(out))
+        return out.reshape(3, 3)
+
+    def gks_point(self, Wl, dWl, Wr, dWr, dt, want_qg=False):
+        Wl, dWl, Wr, dWr = _f64(Wl), _f64(dWl), _f64(Wr), _f64(dWr)
+        F = np.zeros(5)
+        QG = np.zeros(5) if want_qg else None
+        _load().orc_gks_point(self.h, _ptr(Wl), _ptr(dWl), _ptr(Wr), _ptr(dWr), float(dt), _ptr(F), _ptr(QG))
+        return (F, QG) if want_qg else F
+
+    def diag(self, Q, dt):
+        Q, dt = _f64(Q), _f64(dt)
+        D = np.zeros(self.N)
+        _load().orc_diag(self.h, _ptr(Q), _ptr(dt), _ptr(D))
+        return D
+
+    def precond(self, Q, dt, r):
+        Q, dt, r = _f64(Q), _f64(dt), _f64(r)
+        out = np.zeros((5, self.N))
+        _load().orc_precond(self.h, _ptr(Q), _ptr(dt), _ptr(r), _ptr(out))
+        return out
+
+    def jv(self, Q, dt, b, v, sigma=0.0, G=None):
+        Q, dt, b, v = _f64(Q), _f64(dt), _f64(b), _f64(v)
+        G = None if G is None else _f64(G)
+        Av = np.zeros((5, self.N))
+        s = _load().orc_jv(self.h, _ptr(Q), _ptr(G), _ptr(dt), _ptr(b), _ptr(v), float(sigma), _ptr(Av))
+        return Av, s
+
+    def implicit_step(self, Q, G=None):
+        """Returns (status, info); Q (and G for HWENO) are updated in place."""
+        assert Q.dtype == np.float64 and Q.flags.c_contiguous
+        info = StepInfo()
+        st = _load().orc_implicit_step(self.h, _ptr(Q), _ptr(G), ctypes.byref(info))
+        return int(st), info
+
+    def res_norm(self, R):
+        R = _f64(R)
+        return _load().orc_res_norm(self.h, _ptr(R))

@@ -1,0 +1,247 @@
+"""Pins of the oracle's kinetic layer (paper Sec. 2, Eq. (flux) and the moment
+systems below it; Sec. 5 collision time) against independent numerics.
+
+Each pin is chosen so that a plausible slip (dropped term, wrong sign, a
+transposed operand, a wrong half-space limit) fails one of them:
+  * Maxwellian moments vs direct quadrature (half and full space);
+  * the 5x5 slope systems vs a numpy solve of a quadrature-built matrix;
+  * zero slopes: flux = time-weighted mix of Euler(Q0) and the KFVS flux,
+    both evaluated by quadrature (exact for any tau);
+  * continuous data: flux = Euler - tau <u psi (a.u + A)> + dt/2 <u psi A>,
+    evaluated by quadrature, and the same equals the Chapman-Enskog
+    Navier-Stokes flux with mu = tau p, Pr = 1 (textbook closed form);
+  * Prandtl fix in the dt -> 0 limit: heat flux scaled by 1/Pr;
+  * point value Q_G(t) = Q + t Q_t for continuous data;
+  * mirror antisymmetry and invariance under rotating (t1, t2) about n.
+"""
+import numpy as np
+import pytest
+from scipy import integrate
+
+from tests import _indep as I
+
+GAM = 1.4
+K = I.KDOF
+
+
+class VQuad:
+    """Tensor quadrature for E[f(u, v, w, s)] under the normalised Maxwellian,
+    s = xi^2 (for K = 2, xi^2 is exponential with rate lam)."""
+
+    def __init__(self, U, V, W, lam, half=0):
+        if half == 0:
+            x, wx = np.polynomial.hermite.hermgauss(24)
+            u, wu = U + x / np.sqrt(lam), wx / np.sqrt(np.pi)
+        else:
+            lo, hi = (0.0, max(U, 0) + 14 / np.sqrt(lam)) if half > 0 else (min(U, 0) - 14 / np.sqrt(lam), 0.0)
+            g, wg = np.polynomial.legendre.leggauss(160)
+            u = 0.5 * (hi - lo) * (g + 1) + lo
+            wu = 0.5 * (hi - lo) * wg * np.sqrt(lam / np.pi) * np.exp(-lam * (u - U) ** 2)
+        x, wx = np.polynomial.hermite.hermgauss(24)
+        v, wv = V + x / np.sqrt(lam), wx / np.sqrt(np.pi)
+        w, ww = W + x / np.sqrt(lam), wx / np.sqrt(np.pi)
+        sx, sw = np.polynomial.laguerre.laggauss(12)
+        s, ws = sx / lam, sw
+        UU, VV, WW, SS = np.meshgrid(u, v, w, s, indexing="ij")
+        self.u, self.v, self.w, self.s = UU.ravel(), VV.ravel(), WW.ravel(), SS.ravel()
+        self.wt = (wu[:, None, None, None] * wv[None, :, None, None] * ww[None, None, :, None]
+                   * ws[None, None, None, :]).ravel()
+        self.psi = np.stack([np.ones_like(self.u), self.u, self.v, self.w,
+                             0.5 * (self.u ** 2 + self.v ** 2 + self.w ** 2 + self.s)])
+
+    def E(self, f):
+        return (self.psi * (self.wt * f)).sum(axis=1)
+
+    def poly(self, a):
+        return a @ self.psi
+
+
+def lam_of(W):
+    rho, U, p = I.prim(W)
+    return rho, U, p, rho / (2 * p)
+
+
+@pytest.fixture(scope="module")
+def orc(oracle_lib):
+    from inputs import cube_mesh, freestream_prim
+    m = cube_mesh(1)
+    return lambda **kw: oracle_lib.Oracle(m, {t: 0 for t in range(1, 7)}, freestream_prim(0.5), **kw)
+
+
+@pytest.mark.parametrize("half", [-1, 0, 1])
+@pytest.mark.parametrize("U,lam", [(0.3, 0.7), (-1.2, 2.5), (2.0, 0.4)])
+def test_moments_vs_quadrature(oracle_lib, half, U, lam):
+    for a in range(7):
+        f = lambda u: u ** a * np.sqrt(lam / np.pi) * np.exp(-lam * (u - U) ** 2)  # noqa: E731
+        lo, hi = {1: (0, np.inf), -1: (-np.inf, 0), 0: (-np.inf, np.inf)}[half]
+        ref = integrate.quad(f, lo, hi, epsabs=0, epsrel=1e-13, limit=200)[0]
+        got = oracle_lib.moment(U, 0.1, -0.2, lam, K, half, a, 0, 0, 0)
+        assert got == pytest.approx(ref, rel=1e-11, abs=1e-13)
+    # v, w and xi moments
+    q = VQuad(U, 0.1, -0.2, lam)
+    for (b, c, d) in [(1, 0, 0), (2, 0, 0), (3, 1, 0), (0, 2, 1), (1, 1, 2), (0, 0, 1)]:
+        ref = np.sum(q.wt * q.v ** b * q.w ** c * q.s ** d)
+        got = oracle_lib.moment(U, 0.1, -0.2, lam, K, 0, 0, b, c, d)
+        assert got == pytest.approx(ref, rel=1e-11)
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_slope_solve_vs_quadrature(oracle_lib, seed):
+    rng = np.random.default_rng(seed)
+    U, V, W = rng.uniform(-1, 1, 3)
+    lam = rng.uniform(0.3, 3)
+    rhs = rng.normal(size=5)
+    M = I.maxwellian_moment_matrix(U, V, W, lam)
+    ref = np.linalg.solve(M, rhs)
+    got = oracle_lib.slope_solve(U, V, W, lam, K, rhs)
+    np.testing.assert_allclose(got, ref, rtol=1e-10, atol=1e-12 * np.abs(ref).max())
+    # <a psi> reproduces the right-hand side
+    q = VQuad(U, V, W, lam)
+    np.testing.assert_allclose(q.E(q.poly(got)), rhs, rtol=1e-10, atol=1e-12)
+
+
+def test_euler_jacobian_vs_complex_step(oracle_lib):
+    rng = np.random.default_rng(3)
+    for _ in range(5):
+        Q = I.cons(rng.uniform(0.5, 2), rng.uniform(-1, 1, 3), rng.uniform(0.3, 2))
+        n = rng.normal(size=3)
+        n /= np.linalg.norm(n)
+        x = rng.normal(size=5)
+        np.testing.assert_allclose(oracle_lib.euler_jn(GAM, Q, n, x), I.euler_jn_cs(Q, n, x), rtol=1e-12,
+                                   atol=1e-13)
+
+
+def _time_integrals(dt, tau):
+    x = dt / tau
+    e, em1 = np.exp(-x), -np.expm1(-x)
+    return (dt - tau * em1, tau * em1)
+
+
+def test_zero_slope_flux_is_euler_kfvs_mix(orc):
+    """Zero slopes: f = (1 - e^{-t/tau}) g0 + e^{-t/tau} (g_l H + g_r (1 - H)),
+    time-averaged; Q0 from half-space moments (all by quadrature)."""
+    o = orc(tau_eps=0.37, tau_C=1.0)
+    Wl = I.cons(1.2, [0.4, 0.1, -0.3], 0.9)
+    Wr = I.cons(0.8, [-0.2, 0.3, 0.2], 0.6)
+    z = np.zeros((3, 5))
+    dt = 0.013
+    rl, Ul, pl, ll = lam_of(Wl)
+    rr, Ur, pr, lr = lam_of(Wr)
+    ql, qr = VQuad(*Ul, ll, +1), VQuad(*Ur, lr, -1)
+    Q0 = rl * ql.E(1.0) + rr * qr.E(1.0)
+    kfvs = rl * ql.E(ql.u) + rr * qr.E(qr.u)
+    tau = (0.37 + abs(pl - pr) / (pl + pr)) * dt
+    T1, T4 = _time_integrals(dt, tau)
+    ref = (T1 * I.euler_flux(Q0, [1, 0, 0]) + T4 * kfvs) / dt
+    got = o.gks_point(Wl, z, Wr, z, dt)
+    np.testing.assert_allclose(got, ref, rtol=1e-10, atol=1e-12)
+
+
+def _continuous_reference(W, dW, tau, dt):
+    """Flux and point value of Eq. (flux) for l = r, by quadrature:
+    F = rho [<u psi> - tau <u psi (a.u + A)> + dt/2 <u psi A>]."""
+    rho, U, p, lam = lam_of(W)
+    M = I.maxwellian_moment_matrix(*U, lam)
+    q = VQuad(*U, lam)
+    vel = [q.u, q.v, q.w]
+    a = [np.linalg.solve(M, dW[d] / rho) for d in range(3)]
+    au = sum(q.poly(a[d]) * vel[d] for d in range(3))
+    A = np.linalg.solve(M, -q.E(au))
+    Ap = q.poly(A)
+    F = rho * (q.E(q.u) - tau * q.E(q.u * (au + Ap)) + 0.5 * dt * q.E(q.u * Ap))
+    QG = rho * (q.E(1.0) - tau * q.E(au + Ap) + (dt - tau) * 0 + dt * q.E(Ap))
+    return F, QG
+
+
+def _ns_closed_form(W, dW, mu, dt, Pr=1.0):
+    """Euler flux minus the Chapman-Enskog viscous flux of BGK with K internal
+    degrees of freedom (stress with bulk term 2/(K+3), heat flux mu/Pr dh)."""
+    rho, U, p = I.prim(W)
+    dr = np.array([dW[d][0] for d in range(3)])
+    dU = np.array([[(dW[d][1 + k] - U[k] * dW[d][0]) / rho for k in range(3)] for d in range(3)])  # dU[d][k]
+    dp = np.array([(GAM - 1) * (dW[d][4] - U @ dW[d][1:4] + 0.5 * U @ U * dW[d][0]) for d in range(3)])
+    div = np.trace(dU)
+    sig = mu * (dU + dU.T - 2.0 / (K + 3) * div * np.eye(3))  # sig[d][k]
+    dh = GAM / (GAM - 1) * (dp[0] / rho - p * dr[0] / rho ** 2)
+    Fv = np.array([0.0, *sig[0], sig[0] @ U + mu / Pr * dh])
+    Qt = -sum(I.euler_jn_cs(W, np.eye(3)[d], dW[d]) for d in range(3))
+    return I.euler_flux(W, [1, 0, 0]) - Fv + 0.5 * dt * I.euler_jn_cs(W, [1, 0, 0], Qt), Qt
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_continuous_flux_vs_quadrature_and_navier_stokes(orc, seed):
+    rng = np.random.default_rng(10 + seed)
+    W = I.cons(rng.uniform(0.7, 1.3), rng.uniform(-0.6, 0.6, 3), rng.uniform(0.5, 1.2))
+    dW = rng.normal(scale=0.3, size=(3, 5))
+    dt = 0.02
+    o = orc(tau_eps=0.1, tau_C=1.0)
+    tau = 0.1 * dt
+    F, QG = o.gks_point(W, dW, W, dW, dt, want_qg=True)
+    Fq, QGq = _continuous_reference(W, dW, tau, dt)
+    np.testing.assert_allclose(F, Fq, rtol=1e-9, atol=1e-11)
+    np.testing.assert_allclose(QG, QGq, rtol=1e-9, atol=1e-11)
+    Fns, Qt = _ns_closed_form(W, dW, tau * I.prim(W)[2], dt)
+    np.testing.assert_allclose(F, Fns, rtol=1e-9, atol=1e-11)
+    # Eq. (point) for continuous data: Q(x_G, dt) = Q + dt Q_t
+    np.testing.assert_allclose(QG, W + dt * Qt, rtol=1e-9, atol=1e-11)
+
+
+def test_euler_limit(orc):
+    """epsilon = C = 0 (tau = 0): continuous data gives F_E + dt/2 J_n Q_t."""
+    o = orc(tau_eps=0.0, tau_C=0.0)
+    W = I.cons(1.1, [0.3, -0.2, 0.1], 0.8)
+    dW = np.random.default_rng(4).normal(scale=0.2, size=(3, 5))
+    F = o.gks_point(W, dW, W, dW, 0.01)
+    ref, _ = _ns_closed_form(W, dW, 0.0, 0.01)
+    np.testing.assert_allclose(F, ref, rtol=1e-11, atol=1e-13)
+
+
+def test_prandtl_fix_small_dt(orc):
+    mu, Pr = 0.05, 0.72
+    o = orc(physics=1, mu=mu, prandtl=Pr, tau_C=1.0)
+    W = I.cons(1.0, [0.5, 0.2, -0.1], 0.7)
+    dW = np.random.default_rng(5).normal(scale=0.2, size=(3, 5))
+    dt = 1e-9
+    F = o.gks_point(W, dW, W, dW, dt)
+    ref, _ = _ns_closed_form(W, dW, mu, 0.0, Pr=Pr)
+    np.testing.assert_allclose(F, ref, rtol=1e-7, atol=1e-9)
+
+
+def _mirror(W):
+    return W * np.array([1, -1, 1, 1, 1])
+
+
+def test_mirror_antisymmetry(orc):
+    o = orc(tau_eps=0.1, tau_C=1.0)
+    rng = np.random.default_rng(6)
+    Wl = I.cons(1.2, [0.4, 0.1, -0.3], 0.9)
+    Wr = I.cons(0.9, [0.1, 0.2, 0.2], 0.7)
+    dl, dr = rng.normal(scale=0.3, size=(2, 3, 5))
+    Mv = np.array([1, -1, 1, 1, 1])
+    F = o.gks_point(Wl, dl, Wr, dr, 0.02)
+    mir = lambda d: np.stack([-Mv * d[0], Mv * d[1], Mv * d[2]])  # noqa: E731
+    F2 = o.gks_point(_mirror(Wr), mir(dr), _mirror(Wl), mir(dl), 0.02)
+    np.testing.assert_allclose(F2, -Mv * F, rtol=1e-11, atol=1e-13)
+
+
+def test_tangent_rotation_invariance(orc):
+    o = orc(tau_eps=0.1, tau_C=1.0)
+    rng = np.random.default_rng(7)
+    Wl = I.cons(1.2, [0.4, 0.1, -0.3], 0.9)
+    Wr = I.cons(0.9, [0.1, 0.2, 0.2], 0.7)
+    dl, dr = rng.normal(scale=0.3, size=(2, 3, 5))
+    th = 0.7
+    R = np.array([[np.cos(th), -np.sin(th)], [np.sin(th), np.cos(th)]])
+
+    def rot_state(W):
+        W = W.copy()
+        W[2:4] = R @ W[2:4]
+        return W
+
+    def rot_der(d):
+        d = np.array([rot_state(x) for x in d])
+        d[1:3] = np.tensordot(R, d[1:3], axes=1)
+        return d
+    F = o.gks_point(Wl, dl, Wr, dr, 0.02)
+    F2 = o.gks_point(rot_state(Wl), rot_der(dl), rot_state(Wr), rot_der(dr), 0.02)
+    np.testing.assert_allclose(F2, rot_state(F), rtol=1e-11, atol=1e-13)
