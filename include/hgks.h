@@ -1,0 +1,166 @@
+/* hgks.h -- C ABI of the MI355X implementation of the implicit high-order
+ * gas-kinetic scheme (HGKS) for steady compressible flow on tetrahedral meshes
+ * (Yang, Pan, Xu, "Implicit high-order gas-kinetic schemes for compressible
+ * flows on three-dimensional unstructured meshes I: steady flows").
+ *
+ * The library evaluates the residual L(Q) of the semi-discrete finite-volume
+ * scheme (Sec. 2, Eq. (semi)-(finite)) with third-order WENO (Sec. 3.2) or
+ * compact HWENO (Sec. 3.3) reconstruction and the time-averaged BGK
+ * gas-kinetic flux (Sec. 2 Eq. (flux), Sec. 4.1), and drives backward-Euler
+ * implicit steps (Sec. 4.1 Eq. (impEuler)-(impsystem)) with restarted,
+ * Jacobi-preconditioned GMRES (Sec. 4.2 Eq. (precond), Algorithm 1) whose
+ * operator is the matrix-free finite-difference product of Eq. (frechet).
+ *
+ * Conventions
+ *   - Every function returns hgks_status (0 = OK, < 0 = error), never throws
+ *     and never aborts; hgks_last_error(ctx) holds a message.
+ *   - Conserved state Q is variable-major [5][N] doubles: rho, rho U, rho V,
+ *     rho W, rho E, in the caller's tet order.  Cell-averaged gradients are
+ *     [15][N] doubles, row var*3 + dir, Cartesian global frame.
+ *   - Host arrays passed in are copied during the call and stay owned by the
+ *     caller; output arrays are caller-allocated.  Device pointers passed to
+ *     the *_dev functions are borrowed for the call, in stream order.
+ *   - All compute runs on the current HIP device on the context's stream.
+ *   - A context is not thread-safe; use one per thread.
+ */
+#ifndef HGKS_H
+#define HGKS_H
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  HGKS_OK = 0,
+  HGKS_EINVAL = -1,  /* bad argument or call order */
+  HGKS_ENOMEM = -2,  /* device or host allocation failed */
+  HGKS_EMESH = -3,   /* non-manifold, inverted or degenerate tet, unmatched boundary face */
+  HGKS_ESTATE = -4,  /* NaN, rho <= 0 or p <= 0 in a state */
+  HGKS_ENOCONV = -5, /* solve did not reach the requested drop */
+  HGKS_EDEVICE = -6  /* HIP runtime error */
+} hgks_status;
+
+enum { HGKS_WENO = 0, HGKS_HWENO = 1 };              /* Sec. 3.2 / Sec. 3.3 */
+enum { HGKS_EULER = 0, HGKS_NS = 1 };                /* collision time of Sec. 5 */
+enum { HGKS_FP64 = 0, HGKS_FP32_INNER = 1 };         /* arithmetic of the GMRES inner operator */
+enum { HGKS_WEIGHTS_NONLINEAR = 0, HGKS_WEIGHTS_LINEAR = 1 }; /* Sec. 3.4 */
+enum { HGKS_FARFIELD = 0, HGKS_SLIP_WALL = 1, HGKS_NOSLIP_ADIABATIC = 2,
+       HGKS_SUP_IN = 3, HGKS_SUP_OUT = 4 };          /* Sec. 5 boundary conditions */
+
+typedef struct {
+  int32_t scheme;        /* HGKS_WENO | HGKS_HWENO */
+  int32_t physics;       /* HGKS_EULER | HGKS_NS */
+  int32_t precision;     /* HGKS_FP64 | HGKS_FP32_INNER */
+  int32_t weights;       /* HGKS_WEIGHTS_NONLINEAR | HGKS_WEIGHTS_LINEAR */
+  int32_t krylov_dim;    /* 10, Sec. 5 (at most 32) */
+  int32_t restarts;      /* 3, Sec. 5 */
+  int32_t jacobi_sweeps; /* 2, Sec. 5 */
+  int32_t reserved;
+  double gamma;          /* 1.4 */
+  double cfl;            /* 10 */
+  double tau_eps;        /* 0.1, inviscid collision time, Sec. 5 */
+  double tau_C;          /* 1, pressure-jump term of the collision time, Sec. 5 */
+  double gamma_lin;      /* 0.025, linear weights gamma_m, Sec. 3.4 */
+  double weno_eps;       /* 1e-8, epsilon of the nonlinear weights */
+  double mu;             /* dynamic viscosity (NS) */
+  double prandtl;        /* Prandtl number (NS), 1 = plain BGK */
+  double fd_sigma;       /* FD step of Eq. (frechet); 0 = sqrt(eps) max(1,rms Q)/rms v */
+  void* stream;          /* hipStream_t to run on; NULL = library-owned stream */
+} hgks_options;
+
+typedef struct {
+  double res;            /* L1 density residual of L(Q^n), divided by the total volume */
+  double res_rel;        /* res / res of the first step of this context */
+  double gmres_rel;      /* last GMRES residual estimate / initial preconditioned norm */
+  int64_t n_resid_evals; /* residual evaluations in the step (33 with m = 10, 3 restarts) */
+  int64_t n_fallbacks;   /* face sides that fell back to first order (positivity) */
+  double t_ms;           /* wall time of the step */
+} hgks_step_info;
+
+typedef struct {
+  int32_t steps;
+  int32_t converged;
+  double res0, res_final, drop;
+  int64_t n_resid_evals;
+  double t_ms;
+} hgks_solve_info;
+
+typedef struct hgks_ctx hgks_ctx;
+
+/* Fill *opts with the paper's defaults (Sec. 5): WENO, Euler, FP64,
+ * nonlinear weights, m = 10, 3 restarts, 2 Jacobi sweeps, CFL 10. */
+void hgks_default_options(hgks_options* opts);
+
+/* Create a context on the current HIP device.  opts is copied. */
+hgks_status hgks_create(const hgks_options* opts, hgks_ctx** out);
+
+/* Load a tetrahedral mesh: xyz [n_nodes][3], tet2node [n_tets][4] (any
+ * orientation of positive volume; a tet's local face p is the one opposite
+ * its local vertex p, Sec. 3.1), boundary triangles bface2node [n_bfaces][3]
+ * with integer tags bface_tag [n_bfaces] (0 <= tag < 256).  Builds faces,
+ * geometry, ghost cells, stencils and the least-squares operators and uploads
+ * them.  HGKS_EMESH on a bad mesh. */
+hgks_status hgks_load_mesh(hgks_ctx* ctx, int64_t n_nodes, const double* xyz, int64_t n_tets,
+                           const int32_t* tet2node, int64_t n_bfaces, const int32_t* bface2node,
+                           const int32_t* bface_tag);
+
+/* Free stream (rho, U, V, W, p) used by far-field and supersonic-inflow
+ * boundaries (Sec. 5). */
+hgks_status hgks_set_freestream(hgks_ctx* ctx, const double prim[5]);
+
+/* Boundary kind for a tag (default HGKS_FARFIELD).  params is unused. */
+hgks_status hgks_set_bc(hgks_ctx* ctx, int32_t tag, int32_t kind, const double* params);
+
+/* Set / get the state (host, [5][N] and optional [15][N] gradients). */
+hgks_status hgks_set_state(hgks_ctx* ctx, const double* Q, const double* gradQ);
+hgks_status hgks_get_state(hgks_ctx* ctx, double* Q, double* gradQ);
+
+/* Residual L(Q) of Eq. (finite) with the time-averaged flux of Sec. 4.1 and
+ * the local time step computed from Q (host arrays).  Q == NULL uses the
+ * current state; gradQ (HWENO) NULL uses the current gradients.
+ * gradQ_new (may be NULL) receives the HWENO gradient update of Eq.
+ * (derivative).  On a non-physical state returns HGKS_ESTATE after writing R. */
+hgks_status hgks_residual(hgks_ctx* ctx, const double* Q, const double* gradQ, double* R,
+                          double* gradQ_new);
+
+/* Local time step Delta t_i of the state Q (host, [N]). */
+hgks_status hgks_time_step(hgks_ctx* ctx, const double* Q, double* dt);
+
+/* Finite-difference Jacobian-vector product of Eq. (frechet) at the current
+ * state with the time step frozen at its value for the current state:
+ * Av = (|Omega|/dt) v - (L(Q + sigma v) - L(Q)) / sigma.  sigma <= 0 selects
+ * the automatic step.  Host arrays [5][N].  *sigma_used may be NULL. */
+hgks_status hgks_jv(hgks_ctx* ctx, const double* v, double sigma, double* Av, double* sigma_used);
+
+/* Jacobi preconditioner of Eq. (precond) built on the approximate matrix of
+ * Eq. (deri-matrix) at the current state: out = P^{-1} r (host [5][N]). */
+hgks_status hgks_precond(hgks_ctx* ctx, const double* r, double* out);
+
+/* One implicit step (body of Algorithm 1); updates the state in place. */
+hgks_status hgks_implicit_step(hgks_ctx* ctx, hgks_step_info* info);
+
+/* Implicit steps until res/res0 <= drop or max_steps; HGKS_ENOCONV if not. */
+hgks_status hgks_solve_steady(hgks_ctx* ctx, double drop, int32_t max_steps, hgks_solve_info* info);
+
+/* Device-pointer twins (caller's HIP stream; NULL = context stream):
+ * Q_dev [5][N] doubles, R_dev [5][N] doubles. */
+hgks_status hgks_residual_dev(hgks_ctx* ctx, const void* Q_dev, void* R_dev, void* stream);
+hgks_status hgks_jv_dev(hgks_ctx* ctx, const void* v_dev, double sigma, void* Av_dev, void* stream);
+
+/* Number of cells / faces of the loaded mesh. */
+int64_t hgks_n_cells(const hgks_ctx* ctx);
+int64_t hgks_n_faces(const hgks_ctx* ctx);
+
+/* Per-kernel timing of the last residual evaluation, in ms (HIP events on
+ * the context stream): names[k] and ms[k] for k < *n (cap entries). */
+hgks_status hgks_kernel_times(hgks_ctx* ctx, const char** names, double* ms, int32_t* n, int32_t cap);
+
+const char* hgks_last_error(const hgks_ctx* ctx);
+void hgks_destroy(hgks_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

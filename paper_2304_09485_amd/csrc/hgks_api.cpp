@@ -1,0 +1,842 @@
+// C ABI of the HGKS library: context, device buffers, residual and FD-Jv
+// pipelines, Jacobi preconditioner and the restarted GMRES of Algorithm 1
+// (Krylov basis resident in HBM, FP64; small Hessenberg least-squares problem
+// on the host as in Sec. 4.3).
+#include "hgks.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "hgks_device.h"
+#include "hgks_kernels.h"
+#include "mesh_prep.h"
+
+using namespace hgks;
+
+namespace {
+
+struct DevAlloc {
+  std::vector<void*> ptrs;
+  hipError_t last = hipSuccess;
+  template <typename T>
+  T* get(size_t n) {
+    void* p = nullptr;
+    if (n == 0) n = 1;
+    hipError_t e = hipMalloc(&p, n * sizeof(T));
+    if (e != hipSuccess) {
+      last = e;
+      return nullptr;
+    }
+    ptrs.push_back(p);
+    return (T*)p;
+  }
+  void free_all() {
+    for (void* p : ptrs) (void)hipFree(p);
+    ptrs.clear();
+  }
+};
+
+template <typename T>
+struct Work {  // per-precision residual work space
+  T* Qx = nullptr;    // [5][NX] extended state of the evaluation point
+  T* coef = nullptr;  // [105][N]
+  T* sv = nullptr;    // [60][2F]
+  T* ff = nullptr;    // [5][F]
+  T* fq = nullptr;    // [5][F]
+  T* dt = nullptr;    // [N]
+  T* Gx = nullptr;    // [15][NX] (HWENO gradients, frozen)
+};
+
+constexpr int MAXM = 32;
+const char* KNAMES[5] = {"ghost", "recon", "side", "flux", "gather"};
+
+}  // namespace
+
+struct hgks_ctx {
+  hgks_options o{};
+  std::string err;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  HostMesh H;
+  bool mesh = false;
+  double prim_inf[5] = {1.0, 0.0, 0.0, 0.0, 1.0 / 1.4};
+  int kind_of_tag[256];
+  bool kinds_dirty = true;
+  DevAlloc A;
+  DevMesh<double> M{};
+  DevMesh<float> Mf{};
+  bool have_f32 = false;
+  int* d_fkind = nullptr;
+  Params P{};
+  // state
+  double* Qc = nullptr;  // [5][N] master state
+  double* Gc = nullptr;  // [15][NX] master gradients (with ghost slots), HWENO
+  bool have_state = false;
+  Work<double> W64;         // W64.Qx holds the base point Q^n with ghosts
+  Work<float> W32;
+  double* Qp64 = nullptr;   // [5][NX] perturbed state Q + sigma v of a Jv
+  float* Qp32 = nullptr;
+  double* dtc = nullptr;    // [N] frozen time step of the current step
+  double* b = nullptr;      // [5][N] base residual
+  double* Gnew = nullptr;   // [15][N]
+  double* lam = nullptr;    // [F]
+  double* D = nullptr;      // [N]
+  double* V = nullptr;      // [(m+1)][5N]
+  double* wv = nullptr, *yv = nullptr, *rv = nullptr, *dQ = nullptr, *t1 = nullptr, *t2 = nullptr;
+  double* b32 = nullptr;    // [5][N] inner-precision base residual
+  double* part = nullptr;   // reduction partials
+  double* sc = nullptr;     // device scalars [64]
+  int* flags = nullptr;     // [0] positivity fallbacks, [1] bad state
+  double res0 = -1.0;
+  // timing of the residual kernels: a pool of event sextets recorded on the
+  // stream, drained (one synchronisation) when full or when read
+  bool prof = false;
+  std::vector<hipEvent_t> evpool;
+  int evused = 0;
+  double ksum[5] = {0, 0, 0, 0, 0};
+  int64_t kcount = 0;
+};
+
+namespace {
+constexpr int EVSETS = 128;
+
+void drain_events(hgks_ctx* ctx) {
+  if (!ctx->prof || ctx->evused == 0) return;
+  (void)hipEventSynchronize(ctx->evpool[6 * ctx->evused - 1]);
+  for (int k = 0; k < ctx->evused; ++k)
+    for (int j = 0; j < 5; ++j) {
+      float ms = 0.f;
+      (void)hipEventElapsedTime(&ms, ctx->evpool[6 * k + j], ctx->evpool[6 * k + j + 1]);
+      ctx->ksum[j] += ms;
+    }
+  ctx->kcount += ctx->evused;
+  ctx->evused = 0;
+}
+
+hipEvent_t* next_events(hgks_ctx* ctx) {
+  if (!ctx->prof) return nullptr;
+  if (ctx->evused == EVSETS) drain_events(ctx);
+  return &ctx->evpool[6 * ctx->evused++];
+}
+}  // namespace
+
+#define HIPCHK(call)                                                 \
+  do {                                                               \
+    hipError_t e_ = (call);                                          \
+    if (e_ != hipSuccess) {                                          \
+      ctx->err = std::string("HIP error: ") + hipGetErrorString(e_); \
+      return HGKS_EDEVICE;                                           \
+    }                                                                \
+  } while (0)
+
+namespace {
+
+void set_params(hgks_ctx* ctx) {
+  Params& P = ctx->P;
+  const hgks_options& o = ctx->o;
+  P.gamma = o.gamma;
+  P.K = (5.0 - 3.0 * o.gamma) / (o.gamma - 1.0);
+  P.tau_eps = o.tau_eps;
+  P.tau_C = o.tau_C;
+  P.gamma_lin = o.gamma_lin;
+  P.weno_eps = o.weno_eps;
+  P.mu = o.mu;
+  P.prandtl = o.prandtl;
+  P.rhoinf = ctx->prim_inf[0];
+  P.uinf0 = ctx->prim_inf[1];
+  P.uinf1 = ctx->prim_inf[2];
+  P.uinf2 = ctx->prim_inf[3];
+  P.pinf = ctx->prim_inf[4];
+  P.physics = o.physics;
+  P.weights = o.weights;
+  P.scheme = o.scheme;
+}
+
+template <typename T>
+hgks_status upload(hgks_ctx* ctx, const std::vector<T>& h, const T*& dst) {
+  T* d = ctx->A.get<T>(h.size());
+  if (!d) return HGKS_ENOMEM;
+  if (!h.empty()) HIPCHK(hipMemcpy(d, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice));
+  dst = d;
+  return HGKS_OK;
+}
+
+template <typename T>
+hgks_status upload_conv(hgks_ctx* ctx, const std::vector<double>& h, const T*& dst) {
+  std::vector<T> c(h.begin(), h.end());
+  return upload(ctx, c, dst);
+}
+
+#define TRY(x)                         \
+  do {                                 \
+    hgks_status s_ = (x);              \
+    if (s_ != HGKS_OK) return s_;      \
+  } while (0)
+
+// floating-point mesh arrays in precision T (integer arrays shared)
+template <typename T>
+hgks_status upload_mesh_fp(hgks_ctx* ctx, DevMesh<T>& M) {
+  const HostMesh& H = ctx->H;
+  TRY(upload_conv(ctx, H.vol, M.vol));
+  TRY(upload_conv(ctx, H.h, M.h));
+  TRY(upload_conv(ctx, H.hdt, M.hdt));
+  TRY(upload_conv(ctx, H.m2s, M.m2s));
+  TRY(upload_conv(ctx, H.fn, M.fn));
+  TRY(upload_conv(ctx, H.fS, M.fS));
+  TRY(upload_conv(ctx, H.fxiL, M.fxiL));
+  TRY(upload_conv(ctx, H.fxiR, M.fxiR));
+  if (ctx->o.scheme == HGKS_HWENO) {
+    TRY(upload_conv(ctx, H.opH, M.opH));
+    TRY(upload_conv(ctx, H.hsub, M.hsub));
+  } else {
+    TRY(upload_conv(ctx, H.opA, M.opA));
+    TRY(upload_conv(ctx, H.opB, M.opB));
+  }
+  return HGKS_OK;
+}
+
+template <typename T>
+hgks_status alloc_work(hgks_ctx* ctx, Work<T>& w) {
+  const HostMesh& H = ctx->H;
+  size_t N = H.N, F = H.F, NX = H.N + H.Nb;
+  w.Qx = ctx->A.get<T>(5 * NX);
+  w.coef = ctx->A.get<T>(105 * N);
+  w.sv = ctx->A.get<T>(60 * 2 * F);
+  w.ff = ctx->A.get<T>(5 * F);
+  w.fq = ctx->A.get<T>(5 * F);
+  w.dt = ctx->A.get<T>(N);
+  w.Gx = ctx->o.scheme == HGKS_HWENO ? ctx->A.get<T>(15 * NX) : nullptr;
+  if (!w.Qx || !w.coef || !w.sv || !w.ff || !w.fq || !w.dt || (ctx->o.scheme == HGKS_HWENO && !w.Gx))
+    return HGKS_ENOMEM;
+  return HGKS_OK;
+}
+
+hgks_status sync_kinds(hgks_ctx* ctx) {
+  if (!ctx->kinds_dirty) return HGKS_OK;
+  const HostMesh& H = ctx->H;
+  std::vector<int> k(H.F);
+  for (int f = 0; f < H.F; ++f) k[f] = H.ftag[f] < 0 ? -1 : ctx->kind_of_tag[H.ftag[f]];
+  HIPCHK(hipMemcpy(ctx->d_fkind, k.data(), k.size() * sizeof(int), hipMemcpyHostToDevice));
+  ctx->kinds_dirty = false;
+  set_params(ctx);
+  return HGKS_OK;
+}
+
+inline size_t n5(const hgks_ctx* ctx) { return (size_t)5 * ctx->H.N; }
+
+// residual pipeline of precision T on an extended state whose cell part is
+// filled; mode 0: out = L, 1: Jv epilogue, 2: L and gradient update
+template <typename T, typename TO>
+void residual_pipeline(hgks_ctx* ctx, const DevMesh<T>& M, Work<T>& w, T* Qx, const T* dt, int mode, TO* out,
+                       const TO* v, const TO* bb, const double* sigma, TO* gout, hipStream_t s) {
+  hipEvent_t* ev = next_events(ctx);
+  if (ev) (void)hipEventRecord(ev[0], s);
+  launch_ghost<T>(M, ctx->P, Qx, (T*)nullptr, s);
+  if (ev) (void)hipEventRecord(ev[1], s);
+  launch_recon<T>(M, ctx->P, Qx, w.Gx, w.coef, s);
+  if (ev) (void)hipEventRecord(ev[2], s);
+  launch_side<T>(M, ctx->P, Qx, w.coef, w.sv, ctx->flags, s);
+  if (ev) (void)hipEventRecord(ev[3], s);
+  launch_flux<T>(M, ctx->P, w.sv, dt, w.ff, w.fq, mode == 2, s);
+  if (ev) (void)hipEventRecord(ev[4], s);
+  launch_gather<T, TO>(M, mode, w.ff, w.fq, out, v, bb, dt, sigma, gout, s);
+  if (ev) (void)hipEventRecord(ev[5], s);
+}
+
+// state expansion into the FP64 work state and its time step
+void expand_state(hgks_ctx* ctx, const double* Q, hipStream_t s) {
+  launch_perturb<double>(Q, nullptr, nullptr, ctx->H.N, ctx->H.N + ctx->H.Nb, ctx->W64.Qx, s);
+}
+
+hgks_status ensure_f32(hgks_ctx* ctx) {
+  if (ctx->have_f32) return HGKS_OK;
+  DevMesh<float>& Mf = ctx->Mf;
+  const DevMesh<double>& M = ctx->M;
+  Mf.N = M.N; Mf.F = M.F; Mf.Nb = M.Nb; Mf.NX = M.NX;
+  Mf.fL = M.fL; Mf.fR = M.fR; Mf.fkind = M.fkind; Mf.cface = M.cface; Mf.gowner = M.gowner; Mf.gface = M.gface;
+  Mf.stn = M.stn; Mf.sstn = M.sstn; Mf.smask = M.smask; Mf.nb4 = M.nb4;
+  TRY(upload_mesh_fp<float>(ctx, Mf));
+  TRY(alloc_work<float>(ctx, ctx->W32));
+  ctx->Qp32 = ctx->A.get<float>((size_t)5 * M.NX);
+  if (!ctx->Qp32) return HGKS_ENOMEM;
+  ctx->have_f32 = true;
+  if (ctx->o.scheme == HGKS_HWENO)
+    launch_convert(ctx->Gc, ctx->W32.Gx, (size_t)15 * (M.N + M.Nb), ctx->stream);
+  return HGKS_OK;
+}
+
+// FD Jacobian-vector product at the current state: out = A v (Eq. (frechet)
+// with the (|Omega|/dt) term of Eq. (impsystem)); uses ctx->dtc, ctx->b.
+hgks_status jv_device(hgks_ctx* ctx, const double* v, double sigma_fixed, double* out, hipStream_t s) {
+  size_t n = n5(ctx);
+  const int N = ctx->H.N, NX = ctx->H.N + ctx->H.Nb;
+  launch_dot(v, v, n, ctx->part, ctx->sc + 1, false, s);
+  bool f32 = ctx->o.precision == HGKS_FP32_INNER;
+  double eps = f32 ? std::ldexp(1.0, -23) : std::ldexp(1.0, -52);
+  launch_sigma(ctx->sc + 1, ctx->sc + 0, (double)n, eps, sigma_fixed, ctx->sc + 2, s);
+  if (!f32) {
+    launch_perturb<double>(ctx->Qc, v, ctx->sc + 2, N, NX, ctx->Qp64, s);
+    residual_pipeline<double, double>(ctx, ctx->M, ctx->W64, ctx->Qp64, ctx->W64.dt, 1, out, v, ctx->b,
+                                      ctx->sc + 2, (double*)nullptr, s);
+  } else {
+    launch_perturb<float>(ctx->Qc, v, ctx->sc + 2, N, NX, ctx->Qp32, s);
+    residual_pipeline<float, double>(ctx, ctx->Mf, ctx->W32, ctx->Qp32, ctx->W32.dt, 1, out, v, ctx->b32,
+                                     ctx->sc + 2, (double*)nullptr, s);
+  }
+  return HGKS_OK;
+}
+
+// Jacobi preconditioner: out = P^{-1} r (uses ctx->lam, ctx->D, W64.Qx = Q^n)
+void precond_device(hgks_ctx* ctx, const double* r, double* out, hipStream_t s) {
+  int K = std::max(0, ctx->o.jacobi_sweeps);
+  // ping-pong between t1/t2 so that the last sweep lands in out
+  double* bufs[2] = {ctx->t1, ctx->t2};
+  double* cur = K == 0 ? out : bufs[0];
+  launch_jacobi<double>(ctx->M, ctx->P, ctx->W64.Qx, ctx->lam, ctx->D, r, nullptr, cur, s);
+  for (int k = 1; k <= K; ++k) {
+    double* nxt = k == K ? out : bufs[k % 2];
+    launch_jacobi<double>(ctx->M, ctx->P, ctx->W64.Qx, ctx->lam, ctx->D, r, cur, nxt, s);
+    cur = nxt;
+  }
+}
+
+// prepare the base point of an implicit step / Jv: W64.Qx = Q^n with ghosts,
+// dt, b = L(Q^n) (HWENO: Gnew), lam, D; the FP32 copies for the inner form.
+hgks_status prepare_base(hgks_ctx* ctx, bool want_grad, hipStream_t s) {
+  const int N = ctx->H.N, NX = N + ctx->H.Nb;
+  TRY(sync_kinds(ctx));
+  HIPCHK(hipMemsetAsync(ctx->flags, 0, 2 * sizeof(int), s));
+  expand_state(ctx, ctx->Qc, s);
+  launch_ghost<double>(ctx->M, ctx->P, ctx->W64.Qx, (double*)nullptr, s);
+  launch_dt<double>(ctx->M, ctx->P, ctx->o.cfl, ctx->W64.Qx, ctx->W64.dt, s);
+  residual_pipeline<double, double>(ctx, ctx->M, ctx->W64, ctx->W64.Qx, ctx->W64.dt, want_grad ? 2 : 0, ctx->b,
+                                    (const double*)nullptr, (const double*)nullptr, (const double*)nullptr,
+                                    want_grad ? ctx->Gnew : (double*)nullptr, s);
+  // the pipeline rewrote the ghosts of W64.Qx from Q^n: still the base point
+  launch_lambda_diag<double>(ctx->M, ctx->P, ctx->W64.Qx, ctx->W64.dt, ctx->lam, ctx->D, s);
+  launch_dot(ctx->Qc, ctx->Qc, n5(ctx), ctx->part, ctx->sc + 0, false, s);
+  if (ctx->o.precision == HGKS_FP32_INNER) {
+    TRY(ensure_f32(ctx));
+    launch_perturb<float>(ctx->Qc, nullptr, nullptr, N, NX, ctx->W32.Qx, s);
+    launch_dt<float>(ctx->Mf, ctx->P, ctx->o.cfl, ctx->W32.Qx, ctx->W32.dt, s);
+    residual_pipeline<float, double>(ctx, ctx->Mf, ctx->W32, ctx->W32.Qx, ctx->W32.dt, 0, ctx->b32,
+                                     (const double*)nullptr, (const double*)nullptr, (const double*)nullptr,
+                                     (double*)nullptr, s);
+  }
+  return HGKS_OK;
+}
+
+hgks_status check_state(hgks_ctx* ctx, hipStream_t s) {
+  int flags[2];
+  launch_check<double>(ctx->W64.Qx, ctx->H.N, ctx->H.N + ctx->H.Nb, ctx->o.gamma, ctx->flags + 1, s);
+  HIPCHK(hipMemcpyAsync(flags, ctx->flags, sizeof(flags), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  if (flags[1]) {
+    ctx->err = "non-physical state (rho <= 0, p <= 0 or NaN)";
+    return HGKS_ESTATE;
+  }
+  return HGKS_OK;
+}
+
+hgks_status require(hgks_ctx* ctx, bool need_state) {
+  if (!ctx) return HGKS_EINVAL;
+  if (!ctx->mesh) {
+    ctx->err = "no mesh loaded";
+    return HGKS_EINVAL;
+  }
+  if (need_state && !ctx->have_state) {
+    ctx->err = "no state set";
+    return HGKS_EINVAL;
+  }
+  return HGKS_OK;
+}
+
+hgks_status upload_gradients(hgks_ctx* ctx, const double* G, hipStream_t s) {
+  // host [15][N] -> Gc [15][NX] cell slots, then ghost gradients
+  const int N = ctx->H.N, NX = N + ctx->H.Nb;
+  for (int k = 0; k < 15; ++k) {
+    if (G)
+      HIPCHK(hipMemcpyAsync(ctx->Gc + (size_t)k * NX, G + (size_t)k * N, (size_t)N * sizeof(double),
+                            hipMemcpyHostToDevice, s));
+    else
+      HIPCHK(hipMemsetAsync(ctx->Gc + (size_t)k * NX, 0, (size_t)N * sizeof(double), s));
+  }
+  return HGKS_OK;
+}
+
+// ghost gradients of Gc and copies into the work spaces
+hgks_status refresh_gradients(hgks_ctx* ctx, hipStream_t s) {
+  if (ctx->o.scheme != HGKS_HWENO) return HGKS_OK;
+  TRY(sync_kinds(ctx));
+  const int N = ctx->H.N, NX = N + ctx->H.Nb;
+  // the ghost kernel fills the state ghosts too; use a scratch state copy
+  expand_state(ctx, ctx->Qc, s);
+  launch_ghost<double>(ctx->M, ctx->P, ctx->W64.Qx, ctx->Gc, s);
+  HIPCHK(hipMemcpyAsync(ctx->W64.Gx, ctx->Gc, (size_t)15 * NX * sizeof(double), hipMemcpyDeviceToDevice, s));
+  // frozen gradients (with ghosts) in the inner precision
+  if (ctx->have_f32) launch_convert(ctx->Gc, ctx->W32.Gx, (size_t)15 * NX, s);
+  (void)N;
+  return HGKS_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
+extern "C" {
+
+void hgks_default_options(hgks_options* o) {
+  std::memset(o, 0, sizeof(*o));
+  o->scheme = HGKS_WENO;
+  o->physics = HGKS_EULER;
+  o->precision = HGKS_FP64;
+  o->weights = HGKS_WEIGHTS_NONLINEAR;
+  o->krylov_dim = 10;
+  o->restarts = 3;
+  o->jacobi_sweeps = 2;
+  o->gamma = 1.4;
+  o->cfl = 10.0;
+  o->tau_eps = 0.1;
+  o->tau_C = 1.0;
+  o->gamma_lin = 0.025;
+  o->weno_eps = 1e-8;
+  o->mu = 0.0;
+  o->prandtl = 1.0;
+  o->fd_sigma = 0.0;
+  o->stream = nullptr;
+}
+
+hgks_status hgks_create(const hgks_options* opts, hgks_ctx** out) {
+  if (!opts || !out) return HGKS_EINVAL;
+  *out = nullptr;
+  if (opts->krylov_dim < 1 || opts->krylov_dim > MAXM || opts->restarts < 1 || opts->jacobi_sweeps < 0 ||
+      !(opts->gamma > 1.0) || !(opts->cfl > 0.0) || opts->scheme < 0 || opts->scheme > 1 || opts->physics < 0 ||
+      opts->physics > 1 || opts->precision < 0 || opts->precision > 1 ||
+      (opts->physics == HGKS_NS && !(opts->mu > 0.0 && opts->prandtl > 0.0)))
+    return HGKS_EINVAL;
+  hgks_ctx* ctx = new (std::nothrow) hgks_ctx;
+  if (!ctx) return HGKS_ENOMEM;
+  ctx->o = *opts;
+  for (int k = 0; k < 256; ++k) ctx->kind_of_tag[k] = HGKS_FARFIELD;
+  if (opts->stream) {
+    ctx->stream = (hipStream_t)opts->stream;
+  } else {
+    if (hipStreamCreate(&ctx->stream) != hipSuccess) {
+      delete ctx;
+      return HGKS_EDEVICE;
+    }
+    ctx->own_stream = true;
+  }
+  set_params(ctx);
+  *out = ctx;
+  return HGKS_OK;
+}
+
+hgks_status hgks_load_mesh(hgks_ctx* ctx, int64_t n_nodes, const double* xyz, int64_t n_tets,
+                           const int32_t* tet2node, int64_t n_bfaces, const int32_t* bface2node,
+                           const int32_t* bface_tag) {
+  if (!ctx) return HGKS_EINVAL;
+  if (ctx->mesh) {
+    ctx->err = "mesh already loaded";
+    return HGKS_EINVAL;
+  }
+  if ((n_bfaces > 0 && (!bface2node || !bface_tag)) || n_bfaces < 0) {
+    ctx->err = "invalid boundary arrays";
+    return HGKS_EINVAL;
+  }
+  int rc = build_host_mesh(ctx->H, n_nodes, xyz, n_tets, tet2node, n_bfaces, bface2node, bface_tag, ctx->err);
+  if (rc != 0) return rc == -3 ? HGKS_EMESH : HGKS_EINVAL;
+  const HostMesh& H = ctx->H;
+  DevMesh<double>& M = ctx->M;
+  M.N = H.N;
+  M.F = H.F;
+  M.Nb = H.Nb;
+  M.NX = H.N + H.Nb;
+  TRY(upload(ctx, H.fL, M.fL));
+  TRY(upload(ctx, H.fR, M.fR));
+  TRY(upload(ctx, H.cface, M.cface));
+  TRY(upload(ctx, H.gowner, M.gowner));
+  TRY(upload(ctx, H.gface, M.gface));
+  if (ctx->o.scheme == HGKS_HWENO) {
+    TRY(upload(ctx, H.nb4, M.nb4));
+  } else {
+    TRY(upload(ctx, H.stn, M.stn));
+    TRY(upload(ctx, H.sstn, M.sstn));
+    TRY(upload(ctx, H.smask, M.smask));
+  }
+  ctx->d_fkind = ctx->A.get<int>(H.F);
+  if (!ctx->d_fkind) return HGKS_ENOMEM;
+  M.fkind = ctx->d_fkind;
+  TRY(upload_mesh_fp<double>(ctx, M));
+  TRY(alloc_work<double>(ctx, ctx->W64));
+  size_t N = H.N, NX = H.N + H.Nb, n = 5 * N;
+  int m = ctx->o.krylov_dim;
+  ctx->Qc = ctx->A.get<double>(n);
+  ctx->Qp64 = ctx->A.get<double>(5 * NX);
+  ctx->Gc = ctx->o.scheme == HGKS_HWENO ? ctx->A.get<double>(15 * NX) : nullptr;
+  ctx->dtc = ctx->A.get<double>(N);
+  ctx->b = ctx->A.get<double>(n);
+  ctx->b32 = ctx->A.get<double>(n);
+  ctx->Gnew = ctx->A.get<double>(15 * N);
+  ctx->lam = ctx->A.get<double>(H.F);
+  ctx->D = ctx->A.get<double>(N);
+  ctx->V = ctx->A.get<double>((size_t)(m + 1) * n);
+  ctx->wv = ctx->A.get<double>(n);
+  ctx->yv = ctx->A.get<double>(n);
+  ctx->rv = ctx->A.get<double>(n);
+  ctx->dQ = ctx->A.get<double>(n);
+  ctx->t1 = ctx->A.get<double>(n);
+  ctx->t2 = ctx->A.get<double>(n);
+  ctx->part = ctx->A.get<double>(REDUCE_PARTS);
+  ctx->sc = ctx->A.get<double>(64 + MAXM + 1);
+  ctx->flags = ctx->A.get<int>(4);
+  if (!ctx->Qc || !ctx->dtc || !ctx->b || !ctx->V || !ctx->flags || !ctx->sc) {
+    ctx->err = "device allocation failed";
+    return HGKS_ENOMEM;
+  }
+  ctx->mesh = true;
+  ctx->kinds_dirty = true;
+  return HGKS_OK;
+}
+
+hgks_status hgks_set_freestream(hgks_ctx* ctx, const double prim[5]) {
+  if (!ctx || !prim) return HGKS_EINVAL;
+  if (!(prim[0] > 0.0 && prim[4] > 0.0)) {
+    ctx->err = "free stream must have rho > 0 and p > 0";
+    return HGKS_EINVAL;
+  }
+  for (int k = 0; k < 5; ++k) ctx->prim_inf[k] = prim[k];
+  set_params(ctx);
+  return HGKS_OK;
+}
+
+hgks_status hgks_set_bc(hgks_ctx* ctx, int32_t tag, int32_t kind, const double* params) {
+  (void)params;
+  if (!ctx) return HGKS_EINVAL;
+  if (tag < 0 || tag > 255 || kind < HGKS_FARFIELD || kind > HGKS_SUP_OUT) {
+    ctx->err = "invalid boundary tag or kind";
+    return HGKS_EINVAL;
+  }
+  ctx->kind_of_tag[tag] = kind;
+  ctx->kinds_dirty = true;
+  return HGKS_OK;
+}
+
+hgks_status hgks_set_state(hgks_ctx* ctx, const double* Q, const double* gradQ) {
+  TRY(require(ctx, false));
+  if (!Q) return HGKS_EINVAL;
+  hipStream_t s = ctx->stream;
+  HIPCHK(hipMemcpyAsync(ctx->Qc, Q, n5(ctx) * sizeof(double), hipMemcpyHostToDevice, s));
+  if (ctx->o.scheme == HGKS_HWENO) {
+    TRY(upload_gradients(ctx, gradQ, s));
+    TRY(refresh_gradients(ctx, s));
+  }
+  ctx->have_state = true;
+  ctx->res0 = -1.0;
+  HIPCHK(hipStreamSynchronize(s));
+  return HGKS_OK;
+}
+
+hgks_status hgks_get_state(hgks_ctx* ctx, double* Q, double* gradQ) {
+  TRY(require(ctx, true));
+  hipStream_t s = ctx->stream;
+  if (Q) HIPCHK(hipMemcpyAsync(Q, ctx->Qc, n5(ctx) * sizeof(double), hipMemcpyDeviceToHost, s));
+  if (gradQ) {
+    const int N = ctx->H.N, NX = N + ctx->H.Nb;
+    for (int k = 0; k < 15; ++k) {
+      if (ctx->Gc)
+        HIPCHK(hipMemcpyAsync(gradQ + (size_t)k * N, ctx->Gc + (size_t)k * NX, (size_t)N * sizeof(double),
+                              hipMemcpyDeviceToHost, s));
+      else
+        std::memset(gradQ + (size_t)k * N, 0, (size_t)N * sizeof(double));
+    }
+  }
+  HIPCHK(hipStreamSynchronize(s));
+  return HGKS_OK;
+}
+
+hgks_status hgks_residual(hgks_ctx* ctx, const double* Q, const double* gradQ, double* R, double* gradQ_new) {
+  TRY(require(ctx, Q == nullptr));
+  if (!R) return HGKS_EINVAL;
+  hipStream_t s = ctx->stream;
+  if (Q) {
+    HIPCHK(hipMemcpyAsync(ctx->Qc, Q, n5(ctx) * sizeof(double), hipMemcpyHostToDevice, s));
+    ctx->have_state = true;
+    ctx->res0 = -1.0;
+    if (ctx->o.scheme == HGKS_HWENO) {
+      TRY(upload_gradients(ctx, gradQ, s));
+      TRY(refresh_gradients(ctx, s));
+    }
+  } else if (gradQ && ctx->o.scheme == HGKS_HWENO) {
+    TRY(upload_gradients(ctx, gradQ, s));
+    TRY(refresh_gradients(ctx, s));
+  }
+  bool want = gradQ_new && ctx->o.scheme == HGKS_HWENO;
+  TRY(prepare_base(ctx, want, s));
+  HIPCHK(hipMemcpyAsync(R, ctx->b, n5(ctx) * sizeof(double), hipMemcpyDeviceToHost, s));
+  if (want) HIPCHK(hipMemcpyAsync(gradQ_new, ctx->Gnew, 15 * (size_t)ctx->H.N * sizeof(double), hipMemcpyDeviceToHost, s));
+  else if (gradQ_new) std::memset(gradQ_new, 0, 15 * (size_t)ctx->H.N * sizeof(double));
+  return check_state(ctx, s);
+}
+
+hgks_status hgks_time_step(hgks_ctx* ctx, const double* Q, double* dt) {
+  TRY(require(ctx, Q == nullptr));
+  if (!dt) return HGKS_EINVAL;
+  hipStream_t s = ctx->stream;
+  TRY(sync_kinds(ctx));
+  if (Q) {
+    HIPCHK(hipMemcpyAsync(ctx->Qc, Q, n5(ctx) * sizeof(double), hipMemcpyHostToDevice, s));
+    ctx->have_state = true;
+  }
+  expand_state(ctx, ctx->Qc, s);
+  launch_dt<double>(ctx->M, ctx->P, ctx->o.cfl, ctx->W64.Qx, ctx->W64.dt, s);
+  HIPCHK(hipMemcpyAsync(dt, ctx->W64.dt, (size_t)ctx->H.N * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  return HGKS_OK;
+}
+
+hgks_status hgks_jv(hgks_ctx* ctx, const double* v, double sigma, double* Av, double* sigma_used) {
+  TRY(require(ctx, true));
+  if (!v || !Av) return HGKS_EINVAL;
+  hipStream_t s = ctx->stream;
+  TRY(prepare_base(ctx, false, s));
+  HIPCHK(hipMemcpyAsync(ctx->yv, v, n5(ctx) * sizeof(double), hipMemcpyHostToDevice, s));
+  TRY(jv_device(ctx, ctx->yv, sigma, ctx->wv, s));
+  HIPCHK(hipMemcpyAsync(Av, ctx->wv, n5(ctx) * sizeof(double), hipMemcpyDeviceToHost, s));
+  double sg = 0.0;
+  HIPCHK(hipMemcpyAsync(&sg, ctx->sc + 2, sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  if (sigma_used) *sigma_used = sg;
+  return HGKS_OK;
+}
+
+hgks_status hgks_precond(hgks_ctx* ctx, const double* r, double* out) {
+  TRY(require(ctx, true));
+  if (!r || !out) return HGKS_EINVAL;
+  hipStream_t s = ctx->stream;
+  TRY(prepare_base(ctx, false, s));
+  HIPCHK(hipMemcpyAsync(ctx->rv, r, n5(ctx) * sizeof(double), hipMemcpyHostToDevice, s));
+  precond_device(ctx, ctx->rv, ctx->wv, s);
+  HIPCHK(hipMemcpyAsync(out, ctx->wv, n5(ctx) * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  return HGKS_OK;
+}
+
+hgks_status hgks_implicit_step(hgks_ctx* ctx, hgks_step_info* info) {
+  TRY(require(ctx, true));
+  auto t0 = std::chrono::steady_clock::now();
+  hipStream_t s = ctx->stream;
+  const size_t n = n5(ctx);
+  const int N = ctx->H.N;
+  const bool hw = ctx->o.scheme == HGKS_HWENO;
+  TRY(prepare_base(ctx, hw, s));
+  int64_t evals = ctx->o.precision == HGKS_FP32_INNER ? 2 : 1;
+  // residual norm of the base point (L1 density residual / total volume)
+  launch_abssum(ctx->b, (size_t)N, ctx->part, ctx->sc + 3, s);
+  double res_abs = 0.0;
+  HIPCHK(hipMemcpyAsync(&res_abs, ctx->sc + 3, sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemsetAsync(ctx->dQ, 0, n * sizeof(double), s));
+  const int m = ctx->o.krylov_dim;
+  double beta0 = -1.0, last = 0.0;
+  double* hc = ctx->sc + 8;  // device column of H (m+1 entries)
+  for (int rs = 0; rs < ctx->o.restarts; ++rs) {
+    if (rs == 0) {
+      HIPCHK(hipMemcpyAsync(ctx->rv, ctx->b, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    } else {
+      TRY(jv_device(ctx, ctx->dQ, ctx->o.fd_sigma, ctx->yv, s));
+      ++evals;
+      // r = b - A dQ
+      HIPCHK(hipMemcpyAsync(ctx->rv, ctx->b, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+      double one = 1.0;
+      HIPCHK(hipMemcpyAsync(ctx->sc + 4, &one, sizeof(double), hipMemcpyHostToDevice, s));
+      launch_axpy_dev(ctx->yv, ctx->rv, n, ctx->sc + 4, -1.0, s);
+    }
+    precond_device(ctx, ctx->rv, ctx->wv, s);
+    launch_dot(ctx->wv, ctx->wv, n, ctx->part, ctx->sc + 5, true, s);
+    double beta = 0.0;
+    HIPCHK(hipMemcpyAsync(&beta, ctx->sc + 5, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (beta0 < 0) beta0 = beta;
+    if (!(beta > 0.0)) break;
+    launch_scale_inv(ctx->wv, ctx->V, n, ctx->sc + 5, s);
+    std::vector<double> H((size_t)(m + 1) * m, 0.0), cs(m), sn(m), gv(m + 1, 0.0);
+    gv[0] = beta;
+    int jdone = 0;
+    for (int j = 0; j < m; ++j) {
+      double* vj = ctx->V + (size_t)j * n;
+      TRY(jv_device(ctx, vj, ctx->o.fd_sigma, ctx->yv, s));
+      ++evals;
+      precond_device(ctx, ctx->yv, ctx->wv, s);
+      // modified Gram-Schmidt
+      for (int i = 0; i <= j; ++i) {
+        const double* vi = ctx->V + (size_t)i * n;
+        launch_dot(ctx->wv, vi, n, ctx->part, hc + i, false, s);
+        launch_axpy_dev(vi, ctx->wv, n, hc + i, -1.0, s);
+      }
+      launch_dot(ctx->wv, ctx->wv, n, ctx->part, hc + j + 1, true, s);
+      std::vector<double> col(j + 2);
+      HIPCHK(hipMemcpyAsync(col.data(), hc, (j + 2) * sizeof(double), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+      for (int i = 0; i <= j + 1; ++i) H[(size_t)i * m + j] = col[i];
+      double hn = col[j + 1];
+      // Givens rotations (host, FP64)
+      for (int i = 0; i < j; ++i) {
+        double a = H[(size_t)i * m + j], c = H[(size_t)(i + 1) * m + j];
+        H[(size_t)i * m + j] = cs[i] * a + sn[i] * c;
+        H[(size_t)(i + 1) * m + j] = -sn[i] * a + cs[i] * c;
+      }
+      double a = H[(size_t)j * m + j], c = H[(size_t)(j + 1) * m + j];
+      double rr = std::hypot(a, c);
+      cs[j] = a / rr;
+      sn[j] = c / rr;
+      H[(size_t)j * m + j] = rr;
+      H[(size_t)(j + 1) * m + j] = 0.0;
+      gv[j + 1] = -sn[j] * gv[j];
+      gv[j] = cs[j] * gv[j];
+      jdone = j + 1;
+      if (hn <= 1e-14 * beta) break;  // happy breakdown
+      launch_scale_inv(ctx->wv, ctx->V + (size_t)(j + 1) * n, n, hc + j + 1, s);
+    }
+    std::vector<double> y(jdone, 0.0);
+    for (int i = jdone - 1; i >= 0; --i) {
+      double sacc = gv[i];
+      for (int k = i + 1; k < jdone; ++k) sacc -= H[(size_t)i * m + k] * y[k];
+      y[i] = sacc / H[(size_t)i * m + i];
+    }
+    HIPCHK(hipMemcpyAsync(ctx->sc + 48, y.data(), jdone * sizeof(double), hipMemcpyHostToDevice, s));
+    launch_combine(ctx->V, ctx->sc + 48, jdone, n, ctx->dQ, ctx->dQ, s);
+    last = std::fabs(gv[jdone]);
+    HIPCHK(hipStreamSynchronize(s));  // y is a host array
+  }
+  // Q^{n+1} = Q^n + dQ
+  double one = 1.0;
+  HIPCHK(hipMemcpyAsync(ctx->sc + 4, &one, sizeof(double), hipMemcpyHostToDevice, s));
+  launch_axpy_dev(ctx->dQ, ctx->Qc, n, ctx->sc + 4, 1.0, s);
+  if (hw) {
+    const int NX = N + ctx->H.Nb;
+    for (int k = 0; k < 15; ++k)
+      HIPCHK(hipMemcpyAsync(ctx->Gc + (size_t)k * NX, ctx->Gnew + (size_t)k * N, (size_t)N * sizeof(double),
+                            hipMemcpyDeviceToDevice, s));
+    TRY(refresh_gradients(ctx, s));
+  }
+  int flags[2] = {0, 0};
+  HIPCHK(hipMemcpyAsync(flags, ctx->flags, sizeof(flags), hipMemcpyDeviceToHost, s));
+  expand_state(ctx, ctx->Qc, s);
+  HIPCHK(hipStreamSynchronize(s));
+  double res = res_abs / ctx->H.total_volume;
+  if (ctx->res0 < 0) ctx->res0 = res;
+  if (info) {
+    info->res = res;
+    info->res_rel = ctx->res0 > 0 ? res / ctx->res0 : 0.0;
+    info->gmres_rel = beta0 > 0 ? last / beta0 : 0.0;
+    info->n_resid_evals = evals;
+    info->n_fallbacks = flags[0];
+    info->t_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  }
+  return check_state(ctx, s);
+}
+
+hgks_status hgks_solve_steady(hgks_ctx* ctx, double drop, int32_t max_steps, hgks_solve_info* info) {
+  TRY(require(ctx, true));
+  auto t0 = std::chrono::steady_clock::now();
+  hgks_solve_info si{};
+  ctx->res0 = -1.0;
+  hgks_status st = HGKS_OK;
+  for (int k = 0; k < max_steps; ++k) {
+    hgks_step_info s{};
+    st = hgks_implicit_step(ctx, &s);
+    si.steps = k + 1;
+    si.n_resid_evals += s.n_resid_evals;
+    if (k == 0) si.res0 = s.res;
+    si.res_final = s.res;
+    if (st != HGKS_OK) break;
+    if (s.res_rel <= drop) {
+      si.converged = 1;
+      break;
+    }
+  }
+  si.drop = si.res0 > 0 ? si.res_final / si.res0 : 0.0;
+  si.t_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  if (info) *info = si;
+  if (st != HGKS_OK) return st;
+  if (!si.converged) {
+    ctx->err = "requested residual drop not reached";
+    return HGKS_ENOCONV;
+  }
+  return HGKS_OK;
+}
+
+hgks_status hgks_residual_dev(hgks_ctx* ctx, const void* Q_dev, void* R_dev, void* stream) {
+  TRY(require(ctx, false));
+  if (!Q_dev || !R_dev) return HGKS_EINVAL;
+  hipStream_t s = stream ? (hipStream_t)stream : ctx->stream;
+  TRY(sync_kinds(ctx));
+  expand_state(ctx, (const double*)Q_dev, s);
+  launch_ghost<double>(ctx->M, ctx->P, ctx->W64.Qx, (double*)nullptr, s);
+  launch_dt<double>(ctx->M, ctx->P, ctx->o.cfl, ctx->W64.Qx, ctx->W64.dt, s);
+  residual_pipeline<double, double>(ctx, ctx->M, ctx->W64, ctx->W64.Qx, ctx->W64.dt, 0, (double*)R_dev,
+                                    (const double*)nullptr, (const double*)nullptr, (const double*)nullptr,
+                                    (double*)nullptr, s);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) {
+    ctx->err = hipGetErrorString(e);
+    return HGKS_EDEVICE;
+  }
+  return HGKS_OK;
+}
+
+hgks_status hgks_jv_dev(hgks_ctx* ctx, const void* v_dev, double sigma, void* Av_dev, void* stream) {
+  TRY(require(ctx, true));
+  if (!v_dev || !Av_dev) return HGKS_EINVAL;
+  hipStream_t s = stream ? (hipStream_t)stream : ctx->stream;
+  TRY(prepare_base(ctx, false, s));
+  TRY(jv_device(ctx, (const double*)v_dev, sigma, (double*)Av_dev, s));
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) {
+    ctx->err = hipGetErrorString(e);
+    return HGKS_EDEVICE;
+  }
+  return HGKS_OK;
+}
+
+int64_t hgks_n_cells(const hgks_ctx* ctx) { return ctx && ctx->mesh ? ctx->H.N : 0; }
+int64_t hgks_n_faces(const hgks_ctx* ctx) { return ctx && ctx->mesh ? ctx->H.F : 0; }
+
+hgks_status hgks_kernel_times(hgks_ctx* ctx, const char** names, double* ms, int32_t* n, int32_t cap) {
+  if (!ctx || !n) return HGKS_EINVAL;
+  if (!ctx->prof) {
+    ctx->evpool.resize(6 * EVSETS);
+    for (auto& e : ctx->evpool)
+      if (hipEventCreate(&e) != hipSuccess) return HGKS_EDEVICE;
+    ctx->prof = true;  // timing starts with the next evaluation
+  }
+  drain_events(ctx);
+  int c = std::min(cap, 6);
+  for (int k = 0; k < c; ++k) {
+    if (names) names[k] = k < 5 ? KNAMES[k] : "evaluations";
+    if (ms) ms[k] = k < 5 ? (ctx->kcount ? ctx->ksum[k] / ctx->kcount : 0.0) : (double)ctx->kcount;
+  }
+  *n = c;
+  for (int k = 0; k < 5; ++k) ctx->ksum[k] = 0.0;
+  ctx->kcount = 0;
+  return HGKS_OK;
+}
+
+const char* hgks_last_error(const hgks_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+void hgks_destroy(hgks_ctx* ctx) {
+  if (!ctx) return;
+  if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+  ctx->A.free_all();
+  for (auto& e : ctx->evpool) (void)hipEventDestroy(e);
+  if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
+  delete ctx;
+}
+
+}  // extern "C"

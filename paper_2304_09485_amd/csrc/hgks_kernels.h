@@ -1,0 +1,40 @@
+// Host-side launchers of the HGKS kernels (defined in hgks_kernels.hip).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "hgks_device.h"
+
+namespace hgks {
+
+template <typename T> void launch_ghost(const DevMesh<T>&, const Params&, T* Qx, T* Gx, hipStream_t);
+template <typename T>
+void launch_recon(const DevMesh<T>&, const Params&, const T* Qx, const T* Gx, T* coef, hipStream_t);
+template <typename T>
+void launch_side(const DevMesh<T>&, const Params&, const T* Qx, const T* coef, T* sv, int* nfall, hipStream_t);
+template <typename T>
+void launch_flux(const DevMesh<T>&, const Params&, const T* sv, const T* dt, T* ff, T* fq, bool qg, hipStream_t);
+template <typename T, typename TO>
+void launch_gather(const DevMesh<T>&, int mode, const T* ff, const T* fq, TO* out, const TO* v, const TO* b,
+                   const T* dt, const double* sigma, TO* gout, hipStream_t);
+template <typename T> void launch_dt(const DevMesh<T>&, const Params&, double cfl, const T* Qx, T* dt, hipStream_t);
+template <typename T>
+void launch_lambda_diag(const DevMesh<T>&, const Params&, const T* Qx, const T* dt, T* lam, T* D, hipStream_t);
+template <typename T>
+void launch_jacobi(const DevMesh<T>&, const Params&, const T* Qx, const T* lam, const T* D, const double* r,
+                   const double* xo, double* xn, hipStream_t);
+template <typename T>
+void launch_perturb(const double* Q, const double* v, const double* sigma, int N, int NX, T* Qp, hipStream_t);
+template <typename T> void launch_check(const T* Qx, int N, int NX, double gamma, int* bad, hipStream_t);
+
+void launch_dot(const double* x, const double* y, size_t n, double* part, double* out, bool sqrt_out, hipStream_t);
+void launch_abssum(const double* x, size_t n, double* part, double* out, hipStream_t);
+void launch_axpy_dev(const double* x, double* y, size_t n, const double* a, double sgn, hipStream_t);
+void launch_scale_inv(const double* x, double* y, size_t n, const double* a, hipStream_t);
+void launch_combine(const double* V, const double* c, int nv, size_t n, const double* x, double* y, hipStream_t);
+void launch_convert(const double* src, float* dst, size_t n, hipStream_t);
+void launch_sigma(const double* vv, const double* qq, double n, double eps, double fixed, double* sigma,
+                  hipStream_t);
+
+constexpr int REDUCE_PARTS = 1024;
+
+}  // namespace hgks

@@ -1,0 +1,895 @@
+// HIP kernels of the HGKS residual, FD Jacobian-vector product, Jacobi
+// preconditioner and GMRES vector operations (gfx950, wave64).
+//
+// Residual pipeline (paper Sec. 2-3, Sec. 4.1 time-averaged flux):
+//   ghost    one thread per boundary face: ghost-cell state (and gradient)
+//   recon    one thread per cell: stencil gather and the stored least-squares
+//            operator -> coefficients of P0 and P_m in conservative variables
+//   side     one thread per face side: characteristic projection of the
+//            coefficients, smoothness indicators, nonlinear weights, values and
+//            (n,t1,t2) derivatives at the 3 Gauss points, back projection
+//   flux     one thread per face: gas-kinetic flux at the 3 Gauss points,
+//            quadrature and rotation to the global frame
+//   gather   one thread per cell: sum of its 4 signed face fluxes (atomic-free,
+//            deterministic), with the Jv / gradient-update epilogues fused
+#include "hgks_kernels.h"
+
+#include "gks_flux.h"
+#include "hgks_device.h"
+
+namespace hgks {
+
+// ---------------------------------------------------------------------------
+// boundary states
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ void cons_of(T rho, T u0, T u1, T u2, T p, T g, T q[5]) {
+  q[0] = rho;
+  q[1] = rho * u0;
+  q[2] = rho * u1;
+  q[3] = rho * u2;
+  q[4] = p / (g - T(1)) + T(0.5) * rho * (u0 * u0 + u1 * u1 + u2 * u2);
+}
+
+// Riemann-invariant far field along unit normal nn (any frame; uinf in the
+// same frame): supersonic inflow -> free stream, supersonic outflow ->
+// interior, otherwise R+ from inside, R- from the free stream, entropy and
+// tangential velocity from the upwind side.
+template <typename T>
+__device__ void farfield_state(const T qi[5], const T nn[3], const T ui[3], T rinf, T pinf, T g,
+                               T out[5]) {
+  T rho = qi[0];
+  T U[3] = {qi[1] / rho, qi[2] / rho, qi[3] / rho};
+  T p = (g - T(1)) * (qi[4] - T(0.5) * rho * (U[0] * U[0] + U[1] * U[1] + U[2] * U[2]));
+  T ci = sqrt(g * p / rho);
+  T uni = U[0] * nn[0] + U[1] * nn[1] + U[2] * nn[2];
+  if (uni <= -ci) {
+    cons_of(rinf, ui[0], ui[1], ui[2], pinf, g, out);
+    return;
+  }
+  if (uni >= ci) {
+    for (int k = 0; k < 5; ++k) out[k] = qi[k];
+    return;
+  }
+  T cinf = sqrt(g * pinf / rinf);
+  T uninf = ui[0] * nn[0] + ui[1] * nn[1] + ui[2] * nn[2];
+  T Rp = uni + T(2) * ci / (g - T(1));
+  T Rm = uninf - T(2) * cinf / (g - T(1));
+  T unb = T(0.5) * (Rp + Rm);
+  T cb = T(0.25) * (g - T(1)) * (Rp - Rm);
+  T ent, ut[3];
+  if (unb < T(0)) {
+    ent = pinf / pow(rinf, g);
+    for (int d = 0; d < 3; ++d) ut[d] = ui[d] - uninf * nn[d];
+  } else {
+    ent = p / pow(rho, g);
+    for (int d = 0; d < 3; ++d) ut[d] = U[d] - uni * nn[d];
+  }
+  T rb = pow(cb * cb / (g * ent), T(1) / (g - T(1)));
+  T pb = rb * cb * cb / g;
+  cons_of(rb, ut[0] + unb * nn[0], ut[1] + unb * nn[1], ut[2] + unb * nn[2], pb, g, out);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_ghost(DevMesh<T> M, Params P, T* __restrict__ Qx,
+                                               T* __restrict__ Gx) {
+  int gi = blockIdx.x * blockDim.x + threadIdx.x;
+  if (gi >= M.Nb) return;
+  const int NX = M.NX;
+  int o = M.gowner[gi], f = M.gface[gi], kind = M.fkind[f];
+  T n[3] = {M.fn[f], M.fn[M.F + f], M.fn[2 * M.F + f]};
+  T q[5], out[5];
+  for (int v = 0; v < 5; ++v) q[v] = Qx[(size_t)v * NX + o];
+  const T g = T(P.gamma);
+  for (int v = 0; v < 5; ++v) out[v] = q[v];
+  if (kind == 1) {  // slip wall: reflect the momentum about the face plane
+    T mn = q[1] * n[0] + q[2] * n[1] + q[3] * n[2];
+    for (int d = 0; d < 3; ++d) out[1 + d] = q[1 + d] - T(2) * mn * n[d];
+  } else if (kind == 2) {  // no-slip wall: reverse the momentum
+    for (int d = 0; d < 3; ++d) out[1 + d] = -q[1 + d];
+  } else if (kind == 0) {
+    T ui[3] = {T(P.uinf0), T(P.uinf1), T(P.uinf2)};
+    farfield_state(q, n, ui, T(P.rhoinf), T(P.pinf), g, out);
+  } else if (kind == 3) {
+    cons_of(T(P.rhoinf), T(P.uinf0), T(P.uinf1), T(P.uinf2), T(P.pinf), g, out);
+  }
+  for (int v = 0; v < 5; ++v) Qx[(size_t)v * NX + M.N + gi] = out[v];
+  if (Gx) {
+    T G[15], Gg[15];
+    for (int k = 0; k < 15; ++k) G[k] = Gx[(size_t)k * NX + o];
+    if (kind == 0 || kind == 3) {
+      for (int k = 0; k < 15; ++k) Gg[k] = T(0);
+    } else if (kind == 4) {
+      for (int k = 0; k < 15; ++k) Gg[k] = G[k];
+    } else {
+      // mirror x -> Rm x, Rm = I - 2 n n^T: gradient of q(Rm x) is G Rm
+      T Rm[3][3];
+      for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) Rm[a][b] = (a == b ? T(1) : T(0)) - T(2) * n[a] * n[b];
+      T GR[5][3];
+      for (int v = 0; v < 5; ++v)
+        for (int b = 0; b < 3; ++b)
+          GR[v][b] = G[v * 3 + 0] * Rm[0][b] + G[v * 3 + 1] * Rm[1][b] + G[v * 3 + 2] * Rm[2][b];
+      for (int b = 0; b < 3; ++b) {
+        Gg[b] = GR[0][b];
+        Gg[12 + b] = GR[4][b];
+      }
+      for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b)
+          Gg[(1 + a) * 3 + b] = kind == 1 ? Rm[a][0] * GR[1][b] + Rm[a][1] * GR[2][b] + Rm[a][2] * GR[3][b]
+                                          : -GR[1 + a][b];
+    }
+    for (int k = 0; k < 15; ++k) Gx[(size_t)k * NX + M.N + gi] = Gg[k];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// reconstruction: coefficients in conservative variables (linear in the data)
+// coef layout [21*5][N], row k*5+v; k < 9: P0 (xi basis), k = 9+3s+t: P_m
+// gradient in the xi basis (xi = (x - c)/h)
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(256) k_recon_weno(DevMesh<T> M, const T* __restrict__ Qx,
+                                                    T* __restrict__ coef) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= M.N) return;
+  const int N = M.N, NX = M.NX;
+  int st[16], ss[24];
+#pragma unroll
+  for (int j = 0; j < 16; ++j) st[j] = M.stn[j * N + i];
+#pragma unroll
+  for (int r = 0; r < 24; ++r) ss[r] = M.sstn[r * N + i];
+  for (int v = 0; v < 5; ++v) {
+    const T* Qv = Qx + (size_t)v * NX;
+    T q0 = Qv[i];
+    T dq[16];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) dq[j] = Qv[st[j]] - q0;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+      T acc = T(0);
+#pragma unroll
+      for (int j = 0; j < 16; ++j) acc += M.opA[(size_t)(k * 16 + j) * N + i] * dq[j];
+      coef[(size_t)(k * 5 + v) * N + i] = acc;
+    }
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      T ds[6];
+#pragma unroll
+      for (int r = 0; r < 6; ++r) ds[r] = Qv[ss[s * 6 + r]] - q0;
+#pragma unroll
+      for (int t = 0; t < 3; ++t) {
+        T acc = T(0);
+#pragma unroll
+        for (int r = 0; r < 6; ++r) acc += M.opB[(size_t)((s * 3 + t) * 6 + r) * N + i] * ds[r];
+        coef[(size_t)((9 + s * 3 + t) * 5 + v) * N + i] = acc;
+      }
+    }
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_recon_hweno(DevMesh<T> M, const T* __restrict__ Qx,
+                                                     const T* __restrict__ Gx, T* __restrict__ coef) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= M.N) return;
+  const int N = M.N, NX = M.NX;
+  int nb[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) nb[k] = M.nb4[k * N + i];
+  T h = M.h[i];
+  for (int v = 0; v < 5; ++v) {
+    T q0 = Qx[(size_t)v * NX + i];
+    T x[19];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) x[k] = Qx[(size_t)v * NX + nb[k]] - q0;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      x[4 + d] = Gx[(size_t)(v * 3 + d) * NX + i];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) x[7 + 3 * k + d] = Gx[(size_t)(v * 3 + d) * NX + nb[k]];
+    }
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+      T acc = T(0);
+#pragma unroll
+      for (int j = 0; j < 19; ++j) acc += M.opH[(size_t)(k * 19 + j) * N + i] * x[j];
+      coef[(size_t)(k * 5 + v) * N + i] = acc;
+    }
+    // P_m on {i, i_m}: the constrained minimiser has a closed form
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      T wi = M.hsub[(size_t)(s * 6 + 0) * N + i], wm = M.hsub[(size_t)(s * 6 + 1) * N + i];
+      T d0 = M.hsub[(size_t)(s * 6 + 2) * N + i], d1 = M.hsub[(size_t)(s * 6 + 3) * N + i];
+      T d2 = M.hsub[(size_t)(s * 6 + 4) * N + i], id2 = M.hsub[(size_t)(s * 6 + 5) * N + i];
+      T g0 = wi * x[4] + wm * x[7 + 3 * s];
+      T g1 = wi * x[5] + wm * x[8 + 3 * s];
+      T g2 = wi * x[6] + wm * x[9 + 3 * s];
+      T lam = (x[s] - (d0 * g0 + d1 * g1 + d2 * g2)) * id2;
+      coef[(size_t)((9 + s * 3 + 0) * 5 + v) * N + i] = h * (g0 + lam * d0);
+      coef[(size_t)((9 + s * 3 + 1) * 5 + v) * N + i] = h * (g1 + lam * d1);
+      coef[(size_t)((9 + s * 3 + 2) * 5 + v) * N + i] = h * (g2 + lam * d2);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// face side: characteristic WENO (Sec. 3.4 Eq. (weno), Sec. 5 projection)
+// sv layout [60][2F], row (g*4+d)*5+v, column side*F+f
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ bool phys_ok(const T w[5], T g) {
+  if (!(w[0] > T(0))) return false;
+  T p = (g - T(1)) * (w[4] - T(0.5) * (w[1] * w[1] + w[2] * w[2] + w[3] * w[3]) / w[0]);
+  return p > T(0) && isfinite(p);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(128) k_side(DevMesh<T> M, Params P, const T* __restrict__ Qx,
+                                              const T* __restrict__ coef, T* __restrict__ sv,
+                                              int* __restrict__ nfall) {
+  int sidx = blockIdx.x * blockDim.x + threadIdx.x;
+  const int F = M.F, N = M.N, NX = M.NX;
+  if (sidx >= 2 * F) return;
+  int side = sidx >= F;
+  int f = side ? sidx - F : sidx;
+  int L = M.fL[f], R = M.fR[f];
+  if (side && R >= N) return;
+  int i = side ? R : L, j = side ? L : R;
+  const T g = T(P.gamma);
+  T e[3][3];
+  e[0][0] = M.fn[f];
+  e[0][1] = M.fn[F + f];
+  e[0][2] = M.fn[2 * F + f];
+  face_frame(e[0][0], e[0][1], e[0][2], e[1], e[2]);
+  T qi[5], qj[5], qil[5], qs[5];
+  for (int v = 0; v < 5; ++v) {
+    qi[v] = Qx[(size_t)v * NX + i];
+    qj[v] = Qx[(size_t)v * NX + j];
+  }
+  qil[0] = qi[0];
+  qil[4] = qi[4];
+  for (int a = 0; a < 3; ++a) qil[1 + a] = e[a][0] * qi[1] + e[a][1] * qi[2] + e[a][2] * qi[3];
+  qs[0] = T(0.5) * (qi[0] + qj[0]);
+  qs[4] = T(0.5) * (qi[4] + qj[4]);
+  for (int a = 0; a < 3; ++a)
+    qs[1 + a] = T(0.5) * (qil[1 + a] + (e[a][0] * qj[1] + e[a][1] * qj[2] + e[a][2] * qj[3]));
+  // right/left eigenvectors of the x-split Euler Jacobian at Q* (local frame),
+  // columns (u-c, u, u, u, u+c)
+  T rho = qs[0], u = qs[1] / rho, vv = qs[2] / rho, w = qs[3] / rho;
+  T q2 = u * u + vv * vv + w * w;
+  T p = (g - T(1)) * (qs[4] - T(0.5) * rho * q2);
+  T c = sqrt(g * p / rho);
+  T H = (qs[4] + p) / rho;
+  T Rv[5][5] = {{T(1), T(1), T(0), T(0), T(1)},
+                {u - c, u, T(0), T(0), u + c},
+                {vv, vv, T(1), T(0), vv},
+                {w, w, T(0), T(1), w},
+                {H - u * c, T(0.5) * q2, vv, w, H + u * c}};
+  T b1 = (g - T(1)) / (c * c), b2 = T(0.5) * b1 * q2, ic = T(1) / c;
+  T Lv[5][5] = {{T(0.5) * (b2 + u * ic), T(0.5) * (-b1 * u - ic), T(-0.5) * b1 * vv, T(-0.5) * b1 * w, T(0.5) * b1},
+                {T(1) - b2, b1 * u, b1 * vv, b1 * w, -b1},
+                {-vv, T(0), T(1), T(0), T(0)},
+                {-w, T(0), T(0), T(1), T(0)},
+                {T(0.5) * (b2 - u * ic), T(0.5) * (-b1 * u + ic), T(-0.5) * b1 * vv, T(-0.5) * b1 * w, T(0.5) * b1}};
+  const T hh = M.h[i];
+  const T ih = T(1) / hh;
+  T m2[6];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) m2[k] = M.m2s[k * N + i];
+  const T* xis = side ? M.fxiR : M.fxiL;
+  T xi[3][3];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) xi[k / 3][k % 3] = xis[(size_t)k * F + f];
+  unsigned mask = P.scheme == 1 ? 15u : (unsigned)M.smask[i];
+  int nsub = __popc(mask);
+  const T gl = T(P.gamma_lin);
+  const T g0 = T(1) - gl * T(nsub);
+  T out[3][4][5];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int d = 0; d < 4; ++d)
+#pragma unroll
+      for (int v = 0; v < 5; ++v) out[a][d][v] = T(0);
+  for (int cc = 0; cc < 5; ++cc) {
+    // row cc of T = L* . Rot
+    T tc[5];
+    tc[0] = Lv[cc][0];
+    tc[4] = Lv[cc][4];
+    for (int d = 0; d < 3; ++d) tc[1 + d] = Lv[cc][1] * e[0][d] + Lv[cc][2] * e[1][d] + Lv[cc][3] * e[2][d];
+    T q0 = tc[0] * qi[0] + tc[1] * qi[1] + tc[2] * qi[2] + tc[3] * qi[3] + tc[4] * qi[4];
+    T a[9], b[4][3];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+      const T* cp = coef + (size_t)(k * 5) * N + i;
+      a[k] = tc[0] * cp[0] + tc[1] * cp[N] + tc[2] * cp[2 * N] + tc[3] * cp[3 * N] + tc[4] * cp[4 * N];
+    }
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+      for (int t = 0; t < 3; ++t) {
+        const T* cp = coef + (size_t)((9 + s * 3 + t) * 5) * N + i;
+        b[s][t] = tc[0] * cp[0] + tc[1] * cp[N] + tc[2] * cp[2 * N] + tc[3] * cp[3 * N] + tc[4] * cp[4 * N];
+      }
+    // weights
+    T w0, ws[4];
+    if (P.weights == 1) {
+      w0 = g0;
+#pragma unroll
+      for (int s = 0; s < 4; ++s) ws[s] = (mask >> s) & 1u ? gl : T(0);
+    } else {
+      T s0[3] = {T(2) * a[3], a[6], a[7]}, s1[3] = {a[6], T(2) * a[4], a[8]}, s2[3] = {a[7], a[8], T(2) * a[5]};
+      auto quad = [&](const T* sv3) {
+        return m2[0] * sv3[0] * sv3[0] + m2[1] * sv3[1] * sv3[1] + m2[2] * sv3[2] * sv3[2] +
+               T(2) * (m2[3] * sv3[0] * sv3[1] + m2[4] * sv3[0] * sv3[2] + m2[5] * sv3[1] * sv3[2]);
+      };
+      T beta0 = a[0] * a[0] + quad(s0) + a[1] * a[1] + quad(s1) + a[2] * a[2] + quad(s2) +
+                T(4) * (a[3] * a[3] + a[4] * a[4] + a[5] * a[5]) + a[6] * a[6] + a[7] * a[7] + a[8] * a[8];
+      T bm[4], tz = T(0);
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        bm[s] = b[s][0] * b[s][0] + b[s][1] * b[s][1] + b[s][2] * b[s][2];
+        if ((mask >> s) & 1u) tz += fabs(beta0 - bm[s]);
+      }
+      if (nsub > 0) tz /= T(nsub);
+      const T eps = T(P.weno_eps);
+      T wt0 = g0 * (T(1) + tz / (beta0 + eps));
+      T sum = wt0;
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        ws[s] = (mask >> s) & 1u ? gl * (T(1) + tz / (bm[s] + eps)) : T(0);
+        sum += ws[s];
+      }
+      T isum = T(1) / sum;
+      w0 = wt0 * isum;
+#pragma unroll
+      for (int s = 0; s < 4; ++s) ws[s] *= isum;
+    }
+    // combined polynomial: q0 + Lc . xi + Qc . (xi xi - m2)
+    T r0 = w0 / g0;
+    T Lc[3], Qc[6];
+#pragma unroll
+    for (int t = 0; t < 3; ++t) Lc[t] = r0 * a[t];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      if (!((mask >> s) & 1u)) continue;
+      T cs = ws[s] - w0 * gl / g0;
+#pragma unroll
+      for (int t = 0; t < 3; ++t) Lc[t] += cs * b[s][t];
+    }
+#pragma unroll
+    for (int t = 0; t < 6; ++t) Qc[t] = r0 * a[3 + t];
+#pragma unroll
+    for (int gp = 0; gp < 3; ++gp) {
+      T x0 = xi[gp][0], x1 = xi[gp][1], x2 = xi[gp][2];
+      T val = q0 + Lc[0] * x0 + Lc[1] * x1 + Lc[2] * x2 + Qc[0] * (x0 * x0 - m2[0]) +
+              Qc[1] * (x1 * x1 - m2[1]) + Qc[2] * (x2 * x2 - m2[2]) + Qc[3] * (x0 * x1 - m2[3]) +
+              Qc[4] * (x0 * x2 - m2[4]) + Qc[5] * (x1 * x2 - m2[5]);
+      T gx = Lc[0] + T(2) * Qc[0] * x0 + Qc[3] * x1 + Qc[4] * x2;
+      T gy = Lc[1] + T(2) * Qc[1] * x1 + Qc[3] * x0 + Qc[5] * x2;
+      T gz = Lc[2] + T(2) * Qc[2] * x2 + Qc[4] * x0 + Qc[5] * x1;
+      T dd[4];
+      dd[0] = val;
+#pragma unroll
+      for (int a2 = 0; a2 < 3; ++a2) dd[1 + a2] = (gx * e[a2][0] + gy * e[a2][1] + gz * e[a2][2]) * ih;
+#pragma unroll
+      for (int d = 0; d < 4; ++d)
+#pragma unroll
+        for (int v = 0; v < 5; ++v) out[gp][d][v] += Rv[v][cc] * dd[d];
+    }
+  }
+  bool ok = phys_ok(out[0][0], g) && phys_ok(out[1][0], g) && phys_ok(out[2][0], g);
+  if (!ok) {
+    // positivity fallback: first order on this side
+    atomicAdd(nfall, 1);
+    for (int gp = 0; gp < 3; ++gp) {
+      for (int v = 0; v < 5; ++v) out[gp][0][v] = qil[v];
+      for (int d = 1; d < 4; ++d)
+        for (int v = 0; v < 5; ++v) out[gp][d][v] = T(0);
+    }
+  }
+  const size_t ld = 2 * (size_t)F;
+#pragma unroll
+  for (int gp = 0; gp < 3; ++gp)
+#pragma unroll
+    for (int d = 0; d < 4; ++d)
+#pragma unroll
+      for (int v = 0; v < 5; ++v) sv[(size_t)((gp * 4 + d) * 5 + v) * ld + sidx] = out[gp][d][v];
+}
+
+// ---------------------------------------------------------------------------
+// flux at the 3 Gauss points of every face (Sec. 2 Eq. (flux), Sec. 4.1)
+// ff layout [5][F] (global frame, times area, oriented L -> R); fq likewise
+// for the face sum of Gauss-point values (HWENO gradient update)
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ void boundary_right(int kind, const T Wl[5], const T dWl[3][5], const T ul[3], T rinf, T pinf,
+                               T g, T Wr[5], T dWr[3][5]) {
+  if (kind == 1 || kind == 2) {
+    T m[5] = {T(1), T(-1), T(1), T(1), T(1)};
+    if (kind == 2) m[2] = m[3] = T(-1);
+    for (int k = 0; k < 5; ++k) {
+      Wr[k] = m[k] * Wl[k];
+      dWr[0][k] = -m[k] * dWl[0][k];
+      dWr[1][k] = m[k] * dWl[1][k];
+      dWr[2][k] = m[k] * dWl[2][k];
+    }
+    return;
+  }
+  if (kind == 4) {
+    for (int k = 0; k < 5; ++k) {
+      Wr[k] = Wl[k];
+      for (int d = 0; d < 3; ++d) dWr[d][k] = dWl[d][k];
+    }
+    return;
+  }
+  if (kind == 0) {
+    T nloc[3] = {T(1), T(0), T(0)};
+    farfield_state(Wl, nloc, ul, rinf, pinf, g, Wr);
+  } else {
+    cons_of(rinf, ul[0], ul[1], ul[2], pinf, g, Wr);
+  }
+  for (int d = 0; d < 3; ++d)
+    for (int k = 0; k < 5; ++k) dWr[d][k] = T(0);
+}
+
+template <typename T, bool QG>
+__global__ void __launch_bounds__(64) k_flux(DevMesh<T> M, Params P, const T* __restrict__ sv,
+                                             const T* __restrict__ dt, T* __restrict__ ff,
+                                             T* __restrict__ fq) {
+  int f = blockIdx.x * blockDim.x + threadIdx.x;
+  const int F = M.F, N = M.N;
+  if (f >= F) return;
+  int L = M.fL[f], R = M.fR[f];
+  bool bnd = R >= N;
+  T dtf = bnd ? dt[L] : fmin(dt[L], dt[R]);
+  T n[3] = {M.fn[f], M.fn[F + f], M.fn[2 * F + f]}, t1[3], t2[3];
+  face_frame(n[0], n[1], n[2], t1, t2);
+  int kind = M.fkind[f];
+  FluxParams<T> fp;
+  fp.gamma = T(P.gamma);
+  fp.K = T(P.K);
+  fp.tau_eps = T(P.tau_eps);
+  fp.tau_C = T(P.tau_C);
+  fp.mu = T(P.mu);
+  fp.prandtl = T(P.prandtl);
+  fp.physics = P.physics;
+  T ul[3];
+  {
+    T ui[3] = {T(P.uinf0), T(P.uinf1), T(P.uinf2)};
+    ul[0] = ui[0] * n[0] + ui[1] * n[1] + ui[2] * n[2];
+    ul[1] = ui[0] * t1[0] + ui[1] * t1[1] + ui[2] * t1[2];
+    ul[2] = ui[0] * t2[0] + ui[1] * t2[1] + ui[2] * t2[2];
+  }
+  const size_t ld = 2 * (size_t)F;
+  T Fs[5] = {0, 0, 0, 0, 0}, Qs[5] = {0, 0, 0, 0, 0};
+  for (int gp = 0; gp < 3; ++gp) {
+    T Wl[5], dWl[3][5], Wr[5], dWr[3][5];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+      Wl[v] = sv[(size_t)((gp * 4 + 0) * 5 + v) * ld + f];
+#pragma unroll
+      for (int d = 0; d < 3; ++d) dWl[d][v] = sv[(size_t)((gp * 4 + 1 + d) * 5 + v) * ld + f];
+    }
+    if (bnd) {
+      boundary_right(kind, Wl, dWl, ul, T(P.rhoinf), T(P.pinf), fp.gamma, Wr, dWr);
+    } else {
+#pragma unroll
+      for (int v = 0; v < 5; ++v) {
+        Wr[v] = sv[(size_t)((gp * 4 + 0) * 5 + v) * ld + F + f];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) dWr[d][v] = sv[(size_t)((gp * 4 + 1 + d) * 5 + v) * ld + F + f];
+      }
+    }
+    T Fg[5], Qg[5];
+    gks_flux<T, QG>(Wl, dWl, Wr, dWr, dtf, fp, Fg, Qg);
+#pragma unroll
+    for (int v = 0; v < 5; ++v) Fs[v] += Fg[v] / T(3);
+    if (QG) {
+#pragma unroll
+      for (int v = 0; v < 5; ++v) Qs[v] += Qg[v] / T(3);
+    }
+  }
+  T S = M.fS[f];
+  ff[f] = S * Fs[0];
+  ff[4 * (size_t)F + f] = S * Fs[4];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) ff[(size_t)(1 + d) * F + f] = S * (Fs[1] * n[d] + Fs[2] * t1[d] + Fs[3] * t2[d]);
+  if (QG) {
+    fq[f] = S * Qs[0];
+    fq[4 * (size_t)F + f] = S * Qs[4];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) fq[(size_t)(1 + d) * F + f] = S * (Qs[1] * n[d] + Qs[2] * t1[d] + Qs[3] * t2[d]);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// gather: L(Q_i) = - sum of outward face fluxes (Eq. (finite)); epilogues
+//   MODE 0: R = L(Q)
+//   MODE 1: Av = (|Omega|/dt) v - (L(Q + sigma v) - b) / sigma     (Eq. (frechet))
+//   MODE 2: R = L(Q) and the gradient update of Eq. (derivative)
+// ---------------------------------------------------------------------------
+template <typename T, typename TO, int MODE>
+__global__ void __launch_bounds__(256) k_gather(DevMesh<T> M, const T* __restrict__ ff,
+                                                const T* __restrict__ fq, TO* __restrict__ out,
+                                                const TO* __restrict__ vin, const TO* __restrict__ bin,
+                                                const T* __restrict__ dt, const double* __restrict__ sigma,
+                                                TO* __restrict__ gout) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int N = M.N, F = M.F;
+  if (i >= N) return;
+  T r[5] = {0, 0, 0, 0, 0};
+  T gq[15];
+  if (MODE == 2)
+    for (int k = 0; k < 15; ++k) gq[k] = T(0);
+#pragma unroll
+  for (int p = 0; p < 4; ++p) {
+    int cf = M.cface[p * N + i];
+    int f = (cf > 0 ? cf : -cf) - 1;
+    T s = cf > 0 ? T(1) : T(-1);
+#pragma unroll
+    for (int v = 0; v < 5; ++v) r[v] -= s * ff[(size_t)v * F + f];
+    if (MODE == 2) {
+      T n[3] = {M.fn[f], M.fn[F + f], M.fn[2 * F + f]};
+      T iv = T(1) / M.vol[i];
+#pragma unroll
+      for (int v = 0; v < 5; ++v) {
+        T qv = s * fq[(size_t)v * F + f];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) gq[v * 3 + d] += qv * n[d] * iv;
+      }
+    }
+  }
+  if (MODE == 1) {
+    double sg = sigma[0];
+    TO a = TO(M.vol[i] / dt[i]);
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+      size_t k = (size_t)v * N + i;
+      out[k] = sg > 0.0 ? TO(a * vin[k] - (TO(r[v]) - bin[k]) / TO(sg)) : TO(0);
+    }
+  } else {
+#pragma unroll
+    for (int v = 0; v < 5; ++v) out[(size_t)v * N + i] = TO(r[v]);
+  }
+  if (MODE == 2)
+    for (int k = 0; k < 15; ++k) gout[(size_t)k * N + i] = TO(gq[k]);
+}
+
+// ---------------------------------------------------------------------------
+// time step, approximate matrix and Jacobi sweeps (Sec. 4.1-4.2)
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(256) k_dt(DevMesh<T> M, Params P, double cfl, const T* __restrict__ Qx,
+                                            T* __restrict__ dt) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= M.N) return;
+  const int NX = M.NX;
+  T rho = Qx[i], U = Qx[NX + i] / rho, V = Qx[2 * (size_t)NX + i] / rho, W = Qx[3 * (size_t)NX + i] / rho;
+  T g = T(P.gamma);
+  T p = (g - T(1)) * (Qx[4 * (size_t)NX + i] - T(0.5) * rho * (U * U + V * V + W * W));
+  T c = sqrt(g * p / rho);
+  T nu = P.physics ? T(P.mu) / rho : T(0);
+  T hd = M.hdt[i];
+  dt[i] = T(cfl) * hd / (sqrt(U * U + V * V + W * W) + c + T(2) * nu / hd);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_lambda(DevMesh<T> M, Params P, const T* __restrict__ Qx,
+                                                T* __restrict__ lam) {
+  int f = blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= M.F) return;
+  const int NX = M.NX, F = M.F;
+  int a = M.fL[f], b = M.fR[f];
+  T g = T(P.gamma);
+  T pr[2][5];
+  int cells[2] = {a, b};
+  for (int s = 0; s < 2; ++s) {
+    int c = cells[s];
+    T rho = Qx[c];
+    T U = Qx[NX + c] / rho, V = Qx[2 * (size_t)NX + c] / rho, W = Qx[3 * (size_t)NX + c] / rho;
+    pr[s][0] = rho;
+    pr[s][1] = U;
+    pr[s][2] = V;
+    pr[s][3] = W;
+    pr[s][4] = (g - T(1)) * (Qx[4 * (size_t)NX + c] - T(0.5) * rho * (U * U + V * V + W * W));
+  }
+  T rho = T(0.5) * (pr[0][0] + pr[1][0]), p = T(0.5) * (pr[0][4] + pr[1][4]);
+  T un = T(0.5) * (pr[0][1] + pr[1][1]) * M.fn[f] + T(0.5) * (pr[0][2] + pr[1][2]) * M.fn[F + f] +
+         T(0.5) * (pr[0][3] + pr[1][3]) * M.fn[2 * F + f];
+  lam[f] = fabs(un) + sqrt(g * p / rho);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_diag(DevMesh<T> M, const T* __restrict__ lam, const T* __restrict__ dt,
+                                              T* __restrict__ D) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= M.N) return;
+  T s = M.vol[i] / dt[i];
+#pragma unroll
+  for (int p = 0; p < 4; ++p) {
+    int cf = M.cface[p * M.N + i];
+    int f = (cf > 0 ? cf : -cf) - 1;
+    s += T(0.5) * lam[f] * M.fS[f];
+  }
+  D[i] = s;
+}
+
+// Euler flux Jacobian along n applied to x
+template <typename T>
+__device__ __forceinline__ void euler_jn(T g, const T q[5], const T n[3], const T x[5], T out[5]) {
+  T rho = q[0];
+  T U[3] = {q[1] / rho, q[2] / rho, q[3] / rho};
+  T uu = U[0] * U[0] + U[1] * U[1] + U[2] * U[2];
+  T p = (g - T(1)) * (q[4] - T(0.5) * rho * uu);
+  T un = U[0] * n[0] + U[1] * n[1] + U[2] * n[2];
+  T dmn = x[1] * n[0] + x[2] * n[1] + x[3] * n[2];
+  T dun = (dmn - un * x[0]) / rho;
+  T dp = (g - T(1)) * (x[4] - (U[0] * x[1] + U[1] * x[2] + U[2] * x[3]) + T(0.5) * uu * x[0]);
+  out[0] = dmn;
+  for (int d = 0; d < 3; ++d) out[1 + d] = x[1 + d] * un + q[1 + d] * dun + dp * n[d];
+  out[4] = (x[4] + dp) * un + (q[4] + p) * dun;
+}
+
+// x_new = D^{-1} (r - (L+U) x_old); x_old == nullptr gives D^{-1} r
+template <typename T>
+__global__ void __launch_bounds__(256) k_jacobi(DevMesh<T> M, Params P, const T* __restrict__ Qx,
+                                                const T* __restrict__ lam, const T* __restrict__ D,
+                                                const double* __restrict__ r, const double* __restrict__ xo,
+                                                double* __restrict__ xn) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int N = M.N, NX = M.NX, F = M.F;
+  if (i >= N) return;
+  T acc[5];
+  for (int v = 0; v < 5; ++v) acc[v] = T(r[(size_t)v * N + i]);
+  if (xo) {
+    T g = T(P.gamma);
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+      int cf = M.cface[p * N + i];
+      int f = (cf > 0 ? cf : -cf) - 1;
+      int L = M.fL[f], R = M.fR[f];
+      if (R >= N) continue;  // boundary off-diagonal blocks are dropped
+      int jn = cf > 0 ? R : L;
+      T s = cf > 0 ? T(1) : T(-1);
+      T n[3] = {s * M.fn[f], s * M.fn[F + f], s * M.fn[2 * F + f]};
+      T qj[5], xj[5], jx[5];
+      for (int v = 0; v < 5; ++v) {
+        qj[v] = Qx[(size_t)v * NX + jn];
+        xj[v] = T(xo[(size_t)v * N + jn]);
+      }
+      euler_jn(g, qj, n, xj, jx);
+      T hs = T(0.5) * M.fS[f], l = lam[f];
+      for (int v = 0; v < 5; ++v) acc[v] -= hs * (jx[v] - l * xj[v]);
+    }
+  }
+  T id = T(1) / D[i];
+  for (int v = 0; v < 5; ++v) xn[(size_t)v * N + i] = double(acc[v] * id);
+}
+
+// ---------------------------------------------------------------------------
+// vector kernels (FP64 Krylov space); deterministic two-level reductions
+// ---------------------------------------------------------------------------
+constexpr int RB = 256;     // reduction block
+constexpr int RGRID = 1024; // fixed grid -> fixed summation order
+
+__device__ __forceinline__ double block_sum(double x) {
+  __shared__ double sh[RB];
+  sh[threadIdx.x] = x;
+  __syncthreads();
+  for (int s = RB / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+    __syncthreads();
+  }
+  return sh[0];
+}
+
+// part[blockIdx] = sum over a fixed strided slice of op(x, y)
+template <int OP>
+__global__ void __launch_bounds__(RB) k_reduce_part(const double* __restrict__ x, const double* __restrict__ y,
+                                                    size_t n, double* __restrict__ part) {
+  double s = 0.0;
+  for (size_t k = (size_t)blockIdx.x * RB + threadIdx.x; k < n; k += (size_t)RGRID * RB) {
+    if (OP == 0) s += x[k] * y[k];
+    else s += fabs(x[k]);
+  }
+  double t = block_sum(s);
+  if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+
+// out[0] = sum(part) (SQRT: sqrt of it)
+template <bool SQRT>
+__global__ void __launch_bounds__(RB) k_reduce_final(const double* __restrict__ part, double* __restrict__ out) {
+  double s = 0.0;
+  for (int k = threadIdx.x; k < RGRID; k += RB) s += part[k];
+  double t = block_sum(s);
+  if (threadIdx.x == 0) out[0] = SQRT ? sqrt(t) : t;
+}
+
+// y += alpha * x, alpha = sgn * a[0] (or * 1/a[0] if INV)
+__global__ void __launch_bounds__(256) k_axpy_dev(const double* __restrict__ x, double* __restrict__ y,
+                                                  size_t n, const double* __restrict__ a, double sgn) {
+  size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  y[k] += sgn * a[0] * x[k];
+}
+
+// y = x / a[0]
+__global__ void __launch_bounds__(256) k_scale_inv(const double* __restrict__ x, double* __restrict__ y, size_t n,
+                                                   const double* __restrict__ a) {
+  size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  y[k] = x[k] / a[0];
+}
+
+// y = x + sum_j c[j] V[j]  (V: nv vectors of length n, c on the device)
+__global__ void __launch_bounds__(256) k_combine(const double* __restrict__ V, const double* __restrict__ c, int nv,
+                                                 size_t n, const double* __restrict__ x, double* __restrict__ y) {
+  size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  double s = x ? x[k] : 0.0;
+  for (int j = 0; j < nv; ++j) s += c[j] * V[(size_t)j * n + k];
+  y[k] = s;
+}
+
+// Qp(cells) = Q + sigma v (Q, v: [5][N]), written into an extended array [5][NX]
+template <typename T>
+__global__ void __launch_bounds__(256) k_perturb(const double* __restrict__ Q, const double* __restrict__ v,
+                                                 const double* __restrict__ sigma, int N, int NX,
+                                                 T* __restrict__ Qp) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  double s = sigma ? sigma[0] : 0.0;
+  for (int q = 0; q < 5; ++q) {
+    double val = Q[(size_t)q * N + i] + (v ? s * v[(size_t)q * N + i] : 0.0);
+    Qp[(size_t)q * NX + i] = T(val);
+  }
+}
+
+__global__ void __launch_bounds__(256) k_convert(const double* __restrict__ src, float* __restrict__ dst,
+                                                 size_t n) {
+  size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) dst[k] = (float)src[k];
+}
+
+// automatic FD step of Eq. (frechet): sqrt(eps) max(1, rms Q) / rms v
+__global__ void k_sigma(const double* __restrict__ vv, const double* __restrict__ qq, double n, double eps,
+                        double fixed, double* __restrict__ sigma) {
+  if (threadIdx.x != 0) return;
+  double rv = sqrt(vv[0] / n);
+  if (rv == 0.0) {
+    sigma[0] = 0.0;
+    return;
+  }
+  if (fixed > 0.0) {
+    sigma[0] = fixed;
+    return;
+  }
+  double rq = sqrt(qq[0] / n);
+  sigma[0] = sqrt(eps) * fmax(1.0, rq) / rv;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_check(const T* __restrict__ Qx, int N, int NX, double gamma,
+                                               int* __restrict__ bad) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  T w[5];
+  for (int v = 0; v < 5; ++v) w[v] = Qx[(size_t)v * NX + i];
+  if (!phys_ok(w, T(gamma))) atomicOr(bad, 1);
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+static inline unsigned nblk(size_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
+template <typename T>
+void launch_ghost(const DevMesh<T>& M, const Params& P, T* Qx, T* Gx, hipStream_t s) {
+  if (M.Nb) hipLaunchKernelGGL(k_ghost<T>, dim3(nblk(M.Nb, 256)), dim3(256), 0, s, M, P, Qx, Gx);
+}
+template <typename T>
+void launch_recon(const DevMesh<T>& M, const Params& P, const T* Qx, const T* Gx, T* coef, hipStream_t s) {
+  if (P.scheme == 1)
+    hipLaunchKernelGGL(k_recon_hweno<T>, dim3(nblk(M.N, 256)), dim3(256), 0, s, M, Qx, Gx, coef);
+  else
+    hipLaunchKernelGGL(k_recon_weno<T>, dim3(nblk(M.N, 256)), dim3(256), 0, s, M, Qx, coef);
+}
+template <typename T>
+void launch_side(const DevMesh<T>& M, const Params& P, const T* Qx, const T* coef, T* sv, int* nfall,
+                 hipStream_t s) {
+  hipLaunchKernelGGL(k_side<T>, dim3(nblk(2 * (size_t)M.F, 128)), dim3(128), 0, s, M, P, Qx, coef, sv, nfall);
+}
+template <typename T>
+void launch_flux(const DevMesh<T>& M, const Params& P, const T* sv, const T* dt, T* ff, T* fq, bool qg,
+                 hipStream_t s) {
+  if (qg)
+    hipLaunchKernelGGL((k_flux<T, true>), dim3(nblk(M.F, 64)), dim3(64), 0, s, M, P, sv, dt, ff, fq);
+  else
+    hipLaunchKernelGGL((k_flux<T, false>), dim3(nblk(M.F, 64)), dim3(64), 0, s, M, P, sv, dt, ff, fq);
+}
+template <typename T, typename TO>
+void launch_gather(const DevMesh<T>& M, int mode, const T* ff, const T* fq, TO* out, const TO* v, const TO* b,
+                   const T* dt, const double* sigma, TO* gout, hipStream_t s) {
+  dim3 g(nblk(M.N, 256)), bl(256);
+  if (mode == 0)
+    hipLaunchKernelGGL((k_gather<T, TO, 0>), g, bl, 0, s, M, ff, fq, out, v, b, dt, sigma, gout);
+  else if (mode == 1)
+    hipLaunchKernelGGL((k_gather<T, TO, 1>), g, bl, 0, s, M, ff, fq, out, v, b, dt, sigma, gout);
+  else
+    hipLaunchKernelGGL((k_gather<T, TO, 2>), g, bl, 0, s, M, ff, fq, out, v, b, dt, sigma, gout);
+}
+template <typename T>
+void launch_dt(const DevMesh<T>& M, const Params& P, double cfl, const T* Qx, T* dt, hipStream_t s) {
+  hipLaunchKernelGGL(k_dt<T>, dim3(nblk(M.N, 256)), dim3(256), 0, s, M, P, cfl, Qx, dt);
+}
+template <typename T>
+void launch_lambda_diag(const DevMesh<T>& M, const Params& P, const T* Qx, const T* dt, T* lam, T* D,
+                        hipStream_t s) {
+  hipLaunchKernelGGL(k_lambda<T>, dim3(nblk(M.F, 256)), dim3(256), 0, s, M, P, Qx, lam);
+  hipLaunchKernelGGL(k_diag<T>, dim3(nblk(M.N, 256)), dim3(256), 0, s, M, lam, dt, D);
+}
+template <typename T>
+void launch_jacobi(const DevMesh<T>& M, const Params& P, const T* Qx, const T* lam, const T* D, const double* r,
+                   const double* xo, double* xn, hipStream_t s) {
+  hipLaunchKernelGGL(k_jacobi<T>, dim3(nblk(M.N, 256)), dim3(256), 0, s, M, P, Qx, lam, D, r, xo, xn);
+}
+template <typename T>
+void launch_perturb(const double* Q, const double* v, const double* sigma, int N, int NX, T* Qp, hipStream_t s) {
+  hipLaunchKernelGGL(k_perturb<T>, dim3(nblk(N, 256)), dim3(256), 0, s, Q, v, sigma, N, NX, Qp);
+}
+template <typename T>
+void launch_check(const T* Qx, int N, int NX, double gamma, int* bad, hipStream_t s) {
+  hipLaunchKernelGGL(k_check<T>, dim3(nblk(N, 256)), dim3(256), 0, s, Qx, N, NX, gamma, bad);
+}
+
+void launch_dot(const double* x, const double* y, size_t n, double* part, double* out, bool sq, hipStream_t s) {
+  hipLaunchKernelGGL(k_reduce_part<0>, dim3(RGRID), dim3(RB), 0, s, x, y, n, part);
+  if (sq)
+    hipLaunchKernelGGL(k_reduce_final<true>, dim3(1), dim3(RB), 0, s, part, out);
+  else
+    hipLaunchKernelGGL(k_reduce_final<false>, dim3(1), dim3(RB), 0, s, part, out);
+}
+void launch_abssum(const double* x, size_t n, double* part, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_reduce_part<1>, dim3(RGRID), dim3(RB), 0, s, x, x, n, part);
+  hipLaunchKernelGGL(k_reduce_final<false>, dim3(1), dim3(RB), 0, s, part, out);
+}
+void launch_axpy_dev(const double* x, double* y, size_t n, const double* a, double sgn, hipStream_t s) {
+  hipLaunchKernelGGL(k_axpy_dev, dim3(nblk(n, 256)), dim3(256), 0, s, x, y, n, a, sgn);
+}
+void launch_scale_inv(const double* x, double* y, size_t n, const double* a, hipStream_t s) {
+  hipLaunchKernelGGL(k_scale_inv, dim3(nblk(n, 256)), dim3(256), 0, s, x, y, n, a);
+}
+void launch_combine(const double* V, const double* c, int nv, size_t n, const double* x, double* y, hipStream_t s) {
+  hipLaunchKernelGGL(k_combine, dim3(nblk(n, 256)), dim3(256), 0, s, V, c, nv, n, x, y);
+}
+void launch_convert(const double* src, float* dst, size_t n, hipStream_t s) {
+  if (n) hipLaunchKernelGGL(k_convert, dim3(nblk(n, 256)), dim3(256), 0, s, src, dst, n);
+}
+void launch_sigma(const double* vv, const double* qq, double n, double eps, double fixed, double* sigma,
+                  hipStream_t s) {
+  hipLaunchKernelGGL(k_sigma, dim3(1), dim3(64), 0, s, vv, qq, n, eps, fixed, sigma);
+}
+
+#define HGKS_INST(T)                                                                                              \
+  template void launch_ghost<T>(const DevMesh<T>&, const Params&, T*, T*, hipStream_t);                           \
+  template void launch_recon<T>(const DevMesh<T>&, const Params&, const T*, const T*, T*, hipStream_t);           \
+  template void launch_side<T>(const DevMesh<T>&, const Params&, const T*, const T*, T*, int*, hipStream_t);      \
+  template void launch_flux<T>(const DevMesh<T>&, const Params&, const T*, const T*, T*, T*, bool, hipStream_t);  \
+  template void launch_dt<T>(const DevMesh<T>&, const Params&, double, const T*, T*, hipStream_t);                \
+  template void launch_lambda_diag<T>(const DevMesh<T>&, const Params&, const T*, const T*, T*, T*, hipStream_t); \
+  template void launch_jacobi<T>(const DevMesh<T>&, const Params&, const T*, const T*, const T*, const double*,   \
+                                 const double*, double*, hipStream_t);                                           \
+  template void launch_perturb<T>(const double*, const double*, const double*, int, int, T*, hipStream_t);        \
+  template void launch_check<T>(const T*, int, int, double, int*, hipStream_t);
+HGKS_INST(double)
+HGKS_INST(float)
+template void launch_gather<double, double>(const DevMesh<double>&, int, const double*, const double*, double*,
+                                            const double*, const double*, const double*, const double*, double*,
+                                            hipStream_t);
+template void launch_gather<float, double>(const DevMesh<float>&, int, const float*, const float*, double*,
+                                           const double*, const double*, const float*, const double*, double*,
+                                           hipStream_t);
+
+}  // namespace hgks

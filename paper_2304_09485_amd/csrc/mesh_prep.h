@@ -1,0 +1,39 @@
+// Host preprocessing of a tetrahedral mesh: faces, geometry, ghost cells,
+// reconstruction stencils (paper Sec. 3.1) and the per-cell least-squares
+// operators of the WENO (Sec. 3.2) and HWENO (Sec. 3.3) reconstructions.
+#pragma once
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+namespace hgks {
+
+struct HostMesh {
+  int N = 0, F = 0, Nb = 0;
+  // cells
+  std::vector<double> vol, h, hdt, m2s;  // m2s [6][N]
+  std::vector<double> cen;               // [3][N]
+  // faces
+  std::vector<int> fL, fR, ftag;         // ftag: boundary tag or -1
+  std::vector<double> fn, fS, fxiL, fxiR;// fn [3][F], fxi [9][F]
+  std::vector<int> cface;                // [4][N]
+  // ghosts
+  std::vector<int> gowner, gface;
+  // WENO
+  std::vector<int> stn, sstn;            // [16][N], [24][N]
+  std::vector<double> opA, opB;          // [144][N], [72][N]
+  std::vector<uint8_t> smask;            // [N]
+  // HWENO
+  std::vector<int> nb4;                  // [4][N]
+  std::vector<double> opH, hsub;         // [171][N], [24][N]
+  // diagnostics
+  int64_t n_big_fallback = 0, n_sub_dropped = 0;
+  double total_volume = 0.0;
+};
+
+// Returns 0 on success, -3 (mesh error) or -1 (bad argument) with err set.
+int build_host_mesh(HostMesh& H, int64_t n_nodes, const double* xyz, int64_t n_tets, const int32_t* tet2node,
+                    int64_t n_bf, const int32_t* bf, const int32_t* btag, std::string& err);
+
+}  // namespace hgks

@@ -1,0 +1,223 @@
+"""Python binding of libhgks (argument marshalling only).
+
+Every step of the residual / Jv / implicit step runs in the HIP kernels of
+`libhgks.so`; this module converts numpy arrays (host) or torch tensors
+(device) to pointers and checks status codes.  If the library has not been
+built, importing the binding raises: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhgks.so")
+
+WENO, HWENO = 0, 1
+EULER, NS = 0, 1
+FP64, FP32_INNER = 0, 1
+WEIGHTS_NONLINEAR, WEIGHTS_LINEAR = 0, 1
+FARFIELD, SLIP_WALL, NOSLIP_ADIABATIC, SUP_IN, SUP_OUT = 0, 1, 2, 3, 4
+
+STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EMESH", -4: "ESTATE", -5: "ENOCONV", -6: "EDEVICE"}
+
+# exported symbols declared in include/hgks.h
+SYMBOLS = ["hgks_default_options", "hgks_create", "hgks_load_mesh", "hgks_set_freestream", "hgks_set_bc",
+           "hgks_set_state", "hgks_get_state", "hgks_residual", "hgks_time_step", "hgks_jv", "hgks_precond",
+           "hgks_implicit_step", "hgks_solve_steady", "hgks_residual_dev", "hgks_jv_dev", "hgks_n_cells",
+           "hgks_n_faces", "hgks_kernel_times", "hgks_last_error", "hgks_destroy"]
+
+
+class HgksError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("scheme", ctypes.c_int32), ("physics", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("weights", ctypes.c_int32), ("krylov_dim", ctypes.c_int32), ("restarts", ctypes.c_int32),
+                ("jacobi_sweeps", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("gamma", ctypes.c_double), ("cfl", ctypes.c_double), ("tau_eps", ctypes.c_double),
+                ("tau_C", ctypes.c_double), ("gamma_lin", ctypes.c_double), ("weno_eps", ctypes.c_double),
+                ("mu", ctypes.c_double), ("prandtl", ctypes.c_double), ("fd_sigma", ctypes.c_double),
+                ("stream", ctypes.c_void_p)]
+
+
+class StepInfo(ctypes.Structure):
+    _fields_ = [("res", ctypes.c_double), ("res_rel", ctypes.c_double), ("gmres_rel", ctypes.c_double),
+                ("n_resid_evals", ctypes.c_int64), ("n_fallbacks", ctypes.c_int64), ("t_ms", ctypes.c_double)]
+
+
+class SolveInfo(ctypes.Structure):
+    _fields_ = [("steps", ctypes.c_int32), ("converged", ctypes.c_int32), ("res0", ctypes.c_double),
+                ("res_final", ctypes.c_double), ("drop", ctypes.c_double), ("n_resid_evals", ctypes.c_int64),
+                ("t_ms", ctypes.c_double)]
+
+
+_lib = None
+
+
+def load_library():
+    """Load libhgks.so; raises if it is missing (build it with
+    `python -m paper_2304_09485_amd.build`)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} not built: run `python -m paper_2304_09485_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, d = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    sig = {
+        "hgks_default_options": (None, [ctypes.POINTER(Options)]),
+        "hgks_create": (i32, [ctypes.POINTER(Options), ctypes.POINTER(vp)]),
+        "hgks_load_mesh": (i32, [vp, i64, vp, i64, vp, i64, vp, vp]),
+        "hgks_set_freestream": (i32, [vp, vp]),
+        "hgks_set_bc": (i32, [vp, i32, i32, vp]),
+        "hgks_set_state": (i32, [vp, vp, vp]),
+        "hgks_get_state": (i32, [vp, vp, vp]),
+        "hgks_residual": (i32, [vp, vp, vp, vp, vp]),
+        "hgks_time_step": (i32, [vp, vp, vp]),
+        "hgks_jv": (i32, [vp, vp, d, vp, vp]),
+        "hgks_precond": (i32, [vp, vp, vp]),
+        "hgks_implicit_step": (i32, [vp, ctypes.POINTER(StepInfo)]),
+        "hgks_solve_steady": (i32, [vp, d, i32, ctypes.POINTER(SolveInfo)]),
+        "hgks_residual_dev": (i32, [vp, vp, vp, vp]),
+        "hgks_jv_dev": (i32, [vp, vp, d, vp, vp]),
+        "hgks_n_cells": (i64, [vp]),
+        "hgks_n_faces": (i64, [vp]),
+        "hgks_kernel_times": (i32, [vp, vp, vp, ctypes.POINTER(i32), i32]),
+        "hgks_last_error": (ctypes.c_char_p, [vp]),
+        "hgks_destroy": (None, [vp]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(L, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = L
+    return L
+
+
+def default_options(**kw) -> Options:
+    o = Options()
+    load_library().hgks_default_options(ctypes.byref(o))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise AttributeError(k)
+        setattr(o, k, v)
+    return o
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _ptr(a):
+    return None if a is None else ctypes.c_void_p(a.ctypes.data)
+
+
+class Solver:
+    """One steady problem: mesh, boundary kinds, free stream and state."""
+
+    def __init__(self, mesh, kinds: dict, prim, **opts):
+        self._L = load_library()
+        self.opts = default_options(**opts)
+        h = ctypes.c_void_p()
+        self._check(self._L.hgks_create(ctypes.byref(self.opts), ctypes.byref(h)), None)
+        self.h = h
+        xyz, tets, bf, bt = mesh.arrays()
+        self._check(self._L.hgks_load_mesh(self.h, len(xyz), _ptr(xyz), len(tets), _ptr(tets), len(bf), _ptr(bf),
+                                           _ptr(bt)))
+        p = _f64(prim)
+        self._check(self._L.hgks_set_freestream(self.h, _ptr(p)))
+        for tag, kind in kinds.items():
+            self._check(self._L.hgks_set_bc(self.h, int(tag), int(kind), None))
+        self.N = int(self._L.hgks_n_cells(self.h))
+        self.F = int(self._L.hgks_n_faces(self.h))
+
+    def _check(self, st, h="self"):
+        if st != 0:
+            msg = self._L.hgks_last_error(self.h if h == "self" else None)
+            raise HgksError(st, msg.decode() if msg else "")
+
+    def close(self):
+        if getattr(self, "h", None):
+            self._L.hgks_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # --- host-array interface -------------------------------------------------
+    def set_state(self, Q, G=None):
+        Q = _f64(Q)
+        G = None if G is None else _f64(G)
+        self._check(self._L.hgks_set_state(self.h, _ptr(Q), _ptr(G)))
+
+    def get_state(self, want_grad=False):
+        Q = np.zeros((5, self.N))
+        G = np.zeros((15, self.N)) if want_grad else None
+        self._check(self._L.hgks_get_state(self.h, _ptr(Q), _ptr(G)))
+        return (Q, G) if want_grad else Q
+
+    def residual(self, Q=None, G=None, want_grad=False, allow_bad_state=False):
+        Q = None if Q is None else _f64(Q)
+        G = None if G is None else _f64(G)
+        R = np.zeros((5, self.N))
+        Gn = np.zeros((15, self.N)) if want_grad else None
+        st = self._L.hgks_residual(self.h, _ptr(Q), _ptr(G), _ptr(R), _ptr(Gn))
+        if not (allow_bad_state and st == -4):
+            self._check(st)
+        return (R, Gn) if want_grad else R
+
+    def time_step(self, Q=None):
+        Q = None if Q is None else _f64(Q)
+        dt = np.zeros(self.N)
+        self._check(self._L.hgks_time_step(self.h, _ptr(Q), _ptr(dt)))
+        return dt
+
+    def jv(self, v, sigma=0.0):
+        v = _f64(v)
+        Av = np.zeros((5, self.N))
+        s = ctypes.c_double()
+        self._check(self._L.hgks_jv(self.h, _ptr(v), float(sigma), _ptr(Av), ctypes.byref(s)))
+        return Av, s.value
+
+    def precond(self, r):
+        r = _f64(r)
+        out = np.zeros((5, self.N))
+        self._check(self._L.hgks_precond(self.h, _ptr(r), _ptr(out)))
+        return out
+
+    def implicit_step(self):
+        info = StepInfo()
+        self._check(self._L.hgks_implicit_step(self.h, ctypes.byref(info)))
+        return info
+
+    def solve_steady(self, drop=1e-8, max_steps=1000, raise_on_noconv=False):
+        info = SolveInfo()
+        st = self._L.hgks_solve_steady(self.h, float(drop), int(max_steps), ctypes.byref(info))
+        if st != 0 and (st != -5 or raise_on_noconv):
+            self._check(st)
+        return info
+
+    # --- device interface (torch tensors, caller's stream) ---------------------
+    def residual_dev(self, Q, R, stream=None):
+        self._check(self._L.hgks_residual_dev(self.h, ctypes.c_void_p(Q.data_ptr()), ctypes.c_void_p(R.data_ptr()),
+                                              ctypes.c_void_p(stream)))
+
+    def jv_dev(self, v, Av, sigma=0.0, stream=None):
+        self._check(self._L.hgks_jv_dev(self.h, ctypes.c_void_p(v.data_ptr()), float(sigma),
+                                        ctypes.c_void_p(Av.data_ptr()), ctypes.c_void_p(stream)))
+
+    def kernel_times(self):
+        names = (ctypes.c_char_p * 8)()
+        ms = (ctypes.c_double * 8)()
+        n = ctypes.c_int32()
+        self._check(self._L.hgks_kernel_times(self.h, names, ms, ctypes.byref(n), 8))
+        return {names[k].decode(): ms[k] for k in range(n.value)}

@@ -1,0 +1,194 @@
+"""GPU parity of the HIP path (through the C ABI) against the FP64 oracle.
+
+Tolerances (derived, not tuned):
+  * residual: max |R_gpu - R_orc| <= 1e-12 x flux scale, the flux scale being
+    (largest cell surface) x |Euler flux of the free stream|: near a steady
+    state R is a small difference of large face fluxes, so it is normalised by
+    the fluxes, not by |R|.
+  * Jv at step sigma: a residual difference dR becomes dR/sigma, so the bound
+    is 2 x 1e-12 x flux scale / sigma (plus 1e-12 relative).
+  * preconditioner, time step: plain FP64 arithmetic on the same formulas,
+    1e-12 relative.
+  * implicit steps: both sides run the same GMRES on FD products whose
+    round-off differs (see Jv); bound stated at each test.
+"""
+import numpy as np
+import pytest
+
+from inputs import freestream_prim, mesh_for_config, perturbed_state, uniform_state
+from tests import _cases as C
+
+pytestmark = pytest.mark.gpu
+
+
+def _grads(case, n, seed=7):
+    if C.CASES[case][3].get("scheme", 0) != 1:
+        return None
+    return np.random.default_rng(seed).normal(scale=0.05, size=(15, n))
+
+
+@pytest.fixture(scope="module")
+def built(oracle_lib):
+    cache = {}
+
+    def get(case):
+        if case not in cache:
+            mk, kinds, mach, opts = C.CASES[case]
+            m = mk()
+            prim = freestream_prim(mach)
+            o, s = C.pair(oracle_lib, m, kinds, prim, **opts)
+            cache[case] = (m, prim, o, s)
+        return cache[case]
+    return get
+
+
+@pytest.mark.parametrize("case", list(C.CASES))
+def test_residual_parity(built, case):
+    m, prim, o, s = built(case)
+    Q = C.state_for(o.N, prim[1], seed=2, amp=0.02) if False else perturbed_state(o.N, prim, amp=0.02, seed=2)
+    G = _grads(case, o.N)
+    hw = G is not None
+    Ro = o.residual(Q, G=G, want_grad=hw)
+    Rg = s.residual(Q, G=G, want_grad=hw)
+    fs = C.flux_scale(m, prim)
+    if hw:
+        Ro, Gno, fb = Ro
+        Rg, Gng = Rg
+        vol = o.geometry()[0]
+        gscale = np.abs(Q).max() * fs / np.abs(prim).max() / vol.min() * 10
+        assert np.abs(Gng - Gno).max() <= 1e-12 * gscale
+    err = np.abs(Rg - Ro).max() / fs
+    print(f"{case}: max|dR|/flux_scale = {err:.3e}")
+    assert err <= 1e-12
+
+
+@pytest.mark.parametrize("case", ["c1_weno", "shell_ns"])
+def test_time_step_parity(built, case):
+    m, prim, o, s = built(case)
+    Q = perturbed_state(o.N, prim, seed=3)
+    np.testing.assert_allclose(s.time_step(Q), o.dt(Q), rtol=1e-13)
+
+
+@pytest.mark.parametrize("case", ["c1_weno", "shell_hweno", "shell_ns"])
+def test_jv_parity(built, case):
+    m, prim, o, s = built(case)
+    Q = perturbed_state(o.N, prim, seed=4)
+    G = _grads(case, o.N)
+    s.set_state(Q, G)
+    dt = o.dt(Q)
+    b = o.residual(Q, G=G, dt=dt)
+    v = np.random.default_rng(11).normal(size=(5, o.N))
+    fs = C.flux_scale(m, prim)
+    for sigma in (1e-6, 0.0):
+        Avg, sg = s.jv(v, sigma)
+        Avo, so = o.jv(Q, dt, b, v, sigma=sigma, G=G)
+        assert sg == pytest.approx(so, rel=1e-12)
+        tol = 2e-12 * fs / so + 1e-12 * np.abs(Avo).max()
+        err = np.abs(Avg - Avo).max()
+        print(f"{case} sigma={so:.3e}: max|dAv| = {err:.3e} (tol {tol:.3e}, |Av| {np.abs(Avo).max():.3e})")
+        assert err <= tol
+
+
+@pytest.mark.parametrize("case", ["c1_weno", "shell_weno"])
+def test_precond_parity(built, case):
+    m, prim, o, s = built(case)
+    Q = perturbed_state(o.N, prim, seed=5)
+    s.set_state(Q)
+    r = np.random.default_rng(3).normal(size=(5, o.N))
+    pg = s.precond(r)
+    po = o.precond(Q, o.dt(Q), r)
+    np.testing.assert_allclose(pg, po, rtol=1e-12, atol=1e-12 * np.abs(po).max())
+
+
+def test_free_stream_preserved_gpu(built):
+    for case in ("shell_weno", "shell_hweno"):
+        m, prim, o, s = built(case)
+        Q = uniform_state(o.N, prim)
+        R = s.residual(Q, G=np.zeros((15, o.N)))
+        assert np.abs(R).max() <= 1e-13 * C.flux_scale(m, prim)
+
+
+def test_residual_deterministic(built):
+    m, prim, o, s = built("c1_weno")
+    Q = perturbed_state(o.N, prim, seed=6)
+    assert np.array_equal(s.residual(Q), s.residual(Q))
+
+
+def test_implicit_steps_c1(built, oracle_lib):
+    """The configuration-1 run: 10 implicit steps of the FP64 WENO scheme.
+    FD products differ by round-off/sigma (~1e-8 relative), GMRES maps that
+    into the update; the fields must still agree to 1e-9 relative to |Q|
+    after 1 step and 1e-7 after 10 (drift of the FD round-off)."""
+    m, prim, o, s = built("c1_weno")
+    Q0 = perturbed_state(o.N, prim, seed=1)
+    Qo = Q0.copy()
+    s.set_state(Q0)
+    oracle_lib.set_threads(16)
+    try:
+        for k in range(10):
+            st, io = o.implicit_step(Qo)
+            ig = s.implicit_step()
+            assert st == 0 and ig.n_resid_evals == io.n_resid_evals == 33
+            Qg = s.get_state()
+            err = np.abs(Qg - Qo).max() / np.abs(Qo).max()
+            print(f"step {k + 1}: res gpu {ig.res:.6e} orc {io.res:.6e} field err {err:.3e}")
+            assert ig.res == pytest.approx(io.res, rel=1e-9)
+            assert err <= (1e-9 if k == 0 else 1e-7)
+    finally:
+        oracle_lib.set_threads(1)
+
+
+def test_residual_dev_matches_host(built):
+    torch = pytest.importorskip("torch")
+    m, prim, o, s = built("shell_weno")
+    Q = perturbed_state(o.N, prim, seed=8)
+    Rh = s.residual(Q)
+    Qd = torch.from_numpy(Q).cuda()
+    Rd = torch.empty_like(Qd)
+    st = torch.cuda.current_stream()
+    s.residual_dev(Qd, Rd, stream=st.cuda_stream)
+    st.synchronize()
+    assert np.array_equal(Rd.cpu().numpy(), Rh)
+
+
+def test_error_paths(built):
+    from paper_2304_09485_amd import hgks
+    m, prim, o, s = built("shell_weno")
+    Q = perturbed_state(o.N, prim, seed=9)
+    Q[0, 5] = -1.0
+    with pytest.raises(hgks.HgksError) as e:
+        s.residual(Q)
+    assert e.value.status == -4
+    bad = mesh_for_config("c1")
+    t = bad.tets.copy()
+    t[0, [2, 3]] = t[0, [3, 2]]
+    bad.tets = t
+    with pytest.raises(hgks.HgksError) as e:
+        hgks.Solver(bad, {k: 0 for k in range(1, 7)}, prim)
+    assert e.value.status == -3
+    with pytest.raises(hgks.HgksError) as e:
+        hgks.Solver(bad, {}, prim, krylov_dim=0)
+    assert e.value.status == -1
+
+
+def test_c2_full_size(oracle_lib):
+    """Residual at the 202,752-tet sphere-shell size in the benchmark's launch
+    configuration (compact HWENO, slip wall + far field, Mach 0.5)."""
+    from paper_2304_09485_amd import hgks
+    m = mesh_for_config("c2")
+    prim = freestream_prim(0.5)
+    kinds = {1: C.SLIP, 2: C.FAR}
+    s = hgks.Solver(m, kinds, prim, scheme=1)
+    o = oracle_lib.Oracle(m, kinds, prim, scheme=1)
+    Q = perturbed_state(o.N, prim, seed=2)
+    G = np.random.default_rng(5).normal(scale=0.02, size=(15, o.N))
+    oracle_lib.set_threads(16)
+    try:
+        Ro, Gno, _ = o.residual(Q, G=G, want_grad=True)
+    finally:
+        oracle_lib.set_threads(1)
+    Rg, Gng = s.residual(Q, G=G, want_grad=True)
+    fs = C.flux_scale(m, prim)
+    err = np.abs(Rg - Ro).max() / fs
+    print(f"c2 full size: max|dR|/flux_scale = {err:.3e}")
+    assert err <= 1e-12
