@@ -47,7 +47,13 @@ def build(verbose: bool = True) -> str:
     out = subprocess.run([exe], check=True, capture_output=True, text=True).stdout
     with open(os.path.join(HERE, "flux_flops.json"), "w") as f:
         f.write(out)
+    # host instantiation of the flux for the CPU tests (not part of libhgks)
+    _run(["hipcc", "-O2", "-std=c++17", "-fPIC", "-shared", "-I", CSRC, os.path.join(CSRC, "host_check.cpp"),
+          "-o", HOSTCHECK])
     return LIB
+
+
+HOSTCHECK = os.path.join(BUILD, "libhgks_hostcheck.so")
 
 
 if __name__ == "__main__":

@@ -14,17 +14,45 @@
 namespace {
 long n_add = 0, n_mul = 0, n_div = 0, n_sqrt = 0, n_trans = 0;
 
+// A value constructed from a literal 0 or 1 is a structural constant: the
+// compiler folds x * 0, x + 0 and x * 1, so those are not counted.
 struct C {
   double v;
-  C() : v(0) {}
-  C(double x) : v(x) {}
-  explicit C(int x) : v(x) {}
+  bool z, one;
+  C() : v(0), z(true), one(false) {}
+  C(double x) : v(x), z(x == 0.0), one(x == 1.0) {}
+  explicit C(int x) : v(x), z(x == 0), one(x == 1) {}
+  static C val(double x) {
+    C c(x);
+    c.z = c.one = false;
+    return c;
+  }
 };
-inline C operator+(C a, C b) { ++n_add; return C(a.v + b.v); }
-inline C operator-(C a, C b) { ++n_add; return C(a.v - b.v); }
-inline C operator-(C a) { return C(-a.v); }
-inline C operator*(C a, C b) { ++n_mul; return C(a.v * b.v); }
-inline C operator/(C a, C b) { ++n_div; return C(a.v / b.v); }
+inline C operator+(C a, C b) {
+  if (a.z) return b;
+  if (b.z) return a;
+  ++n_add;
+  return C::val(a.v + b.v);
+}
+inline C operator-(C a) {
+  C r = C::val(-a.v);
+  r.z = a.z;
+  return r;
+}
+inline C operator-(C a, C b) { return a + (-b); }
+inline C operator*(C a, C b) {
+  if (a.z || b.z) return C();
+  if (a.one) return b;
+  if (b.one) return a;
+  ++n_mul;
+  return C::val(a.v * b.v);
+}
+inline C operator/(C a, C b) {
+  if (a.z) return C();
+  if (b.one) return a;
+  ++n_div;
+  return C::val(a.v / b.v);
+}
 inline C& operator+=(C& a, C b) { a = a + b; return a; }
 inline C& operator-=(C& a, C b) { a = a - b; return a; }
 inline C& operator*=(C& a, C b) { a = a * b; return a; }

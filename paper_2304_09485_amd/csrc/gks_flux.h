@@ -2,28 +2,34 @@
 // (paper Sec. 2 Eq. (flux) and the moment systems below it; time average of
 // Sec. 4.1; collision time of Sec. 5; Prandtl correction of the heat flux).
 //
-// Velocity moments of a Maxwellian are tabulated per side once; every moment
-// the flux needs is then a compile-time indexed product, so the compiler emits
-// straight-line VALU code.  T is double (plain path) or float (inner path of
-// the mixed-precision form).
+// Every velocity moment the scheme needs has the form <u^k psi_j W>, with W a
+// polynomial in (u, v, w, xi^2) of degree <= 3 built from the expansion
+// coefficients (a . psi, u a_n.psi + v a_t1.psi + w a_t2.psi, A . psi).  W is
+// held in a fixed 23-monomial basis.  Because the Maxwellian factorises over
+// u, v, w and xi, the (v, w, xi) part of each monomial is summed once into 16
+// "G-sums" (grouped by the power of u); the moments for any u-table (half or
+// full space, k = 0 or 1) are then 4-term dot products.  T is double (plain
+// path) or float (inner operator of the mixed-precision form).
 #pragma once
 #include <hip/hip_runtime.h>
 
 namespace hgks {
 
+#define HGKS_HD __host__ __device__ __forceinline__
+
+// moments of v, w (full space) and xi of one Maxwellian
 template <typename T>
-struct Mxw {
-  T u[8];  // <u^k>, half or full space
-  T v[6];  // <v^k>
-  T w[6];  // <w^k>
-  T x2, x4;  // <xi^2>, <xi^4>
+struct VWX {
+  T v[6], w[6], x2, x4;
 };
 
 template <typename T>
-__host__ __device__ __forceinline__ void mxw_vw(Mxw<T>& M, T V, T W, T lam, T K) {
+HGKS_HD void vwx_table(VWX<T>& M, T V, T W, T lam, T K) {
   T r = T(0.5) / lam;
-  M.v[0] = T(1); M.v[1] = V;
-  M.w[0] = T(1); M.w[1] = W;
+  M.v[0] = T(1);
+  M.v[1] = V;
+  M.w[0] = T(1);
+  M.w[1] = W;
 #pragma unroll
   for (int k = 2; k < 6; ++k) {
     M.v[k] = V * M.v[k - 1] + T(k - 1) * r * M.v[k - 2];
@@ -33,66 +39,154 @@ __host__ __device__ __forceinline__ void mxw_vw(Mxw<T>& M, T V, T W, T lam, T K)
   M.x4 = K * (K + T(2)) * r * r;
 }
 
-// u-moments; sgn = 0 full space, +1 half space u > 0, -1 half space u < 0
+// u-moments <u^k>, k < 8, from <u^0> and <u^1> (recurrence valid for the
+// full space and both half spaces)
 template <typename T>
-__host__ __device__ __forceinline__ void mxw_u(Mxw<T>& M, T U, T lam, int sgn) {
+HGKS_HD void u_table(T u[8], T U, T lam, T u0, T u1) {
   T r = T(0.5) / lam;
-  if (sgn == 0) {
-    M.u[0] = T(1);
-    M.u[1] = U;
-  } else {
-    T sl = sqrt(lam);
-    T e = exp(-lam * U * U) / sqrt(T(M_PI) * lam);
-    if (sgn > 0) {
-      M.u[0] = T(0.5) * erfc(-sl * U);
-      M.u[1] = U * M.u[0] + T(0.5) * e;
-    } else {
-      M.u[0] = T(0.5) * erfc(sl * U);
-      M.u[1] = U * M.u[0] - T(0.5) * e;
-    }
-  }
+  u[0] = u0;
+  u[1] = u1;
 #pragma unroll
-  for (int k = 2; k < 8; ++k) M.u[k] = U * M.u[k - 1] + T(k - 1) * r * M.u[k - 2];
+  for (int k = 2; k < 8; ++k) u[k] = U * u[k - 1] + T(k - 1) * r * u[k - 2];
 }
 
-template <int a, int b, int c, int d, typename T>
-__host__ __device__ __forceinline__ T mm(const Mxw<T>& M) {
-  T x = M.u[a] * M.v[b] * M.w[c];
-  if (d == 1) x *= M.x2;
-  if (d == 2) x *= M.x4;
-  return x;
+// <u^0>, <u^1> over u > 0 (sgn > 0) or u < 0 (sgn < 0)
+template <typename T>
+HGKS_HD void half_base(T U, T lam, int sgn, T& u0, T& u1) {
+  T sl = sqrt(lam);
+  T e = exp(-lam * U * U) / sqrt(T(M_PI) * lam);
+  if (sgn > 0) {
+    u0 = T(0.5) * erfc(-sl * U);
+    u1 = U * u0 + T(0.5) * e;
+  } else {
+    u0 = T(0.5) * erfc(sl * U);
+    u1 = U * u0 - T(0.5) * e;
+  }
 }
 
-// out += s <u^a v^b w^c xi^(2d) psi>
-template <int a, int b, int c, int d, typename T>
-__host__ __device__ __forceinline__ void psi5(const Mxw<T>& M, T s, T out[5]) {
-  out[0] += s * mm<a, b, c, d>(M);
-  out[1] += s * mm<a + 1, b, c, d>(M);
-  out[2] += s * mm<a, b + 1, c, d>(M);
-  out[3] += s * mm<a, b, c + 1, d>(M);
-  out[4] += s * T(0.5) * (mm<a + 2, b, c, d>(M) + mm<a, b + 2, c, d>(M) + mm<a, b, c + 2, d>(M) +
-                          mm<a, b, c, d + 1>(M));
+// Monomial basis u^i v^j w^l xi^(2q), 23 entries, grouped by i:
+//  i=0: 1 v w v2 w2 vw xi2 v3 vw2 vxi2 v2w w3 wxi2   i=1: u uv uw uv2 uw2 uxi2
+//  i=2: u2 u2v u2w                                    i=3: u3
+HGKS_HD constexpr int mono_i(int m) { return m < 13 ? 0 : (m < 19 ? 1 : (m < 22 ? 2 : 3)); }
+HGKS_HD constexpr int mono_j(int m) {
+  return m == 1 || m == 5 || m == 8 || m == 9 || m == 14 || m == 20 ? 1
+         : m == 3 || m == 10 || m == 16                            ? 2
+         : m == 7                                                  ? 3
+                                                                   : 0;
+}
+HGKS_HD constexpr int mono_l(int m) {
+  return m == 2 || m == 5 || m == 10 || m == 12 || m == 15 || m == 21 ? 1
+         : m == 4 || m == 8 || m == 17                              ? 2
+         : m == 11                                                  ? 3
+                                                                    : 0;
+}
+HGKS_HD constexpr int mono_q(int m) { return m == 6 || m == 9 || m == 12 || m == 18 ? 1 : 0; }
+
+// c += s (a . psi), psi = (1, u, v, w, (u^2+v^2+w^2+xi^2)/2)
+template <typename T>
+HGKS_HD void add_apsi(T c[23], const T a[5], T s) {
+  c[0] += s * a[0];
+  c[13] += s * a[1];
+  c[1] += s * a[2];
+  c[2] += s * a[3];
+  T h = T(0.5) * s * a[4];
+  c[19] += h;
+  c[3] += h;
+  c[4] += h;
+  c[6] += h;
 }
 
-// out += s <(co . psi) u^a v^b w^c psi>
-template <int a, int b, int c, typename T>
-__host__ __device__ __forceinline__ void apsi(const Mxw<T>& M, const T co[5], T s, T out[5]) {
-  psi5<a, b, c, 0>(M, s * co[0], out);
-  psi5<a + 1, b, c, 0>(M, s * co[1], out);
-  psi5<a, b + 1, c, 0>(M, s * co[2], out);
-  psi5<a, b, c + 1, 0>(M, s * co[3], out);
-  T hh = T(0.5) * s * co[4];
-  psi5<a + 2, b, c, 0>(M, hh, out);
-  psi5<a, b + 2, c, 0>(M, hh, out);
-  psi5<a, b, c + 2, 0>(M, hh, out);
-  psi5<a, b, c, 1>(M, hh, out);
+// c += s (u a_n.psi + v a_t1.psi + w a_t2.psi)
+template <typename T>
+HGKS_HD void add_slopes(T c[23], const T an[5], const T at1[5], const T at2[5], T s) {
+  T hn = T(0.5) * s * an[4], h1 = T(0.5) * s * at1[4], h2 = T(0.5) * s * at2[4];
+  c[13] += s * an[0];
+  c[19] += s * an[1];
+  c[14] += s * (an[2] + at1[1]);
+  c[15] += s * (an[3] + at2[1]);
+  c[22] += hn;
+  c[16] += hn;
+  c[17] += hn;
+  c[18] += hn;
+  c[1] += s * at1[0];
+  c[3] += s * at1[2];
+  c[5] += s * (at1[3] + at2[2]);
+  c[20] += h1;
+  c[7] += h1;
+  c[8] += h1;
+  c[9] += h1;
+  c[2] += s * at2[0];
+  c[4] += s * at2[3];
+  c[21] += h2;
+  c[10] += h2;
+  c[11] += h2;
+  c[12] += h2;
+}
+
+template <typename T>
+struct GSum {
+  T g0[4], gv[4], gw[4], g4[4];
+};
+
+template <typename T>
+HGKS_HD T xi_mom(const VWX<T>& M, int q) {
+  return q == 0 ? T(1) : (q == 1 ? M.x2 : M.x4);
+}
+
+// G-sums of a weight polynomial: for each power i of u,
+//   g0 = sum c <v^j w^l xi^2q>,  gv: one more v,  gw: one more w,
+//   g4 = sum c (<v^(j+2) w^l xi^2q> + <v^j w^(l+2) xi^2q> + <v^j w^l xi^(2q+2)>)
+template <typename T>
+HGKS_HD void gsum(const T c[23], const VWX<T>& M, GSum<T>& G) {
+#pragma unroll
+  for (int i = 0; i < 4; ++i) G.g0[i] = G.gv[i] = G.gw[i] = G.g4[i] = T(0);
+#pragma unroll
+  for (int m = 0; m < 23; ++m) {
+    const int i = mono_i(m), j = mono_j(m), l = mono_l(m), q = mono_q(m);
+    T x0 = xi_mom(M, q), x1 = xi_mom(M, q + 1);
+    T vw = M.v[j] * M.w[l];
+    G.g0[i] += c[m] * (vw * x0);
+    G.gv[i] += c[m] * (M.v[j + 1] * M.w[l] * x0);
+    G.gw[i] += c[m] * (M.v[j] * M.w[l + 1] * x0);
+    G.g4[i] += c[m] * ((M.v[j + 2] * M.w[l] + M.v[j] * M.w[l + 2]) * x0 + vw * x1);
+  }
+}
+
+template <typename T>
+HGKS_HD void gaxpy(GSum<T>& Y, T s, const GSum<T>& X) {
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    Y.g0[i] += s * X.g0[i];
+    Y.gv[i] += s * X.gv[i];
+    Y.gw[i] += s * X.gw[i];
+    Y.g4[i] += s * X.g4[i];
+  }
+}
+
+// out += s <u^k psi W> for the u-table u[] and the G-sums of W
+template <int k, typename T>
+HGKS_HD void gmom(const T u[8], const GSum<T>& G, T s, T out[5]) {
+  T o0 = T(0), o1 = T(0), o2 = T(0), o3 = T(0), o4 = T(0);
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    o0 += u[k + i] * G.g0[i];
+    o1 += u[k + i + 1] * G.g0[i];
+    o2 += u[k + i] * G.gv[i];
+    o3 += u[k + i] * G.gw[i];
+    o4 += u[k + i + 2] * G.g0[i] + u[k + i] * G.g4[i];
+  }
+  out[0] += s * o0;
+  out[1] += s * o1;
+  out[2] += s * o2;
+  out[3] += s * o3;
+  out[4] += s * T(0.5) * o4;
 }
 
 // Closed-form solution of <a psi> = b (normalised moments of the full-space
 // Maxwellian with velocity (U,V,W), lam = rho/(2p), K internal dof): solved
 // in the peculiar-velocity basis where the moment matrix is block diagonal.
 template <typename T>
-__host__ __device__ __forceinline__ void micro_slope(const T b[5], T U, T V, T W, T lam, T K, T a[5]) {
+HGKS_HD void micro_slope(const T b[5], T U, T V, T W, T lam, T K, T a[5]) {
   T q2 = U * U + V * V + W * W;
   T d1 = b[0];
   T d2 = b[1] - U * b[0];
@@ -108,43 +202,79 @@ __host__ __device__ __forceinline__ void micro_slope(const T b[5], T U, T V, T W
   a[0] = al0 - U * a[1] - V * a[2] - W * a[3] - T(0.5) * q2 * a5;
 }
 
-// time derivative coefficients from <a_n u + a_t1 v + a_t2 w + A> = 0
-template <typename T>
-__host__ __device__ __forceinline__ void time_slope(const Mxw<T>& M, const T an[5], const T at1[5],
-                                           const T at2[5], T U, T V, T W, T lam, T K, T A[5]) {
-  T s[5] = {0, 0, 0, 0, 0};
-  apsi<1, 0, 0>(M, an, T(-1), s);
-  apsi<0, 1, 0>(M, at1, T(-1), s);
-  apsi<0, 0, 1>(M, at2, T(-1), s);
-  micro_slope(s, U, V, W, lam, K, A);
-}
-
-// Moments of one distribution term with an extra u^k weight:
-// out += rho [c0 <u^k psi> + c1 (<u^(k+1) a_n psi> + <u^k v a_t1 psi> + <u^k w a_t2 psi>) + c2 <u^k A psi>]
-template <int k, typename T>
-__host__ __device__ __forceinline__ void term_moments(const Mxw<T>& M, T rho, T c0, T c1, T c2,
-                                             const T an[5], const T at1[5], const T at2[5],
-                                             const T A[5], T out[5]) {
-  psi5<k, 0, 0, 0>(M, rho * c0, out);
-  apsi<k + 1, 0, 0>(M, an, rho * c1, out);
-  apsi<k, 1, 0>(M, at1, rho * c1, out);
-  apsi<k, 0, 1>(M, at2, rho * c1, out);
-  apsi<k, 0, 0>(M, A, rho * c2, out);
-}
-
 template <typename T>
 struct FluxParams {
   T gamma, K, tau_eps, tau_C, mu, prandtl;
   int physics;
 };
 
+// One distribution term of Eq. (flux): a Maxwellian (vw-table, u-table uh for
+// the flux moments, u-table uf of its full space for the time derivative)
+// times [c_e + c_s (u a_n.psi + v a_t1.psi + w a_t2.psi) + c_A A.psi], where
+// A solves <a_n u + a_t1 v + a_t2 w + A> = 0.  Accumulates rho x the
+// flux moments (k = 1) into F, density moments (k = 0) into Ph (NS) and the
+// point-value moments with the second coefficient set into QG.
+template <typename T, bool NS, bool QG>
+HGKS_HD void term(const VWX<T>& M, const T uh[8], const T uf[8], T rho, T U, T V, T W, T lam, T K,
+                  const T an[5], const T at1[5], const T at2[5], T ce, T cs, T cA, T de, T ds, T dA, T F[5],
+                  T Ph[5], T Qg[5]) {
+  GSum<T> Ga;
+  {
+    T c[23];
+#pragma unroll
+    for (int m = 0; m < 23; ++m) c[m] = T(0);
+    add_slopes(c, an, at1, at2, T(1));
+    gsum(c, M, Ga);
+  }
+  T A[5];
+  {
+    T rhs[5] = {0, 0, 0, 0, 0};
+    gmom<0>(uf, Ga, T(-1), rhs);
+    micro_slope(rhs, U, V, W, lam, K, A);
+  }
+  if (QG) {
+    T c[23];
+#pragma unroll
+    for (int m = 0; m < 23; ++m) c[m] = T(0);
+    c[0] = de;
+    add_apsi(c, A, dA);
+    GSum<T> Gq;
+    gsum(c, M, Gq);
+    gaxpy(Gq, ds, Ga);
+    gmom<0>(uh, Gq, rho, Qg);
+  }
+  GSum<T> Gt;
+  {
+    T c[23];
+#pragma unroll
+    for (int m = 0; m < 23; ++m) c[m] = T(0);
+    c[0] = ce;
+    add_apsi(c, A, cA);
+    gsum(c, M, Gt);
+  }
+  gaxpy(Gt, cs, Ga);
+  gmom<1>(uh, Gt, rho, F);
+  if (NS) gmom<0>(uh, Gt, rho, Ph);
+}
+
+// <psi a.psi> over a u-table: the moment of a single expansion (k = 0)
+template <typename T>
+HGKS_HD void apsi_mom(const VWX<T>& M, const T u[8], const T a[5], T s, T out[5]) {
+  T c[23];
+#pragma unroll
+  for (int m = 0; m < 23; ++m) c[m] = T(0);
+  add_apsi(c, a, T(1));
+  GSum<T> G;
+  gsum(c, M, G);
+  gmom<0>(u, G, s, out);
+}
+
 // Time-averaged flux over [0, dt] (local frame) and, if want_qg, the point
 // value Q(x_G, t = dt) of Eq. (point).  W*: conserved local-frame states,
 // d*[3][5]: their derivatives along (n, t1, t2).
 template <typename T, bool want_qg>
-__host__ __device__ __forceinline__ void gks_flux(const T Wl[5], const T dWl[3][5], const T Wr[5],
-                                         const T dWr[3][5], T dt, const FluxParams<T>& P, T F[5],
-                                         T QG[5]) {
+HGKS_HD void gks_flux(const T Wl[5], const T dWl[3][5], const T Wr[5], const T dWr[3][5], T dt,
+                      const FluxParams<T>& P, T F[5], T QG[5]) {
   const T g = P.gamma, K = P.K;
   // primitive variables of both sides
   T rl = Wl[0], Ul = Wl[1] / rl, Vl = Wl[2] / rl, Wwl = Wl[3] / rl;
@@ -153,62 +283,38 @@ __host__ __device__ __forceinline__ void gks_flux(const T Wl[5], const T dWl[3][
   T rr = Wr[0], Ur = Wr[1] / rr, Vr = Wr[2] / rr, Wwr = Wr[3] / rr;
   T pr = (g - T(1)) * (Wr[4] - T(0.5) * rr * (Ur * Ur + Vr * Vr + Wwr * Wwr));
   T lr = rr / (T(2) * pr);
-
-  Mxw<T> Ml, Mr;  // half-space moments u>0 (left) and u<0 (right)
-  mxw_vw(Ml, Vl, Wwl, ll, K);
-  mxw_u(Ml, Ul, ll, +1);
-  mxw_vw(Mr, Vr, Wwr, lr, K);
-  mxw_u(Mr, Ur, lr, -1);
+  T ul0, ul1, ur0, ur1;  // half-space base moments: u > 0 left, u < 0 right
+  half_base(Ul, ll, +1, ul0, ul1);
+  half_base(Ur, lr, -1, ur0, ur1);
 
   // interface equilibrium Q0 from the compatibility condition
   T Q0[5] = {0, 0, 0, 0, 0};
-  psi5<0, 0, 0, 0>(Ml, rl, Q0);
-  psi5<0, 0, 0, 0>(Mr, rr, Q0);
+  {
+    VWX<T> M;
+    T u[8];
+    vwx_table(M, Vl, Wwl, ll, K);
+    u_table(u, Ul, ll, ul0, ul1);
+    Q0[0] += rl * u[0];
+    Q0[1] += rl * u[1];
+    Q0[2] += rl * u[0] * M.v[1];
+    Q0[3] += rl * u[0] * M.w[1];
+    Q0[4] += rl * T(0.5) * (u[2] + u[0] * (M.v[2] + M.w[2] + M.x2));
+    vwx_table(M, Vr, Wwr, lr, K);
+    u_table(u, Ur, lr, ur0, ur1);
+    Q0[0] += rr * u[0];
+    Q0[1] += rr * u[1];
+    Q0[2] += rr * u[0] * M.v[1];
+    Q0[3] += rr * u[0] * M.w[1];
+    Q0[4] += rr * T(0.5) * (u[2] + u[0] * (M.v[2] + M.w[2] + M.x2));
+  }
   T r0 = Q0[0], U0 = Q0[1] / r0, V0 = Q0[2] / r0, W0 = Q0[3] / r0;
   T p0 = (g - T(1)) * (Q0[4] - T(0.5) * r0 * (U0 * U0 + V0 * V0 + W0 * W0));
   T l0 = r0 / (T(2) * p0);
 
-  // slopes of the initial distributions and kinetic-weighted equilibrium slopes
-  T al[3][5], ar[3][5], ab[3][5];
-  {
-    T il = T(1) / rl, ir = T(1) / rr, i0 = T(1) / r0;
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      T bl[5], br[5];
-#pragma unroll
-      for (int k = 0; k < 5; ++k) {
-        bl[k] = dWl[d][k] * il;
-        br[k] = dWr[d][k] * ir;
-      }
-      micro_slope(bl, Ul, Vl, Wwl, ll, K, al[d]);
-      micro_slope(br, Ur, Vr, Wwr, lr, K, ar[d]);
-      T dq0[5] = {0, 0, 0, 0, 0};
-      apsi<0, 0, 0>(Ml, al[d], rl, dq0);
-      apsi<0, 0, 0>(Mr, ar[d], rr, dq0);
-#pragma unroll
-      for (int k = 0; k < 5; ++k) dq0[k] *= i0;
-      micro_slope(dq0, U0, V0, W0, l0, K, ab[d]);
-    }
-  }
-  // time derivatives (full-space moments of each Maxwellian)
-  Mxw<T> M0;
-  mxw_vw(M0, V0, W0, l0, K);
-  mxw_u(M0, U0, l0, 0);
-  T Ab[5], Al[5], Ar[5];
-  time_slope(M0, ab[0], ab[1], ab[2], U0, V0, W0, l0, K, Ab);
-  {
-    Mxw<T> Mf;
-    mxw_vw(Mf, Vl, Wwl, ll, K);
-    mxw_u(Mf, Ul, ll, 0);
-    time_slope(Mf, al[0], al[1], al[2], Ul, Vl, Wwl, ll, K, Al);
-    mxw_vw(Mf, Vr, Wwr, lr, K);
-    mxw_u(Mf, Ur, lr, 0);
-    time_slope(Mf, ar[0], ar[1], ar[2], Ur, Vr, Wwr, lr, K, Ar);
-  }
-  // collision time (Sec. 5)
+  // collision time (Sec. 5) and the time coefficients of Eq. (flux),
+  // integrated over [0, dt] and divided by dt
   T jump = fabs((pl - pr) / (pl + pr));
   T tau = P.physics ? P.mu / p0 + P.tau_C * jump * dt : (P.tau_eps + P.tau_C * jump) * dt;
-  // time integrals of the coefficients of Eq. (flux), divided by dt
   T x = dt / tau;
   T e = exp(-x);
   T em1 = -expm1(-x);
@@ -219,32 +325,107 @@ __host__ __device__ __forceinline__ void gks_flux(const T Wl[5], const T dWl[3][
   T c4 = tau * em1 * idt;
   T c5 = (-T(2) * tau * tau * em1 + tau * dt * e) * idt;
   T c6 = (-tau * tau * em1) * idt;
+  // coefficients at t = dt for the point value (HWENO)
+  T d1 = em1, d2 = (dt + tau) * e - tau, d3 = dt - tau + tau * e;
+  T d4 = e, d5 = -(tau + dt) * e, d6 = -tau * e;
+
+  // slopes of the initial distributions in the directions (n, t1, t2) and
+  // the kinetic-weighted derivatives of Q0
+  T al[3][5], ar[3][5], ab[3][5];
+  {
+    T il = T(1) / rl, ir = T(1) / rr;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      T bl[5], br[5];
+#pragma unroll
+      for (int k = 0; k < 5; ++k) {
+        bl[k] = dWl[d][k] * il;
+        br[k] = dWr[d][k] * ir;
+      }
+      micro_slope(bl, Ul, Vl, Wwl, ll, K, al[d]);
+      micro_slope(br, Ur, Vr, Wwr, lr, K, ar[d]);
+    }
+  }
+  {
+    T dq[3][5];
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+#pragma unroll
+      for (int k = 0; k < 5; ++k) dq[d][k] = T(0);
+    VWX<T> M;
+    T u[8];
+    vwx_table(M, Vl, Wwl, ll, K);
+    u_table(u, Ul, ll, ul0, ul1);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) apsi_mom(M, u, al[d], rl, dq[d]);
+    vwx_table(M, Vr, Wwr, lr, K);
+    u_table(u, Ur, lr, ur0, ur1);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) apsi_mom(M, u, ar[d], rr, dq[d]);
+    T i0 = T(1) / r0;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+#pragma unroll
+      for (int k = 0; k < 5; ++k) dq[d][k] *= i0;
+      micro_slope(dq[d], U0, V0, W0, l0, K, ab[d]);
+    }
+  }
 #pragma unroll
   for (int k = 0; k < 5; ++k) F[k] = T(0);
-  term_moments<1>(M0, r0, c1, c2, c3, ab[0], ab[1], ab[2], Ab, F);
-  term_moments<1>(Ml, rl, c4, c5, c6, al[0], al[1], al[2], Al, F);
-  term_moments<1>(Mr, rr, c4, c5, c6, ar[0], ar[1], ar[2], Ar, F);
+  T Ph[5] = {0, 0, 0, 0, 0};
+  T Qg[5] = {0, 0, 0, 0, 0};
+  // initial-distribution terms: half-space moments of g_l (u > 0), g_r (u < 0)
+  // (first, so that their slopes are dead before the equilibrium term)
+  {
+    VWX<T> M;
+    T uh[8], uf[8];
+    vwx_table(M, Vl, Wwl, ll, K);
+    u_table(uh, Ul, ll, ul0, ul1);
+    u_table(uf, Ul, ll, T(1), Ul);
+    if (P.physics)
+      term<T, true, want_qg>(M, uh, uf, rl, Ul, Vl, Wwl, ll, K, al[0], al[1], al[2], c4, c5, c6, d4, d5, d6, F, Ph,
+                             Qg);
+    else
+      term<T, false, want_qg>(M, uh, uf, rl, Ul, Vl, Wwl, ll, K, al[0], al[1], al[2], c4, c5, c6, d4, d5, d6, F, Ph,
+                              Qg);
+  }
+  {
+    VWX<T> M;
+    T uh[8], uf[8];
+    vwx_table(M, Vr, Wwr, lr, K);
+    u_table(uh, Ur, lr, ur0, ur1);
+    u_table(uf, Ur, lr, T(1), Ur);
+    if (P.physics)
+      term<T, true, want_qg>(M, uh, uf, rr, Ur, Vr, Wwr, lr, K, ar[0], ar[1], ar[2], c4, c5, c6, d4, d5, d6, F, Ph,
+                             Qg);
+    else
+      term<T, false, want_qg>(M, uh, uf, rr, Ur, Vr, Wwr, lr, K, ar[0], ar[1], ar[2], c4, c5, c6, d4, d5, d6, F, Ph,
+                              Qg);
+  }
+  // equilibrium term: full-space moments of g0
+  {
+    VWX<T> M;
+    T u[8];
+    vwx_table(M, V0, W0, l0, K);
+    u_table(u, U0, l0, T(1), U0);
+    if (P.physics)
+      term<T, true, want_qg>(M, u, u, r0, U0, V0, W0, l0, K, ab[0], ab[1], ab[2], c1, c2, c3, d1, d2, d3, F, Ph, Qg);
+    else
+      term<T, false, want_qg>(M, u, u, r0, U0, V0, W0, l0, K, ab[0], ab[1], ab[2], c1, c2, c3, d1, d2, d3, F, Ph,
+                              Qg);
+  }
   if (P.physics) {
     // heat flux relative to U0 carried by the time-averaged f, rescaled to Pr
-    T Ph[5] = {0, 0, 0, 0, 0};
-    term_moments<0>(M0, r0, c1, c2, c3, ab[0], ab[1], ab[2], Ab, Ph);
-    term_moments<0>(Ml, rl, c4, c5, c6, al[0], al[1], al[2], Al, Ph);
-    term_moments<0>(Mr, rr, c4, c5, c6, ar[0], ar[1], ar[2], Ar, Ph);
     T u2 = U0 * U0 + V0 * V0 + W0 * W0;
     T q = F[4] - (F[1] * U0 + F[2] * V0 + F[3] * W0) + T(0.5) * u2 * F[0] -
           U0 * (Ph[4] - (Ph[1] * U0 + Ph[2] * V0 + Ph[3] * W0) + T(0.5) * u2 * Ph[0]);
     F[4] += (T(1) / P.prandtl - T(1)) * q;
   }
-  if (want_qg) {
-    T t = dt;
-    T d1 = em1, d2 = (t + tau) * e - tau, d3 = t - tau + tau * e;
-    T d4 = e, d5 = -(tau + t) * e, d6 = -tau * e;
+  if (want_qg)
 #pragma unroll
-    for (int k = 0; k < 5; ++k) QG[k] = T(0);
-    term_moments<0>(M0, r0, d1, d2, d3, ab[0], ab[1], ab[2], Ab, QG);
-    term_moments<0>(Ml, rl, d4, d5, d6, al[0], al[1], al[2], Al, QG);
-    term_moments<0>(Mr, rr, d4, d5, d6, ar[0], ar[1], ar[2], Ar, QG);
-  }
+    for (int k = 0; k < 5; ++k) QG[k] = Qg[k];
 }
+
+#undef HGKS_HD
 
 }  // namespace hgks

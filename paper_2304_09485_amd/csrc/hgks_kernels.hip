@@ -434,37 +434,34 @@ __device__ void boundary_right(int kind, const T Wl[5], const T dWl[3][5], const
     for (int k = 0; k < 5; ++k) dWr[d][k] = T(0);
 }
 
+// one lane per Gauss point: 21 faces per 64-lane block, the three Gauss-point
+// fluxes of a face are summed through LDS by the face's first lane
+constexpr int FLUX_FPB = 21;
+
 template <typename T, bool QG>
 __global__ void __launch_bounds__(64) k_flux(DevMesh<T> M, Params P, const T* __restrict__ sv,
                                              const T* __restrict__ dt, T* __restrict__ ff,
                                              T* __restrict__ fq) {
-  int f = blockIdx.x * blockDim.x + threadIdx.x;
+  __shared__ T red[QG ? 10 : 5][64];
   const int F = M.F, N = M.N;
-  if (f >= F) return;
-  int L = M.fL[f], R = M.fR[f];
-  bool bnd = R >= N;
-  T dtf = bnd ? dt[L] : fmin(dt[L], dt[R]);
-  T n[3] = {M.fn[f], M.fn[F + f], M.fn[2 * F + f]}, t1[3], t2[3];
-  face_frame(n[0], n[1], n[2], t1, t2);
-  int kind = M.fkind[f];
-  FluxParams<T> fp;
-  fp.gamma = T(P.gamma);
-  fp.K = T(P.K);
-  fp.tau_eps = T(P.tau_eps);
-  fp.tau_C = T(P.tau_C);
-  fp.mu = T(P.mu);
-  fp.prandtl = T(P.prandtl);
-  fp.physics = P.physics;
-  T ul[3];
-  {
-    T ui[3] = {T(P.uinf0), T(P.uinf1), T(P.uinf2)};
-    ul[0] = ui[0] * n[0] + ui[1] * n[1] + ui[2] * n[2];
-    ul[1] = ui[0] * t1[0] + ui[1] * t1[1] + ui[2] * t1[2];
-    ul[2] = ui[0] * t2[0] + ui[1] * t2[1] + ui[2] * t2[2];
-  }
-  const size_t ld = 2 * (size_t)F;
-  T Fs[5] = {0, 0, 0, 0, 0}, Qs[5] = {0, 0, 0, 0, 0};
-  for (int gp = 0; gp < 3; ++gp) {
+  const int lane = threadIdx.x;
+  const int f = blockIdx.x * FLUX_FPB + lane / 3;
+  const int gp = lane % 3;
+  const bool active = lane < 3 * FLUX_FPB && f < F;
+  T Fg[5] = {0, 0, 0, 0, 0}, Qg[5] = {0, 0, 0, 0, 0};
+  if (active) {
+    int L = M.fL[f], R = M.fR[f];
+    bool bnd = R >= N;
+    T dtf = bnd ? dt[L] : fmin(dt[L], dt[R]);
+    FluxParams<T> fp;
+    fp.gamma = T(P.gamma);
+    fp.K = T(P.K);
+    fp.tau_eps = T(P.tau_eps);
+    fp.tau_C = T(P.tau_C);
+    fp.mu = T(P.mu);
+    fp.prandtl = T(P.prandtl);
+    fp.physics = P.physics;
+    const size_t ld = 2 * (size_t)F;
     T Wl[5], dWl[3][5], Wr[5], dWr[3][5];
 #pragma unroll
     for (int v = 0; v < 5; ++v) {
@@ -473,7 +470,12 @@ __global__ void __launch_bounds__(64) k_flux(DevMesh<T> M, Params P, const T* __
       for (int d = 0; d < 3; ++d) dWl[d][v] = sv[(size_t)((gp * 4 + 1 + d) * 5 + v) * ld + f];
     }
     if (bnd) {
-      boundary_right(kind, Wl, dWl, ul, T(P.rhoinf), T(P.pinf), fp.gamma, Wr, dWr);
+      T n[3] = {M.fn[f], M.fn[F + f], M.fn[2 * F + f]}, t1[3], t2[3];
+      face_frame(n[0], n[1], n[2], t1, t2);
+      T ui[3] = {T(P.uinf0), T(P.uinf1), T(P.uinf2)};
+      T ul[3] = {ui[0] * n[0] + ui[1] * n[1] + ui[2] * n[2], ui[0] * t1[0] + ui[1] * t1[1] + ui[2] * t1[2],
+                 ui[0] * t2[0] + ui[1] * t2[1] + ui[2] * t2[2]};
+      boundary_right(M.fkind[f], Wl, dWl, ul, T(P.rhoinf), T(P.pinf), fp.gamma, Wr, dWr);
     } else {
 #pragma unroll
       for (int v = 0; v < 5; ++v) {
@@ -482,15 +484,24 @@ __global__ void __launch_bounds__(64) k_flux(DevMesh<T> M, Params P, const T* __
         for (int d = 0; d < 3; ++d) dWr[d][v] = sv[(size_t)((gp * 4 + 1 + d) * 5 + v) * ld + F + f];
       }
     }
-    T Fg[5], Qg[5];
     gks_flux<T, QG>(Wl, dWl, Wr, dWr, dtf, fp, Fg, Qg);
-#pragma unroll
-    for (int v = 0; v < 5; ++v) Fs[v] += Fg[v] / T(3);
-    if (QG) {
-#pragma unroll
-      for (int v = 0; v < 5; ++v) Qs[v] += Qg[v] / T(3);
-    }
   }
+#pragma unroll
+  for (int v = 0; v < 5; ++v) red[v][lane] = Fg[v];
+  if (QG)
+#pragma unroll
+    for (int v = 0; v < 5; ++v) red[5 + v][lane] = Qg[v];
+  __syncthreads();
+  if (!active || gp != 0) return;
+  // quadrature with weights 1/3
+  T Fs[5], Qs[5];
+#pragma unroll
+  for (int v = 0; v < 5; ++v) {
+    Fs[v] = (red[v][lane] / T(3) + red[v][lane + 1] / T(3)) + red[v][lane + 2] / T(3);
+    if (QG) Qs[v] = (red[5 + v][lane] / T(3) + red[5 + v][lane + 1] / T(3)) + red[5 + v][lane + 2] / T(3);
+  }
+  T n[3] = {M.fn[f], M.fn[F + f], M.fn[2 * F + f]}, t1[3], t2[3];
+  face_frame(n[0], n[1], n[2], t1, t2);
   T S = M.fS[f];
   ff[f] = S * Fs[0];
   ff[4 * (size_t)F + f] = S * Fs[4];
@@ -804,10 +815,11 @@ void launch_side(const DevMesh<T>& M, const Params& P, const T* Qx, const T* coe
 template <typename T>
 void launch_flux(const DevMesh<T>& M, const Params& P, const T* sv, const T* dt, T* ff, T* fq, bool qg,
                  hipStream_t s) {
+  dim3 grid(nblk(M.F, FLUX_FPB));
   if (qg)
-    hipLaunchKernelGGL((k_flux<T, true>), dim3(nblk(M.F, 64)), dim3(64), 0, s, M, P, sv, dt, ff, fq);
+    hipLaunchKernelGGL((k_flux<T, true>), grid, dim3(64), 0, s, M, P, sv, dt, ff, fq);
   else
-    hipLaunchKernelGGL((k_flux<T, false>), dim3(nblk(M.F, 64)), dim3(64), 0, s, M, P, sv, dt, ff, fq);
+    hipLaunchKernelGGL((k_flux<T, false>), grid, dim3(64), 0, s, M, P, sv, dt, ff, fq);
 }
 template <typename T, typename TO>
 void launch_gather(const DevMesh<T>& M, int mode, const T* ff, const T* fq, TO* out, const TO* v, const TO* b,
