@@ -67,6 +67,8 @@ typedef struct {
   double mu;             /* dynamic viscosity (NS) */
   double prandtl;        /* Prandtl number (NS), 1 = plain BGK */
   double fd_sigma;       /* FD step of Eq. (frechet); 0 = sqrt(eps) max(1,rms Q)/rms v */
+  double cfl_flux;       /* CFL number of the time interval the flux is averaged over
+                            (Sec. 4.1); default 1; 0 = the implicit step's cfl */
   void* stream;          /* hipStream_t to run on; NULL = library-owned stream */
 } hgks_options;
 

@@ -54,7 +54,7 @@ class Options(ctypes.Structure):
                 ("jacobi_sweeps", ctypes.c_int32), ("gamma", ctypes.c_double), ("cfl", ctypes.c_double),
                 ("tau_eps", ctypes.c_double), ("tau_C", ctypes.c_double), ("gamma_lin", ctypes.c_double),
                 ("weno_eps", ctypes.c_double), ("mu", ctypes.c_double), ("prandtl", ctypes.c_double),
-                ("fd_sigma", ctypes.c_double)]
+                ("fd_sigma", ctypes.c_double), ("cfl_flux", ctypes.c_double)]
 
 
 class StepInfo(ctypes.Structure):
@@ -115,7 +115,7 @@ def _f64(a):
 def default_options(**kw) -> Options:
     o = Options(scheme=WENO, physics=EULER, weights=0, krylov_dim=10, restarts=3, jacobi_sweeps=2,
                 gamma=1.4, cfl=10.0, tau_eps=0.1, tau_C=1.0, gamma_lin=0.025, weno_eps=1e-8,
-                mu=0.0, prandtl=1.0, fd_sigma=0.0)
+                mu=0.0, prandtl=1.0, fd_sigma=0.0, cfl_flux=1.0)
     for k, v in kw.items():
         setattr(o, k, v)
     return o

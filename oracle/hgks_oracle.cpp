@@ -882,9 +882,11 @@ static void gks_point(const orc_ctx& C, const V5& Wl, const V5 dWl[3], const V5&
     F[4] += (1.0 / C.o.prandtl - 1.0) * q;
   }
   if (QG) {
-    // point value of Eq. (point) at t = dt (reading A15)
-    double t = dt;
-    double c[6] = {em1, (t + tau) * e - tau, t - tau + tau * e, e, -(tau + t) * e, -tau * e};
+    // point value of Eq. (point) at t^n, the start of the local time
+    // interval, as in the gradient update formula of Sec. 4.2 (reading A15')
+    double t = 0.0;
+    double et = std::exp(-t / tau), em1t = -std::expm1(-t / tau);
+    double c[6] = {em1t, (t + tau) * et - tau, t - tau + tau * et, et, -(tau + t) * et, -tau * et};
     *QG = fmoment(0, c);
   }
 }
@@ -932,6 +934,9 @@ static int face_flux(const orc_ctx& C, const double* Q, const double* G, const d
   bool bnd = f.R < 0;
   if (!bnd) fb += side_values(C, Q, G, fidx, 1, sr);
   double dtf = bnd ? dt[f.L] : std::min(dt[f.L], dt[f.R]);
+  // time interval of the flux average (reading A18'): the local time step at
+  // CFL number cfl_flux; the implicit diagonal keeps the step at cfl
+  if (C.o.cfl_flux > 0.0) dtf *= C.o.cfl_flux / C.o.cfl;
   V5 Fsum{0, 0, 0, 0, 0}, Qsum{0, 0, 0, 0, 0};
   for (int g = 0; g < 3; ++g) {
     V5 Wl, Wr, dWl[3], dWr[3];

@@ -37,6 +37,7 @@ typedef struct {
   double mu;             /* dynamic viscosity (NS) */
   double prandtl;        /* NS */
   double fd_sigma;       /* 0 = automatic */
+  double cfl_flux;       /* CFL of the flux time average; 0 = same as cfl */
 } orc_options;
 
 /* boundary kinds */

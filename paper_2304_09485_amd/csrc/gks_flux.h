@@ -325,9 +325,10 @@ HGKS_HD void gks_flux(const T Wl[5], const T dWl[3][5], const T Wr[5], const T d
   T c4 = tau * em1 * idt;
   T c5 = (-T(2) * tau * tau * em1 + tau * dt * e) * idt;
   T c6 = (-tau * tau * em1) * idt;
-  // coefficients at t = dt for the point value (HWENO)
-  T d1 = em1, d2 = (dt + tau) * e - tau, d3 = dt - tau + tau * e;
-  T d4 = e, d5 = -(tau + dt) * e, d6 = -tau * e;
+  // coefficients of Eq. (flux) at t^n (local t = 0) for the point value of
+  // the gradient update (Sec. 4.2): the equilibrium terms vanish there
+  T d1 = T(0), d2 = T(0), d3 = T(0);
+  T d4 = T(1), d5 = -tau, d6 = -tau;
 
   // slopes of the initial distributions in the directions (n, t1, t2) and
   // the kinetic-weighted derivatives of Q0
@@ -408,11 +409,11 @@ HGKS_HD void gks_flux(const T Wl[5], const T dWl[3][5], const T Wr[5], const T d
     T u[8];
     vwx_table(M, V0, W0, l0, K);
     u_table(u, U0, l0, T(1), U0);
+    // (no point-value contribution: its coefficients d1..d3 vanish at t^n)
     if (P.physics)
-      term<T, true, want_qg>(M, u, u, r0, U0, V0, W0, l0, K, ab[0], ab[1], ab[2], c1, c2, c3, d1, d2, d3, F, Ph, Qg);
+      term<T, true, false>(M, u, u, r0, U0, V0, W0, l0, K, ab[0], ab[1], ab[2], c1, c2, c3, d1, d2, d3, F, Ph, Qg);
     else
-      term<T, false, want_qg>(M, u, u, r0, U0, V0, W0, l0, K, ab[0], ab[1], ab[2], c1, c2, c3, d1, d2, d3, F, Ph,
-                              Qg);
+      term<T, false, false>(M, u, u, r0, U0, V0, W0, l0, K, ab[0], ab[1], ab[2], c1, c2, c3, d1, d2, d3, F, Ph, Qg);
   }
   if (P.physics) {
     // heat flux relative to U0 carried by the time-averaged f, rescaled to Pr

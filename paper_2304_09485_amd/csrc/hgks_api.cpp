@@ -149,6 +149,7 @@ void set_params(hgks_ctx* ctx) {
   P.weno_eps = o.weno_eps;
   P.mu = o.mu;
   P.prandtl = o.prandtl;
+  P.flux_scale = o.cfl_flux > 0.0 ? o.cfl_flux / o.cfl : 1.0;
   P.rhoinf = ctx->prim_inf[0];
   P.uinf0 = ctx->prim_inf[1];
   P.uinf1 = ctx->prim_inf[2];
@@ -409,6 +410,7 @@ void hgks_default_options(hgks_options* o) {
   o->mu = 0.0;
   o->prandtl = 1.0;
   o->fd_sigma = 0.0;
+  o->cfl_flux = 1.0;
   o->stream = nullptr;
 }
 

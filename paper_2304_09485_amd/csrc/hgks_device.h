@@ -42,6 +42,7 @@ struct DevMesh {
 
 struct Params {
   double gamma, K, tau_eps, tau_C, gamma_lin, weno_eps, mu, prandtl;
+  double flux_scale;  // time interval of the flux average / implicit time step
   double rhoinf, uinf0, uinf1, uinf2, pinf;
   int physics, weights, scheme, pad;
 };

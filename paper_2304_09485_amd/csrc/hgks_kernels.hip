@@ -452,7 +452,8 @@ __global__ void __launch_bounds__(64) k_flux(DevMesh<T> M, Params P, const T* __
   if (active) {
     int L = M.fL[f], R = M.fR[f];
     bool bnd = R >= N;
-    T dtf = bnd ? dt[L] : fmin(dt[L], dt[R]);
+    // the flux is averaged over the local time step at CFL cfl_flux
+    T dtf = (bnd ? dt[L] : fmin(dt[L], dt[R])) * T(P.flux_scale);
     FluxParams<T> fp;
     fp.gamma = T(P.gamma);
     fp.K = T(P.K);

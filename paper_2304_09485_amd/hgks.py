@@ -43,7 +43,7 @@ class Options(ctypes.Structure):
                 ("gamma", ctypes.c_double), ("cfl", ctypes.c_double), ("tau_eps", ctypes.c_double),
                 ("tau_C", ctypes.c_double), ("gamma_lin", ctypes.c_double), ("weno_eps", ctypes.c_double),
                 ("mu", ctypes.c_double), ("prandtl", ctypes.c_double), ("fd_sigma", ctypes.c_double),
-                ("stream", ctypes.c_void_p)]
+                ("cfl_flux", ctypes.c_double), ("stream", ctypes.c_void_p)]
 
 
 class StepInfo(ctypes.Structure):
@@ -68,6 +68,12 @@ def load_library():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} not built: run `python -m paper_2304_09485_amd.build`")
+    # bind the process to PyTorch's HIP runtime first, so that the library and
+    # torch tensors share one runtime (same soname, libamdhip64.so.7)
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     L = ctypes.CDLL(LIB_PATH)
     vp, i32, i64, d = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
     sig = {

@@ -11,7 +11,7 @@ transposed operand, a wrong half-space limit) fails one of them:
     evaluated by quadrature, and the same equals the Chapman-Enskog
     Navier-Stokes flux with mu = tau p, Pr = 1 (textbook closed form);
   * Prandtl fix in the dt -> 0 limit: heat flux scaled by 1/Pr;
-  * point value Q_G(t) = Q + t Q_t for continuous data;
+  * point value Q_G at t^n equals the state for continuous data;
   * mirror antisymmetry and invariance under rotating (t1, t2) about n.
 """
 import numpy as np
@@ -149,7 +149,8 @@ def _continuous_reference(W, dW, tau, dt):
     A = np.linalg.solve(M, -q.E(au))
     Ap = q.poly(A)
     F = rho * (q.E(q.u) - tau * q.E(q.u * (au + Ap)) + 0.5 * dt * q.E(q.u * Ap))
-    QG = rho * (q.E(1.0) - tau * q.E(au + Ap) + (dt - tau) * 0 + dt * q.E(Ap))
+    # point value of Eq. (point) at t^n (local t = 0): f = g [1 - tau (a.u + A)]
+    QG = rho * (q.E(1.0) - tau * q.E(au + Ap))
     return F, QG
 
 
@@ -182,8 +183,9 @@ def test_continuous_flux_vs_quadrature_and_navier_stokes(orc, seed):
     np.testing.assert_allclose(QG, QGq, rtol=1e-9, atol=1e-11)
     Fns, Qt = _ns_closed_form(W, dW, tau * I.prim(W)[2], dt)
     np.testing.assert_allclose(F, Fns, rtol=1e-9, atol=1e-11)
-    # Eq. (point) for continuous data: Q(x_G, dt) = Q + dt Q_t
-    np.testing.assert_allclose(QG, W + dt * Qt, rtol=1e-9, atol=1e-11)
+    # Eq. (point) for continuous data at t^n: the compatibility condition
+    # <psi (a.u + A)> = 0 makes the point value the state itself
+    np.testing.assert_allclose(QG, W, rtol=1e-9, atol=1e-11)
 
 
 def test_euler_limit(orc):
