@@ -162,6 +162,69 @@ hgks_status hgks_kernel_times(hgks_ctx* ctx, const char** names, double* ms, int
 const char* hgks_last_error(const hgks_ctx* ctx);
 void hgks_destroy(hgks_ctx* ctx);
 
+/* ---------------------------------------------------------------------------
+ * Serving: continuous batching of steady solves (Algorithm 1 run to a residual
+ * drop) on one GPU.  Requests are queued on submission and admitted, in
+ * arrival order with smaller requests allowed to pass a waiting large one, as
+ * soon as a slot is free and their estimated device footprint fits the HBM
+ * budget.  Every admitted request owns a context (mesh data, state, Krylov
+ * basis resident in HBM) and a HIP stream driven by its own host thread, so
+ * the work of concurrent requests overlaps on the device.  Results of a
+ * request do not depend on what else runs (no shared mutable device state,
+ * deterministic kernels and reductions).  All server calls are thread-safe.
+ * ------------------------------------------------------------------------- */
+typedef struct hgks_server hgks_server;
+
+typedef struct {
+  int64_t n_nodes;
+  const double* xyz;        /* [n_nodes][3] */
+  int64_t n_tets;
+  const int32_t* tet2node;  /* [n_tets][4] */
+  int64_t n_bfaces;
+  const int32_t* bface2node;/* [n_bfaces][3] */
+  const int32_t* bface_tag; /* [n_bfaces] */
+  int32_t n_bc;             /* boundary kinds per tag */
+  const int32_t* bc_tag;
+  const int32_t* bc_kind;
+  double prim_inf[5];       /* free stream (rho, U, V, W, p); also the initial state */
+  hgks_options opts;        /* scheme, physics, precision, ...; stream is ignored */
+  double drop;              /* target res/res0, e.g. 1e-8 */
+  int32_t max_steps;
+} hgks_request;             /* all arrays are copied by hgks_server_submit */
+
+typedef struct {
+  int32_t status;           /* hgks_status of the solve (HGKS_ENOCONV if max_steps hit) */
+  int32_t steps;
+  double res0, res_final;
+  int64_t n_cells;
+  int64_t n_resid_evals;
+  double t_queue_ms;        /* submission -> admission */
+  double t_solve_ms;        /* admission -> result (includes mesh preprocessing) */
+  double t_total_ms;        /* submission -> result */
+  size_t footprint_bytes;   /* estimate used for admission */
+} hgks_result;
+
+typedef struct {
+  int32_t queued, active, done;
+  size_t bytes_in_use, budget;
+  int64_t cell_resid_evals; /* sum over finished requests of cells x residual evaluations */
+} hgks_server_info;
+
+/* Device bytes a request of this size needs (the admission estimate). */
+size_t hgks_estimate_bytes(int64_t n_tets, int64_t n_bfaces, const hgks_options* opts);
+
+hgks_status hgks_server_create(size_t hbm_budget_bytes, int32_t max_slots, hgks_server** out);
+hgks_status hgks_server_submit(hgks_server* srv, const hgks_request* req, int64_t* ticket);
+/* *done = 1 and *out filled when the request has finished */
+hgks_status hgks_server_poll(hgks_server* srv, int64_t ticket, int32_t* done, hgks_result* out);
+hgks_status hgks_server_wait(hgks_server* srv, int64_t ticket, hgks_result* out);
+/* final state [5][n_tets] of a finished request (host memory of the caller) */
+hgks_status hgks_server_get_state(hgks_server* srv, int64_t ticket, double* Q);
+hgks_status hgks_server_release(hgks_server* srv, int64_t ticket);
+hgks_status hgks_server_stats(hgks_server* srv, hgks_server_info* out);
+/* waits for active requests, drops queued ones */
+void hgks_server_destroy(hgks_server* srv);
+
 #ifdef __cplusplus
 }
 #endif

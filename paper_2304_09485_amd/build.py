@@ -29,7 +29,8 @@ def _run(cmd):
 def build(verbose: bool = True) -> str:
     os.makedirs(BUILD, exist_ok=True)
     objs = []
-    for src, kind in (("hgks_kernels.hip", "hip"), ("hgks_api.cpp", "hip"), ("mesh_prep.cpp", "cxx")):
+    for src, kind in (("hgks_kernels.hip", "hip"), ("hgks_api.cpp", "hip"), ("hgks_server.cpp", "hip"),
+                      ("mesh_prep.cpp", "cxx")):
         obj = os.path.join(BUILD, src + ".o")
         path = os.path.join(CSRC, src)
         if kind == "hip":

@@ -27,7 +27,9 @@ STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EMESH", -4: "ESTATE", -5: "E
 SYMBOLS = ["hgks_default_options", "hgks_create", "hgks_load_mesh", "hgks_set_freestream", "hgks_set_bc",
            "hgks_set_state", "hgks_get_state", "hgks_residual", "hgks_time_step", "hgks_jv", "hgks_precond",
            "hgks_implicit_step", "hgks_solve_steady", "hgks_residual_dev", "hgks_jv_dev", "hgks_n_cells",
-           "hgks_n_faces", "hgks_kernel_times", "hgks_last_error", "hgks_destroy"]
+           "hgks_n_faces", "hgks_kernel_times", "hgks_last_error", "hgks_destroy", "hgks_estimate_bytes",
+           "hgks_server_create", "hgks_server_submit", "hgks_server_poll", "hgks_server_wait",
+           "hgks_server_get_state", "hgks_server_release", "hgks_server_stats", "hgks_server_destroy"]
 
 
 class HgksError(RuntimeError):
@@ -55,6 +57,27 @@ class SolveInfo(ctypes.Structure):
     _fields_ = [("steps", ctypes.c_int32), ("converged", ctypes.c_int32), ("res0", ctypes.c_double),
                 ("res_final", ctypes.c_double), ("drop", ctypes.c_double), ("n_resid_evals", ctypes.c_int64),
                 ("t_ms", ctypes.c_double)]
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("n_nodes", ctypes.c_int64), ("xyz", ctypes.c_void_p), ("n_tets", ctypes.c_int64),
+                ("tet2node", ctypes.c_void_p), ("n_bfaces", ctypes.c_int64), ("bface2node", ctypes.c_void_p),
+                ("bface_tag", ctypes.c_void_p), ("n_bc", ctypes.c_int32), ("bc_tag", ctypes.c_void_p),
+                ("bc_kind", ctypes.c_void_p), ("prim_inf", ctypes.c_double * 5), ("opts", Options),
+                ("drop", ctypes.c_double), ("max_steps", ctypes.c_int32)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("steps", ctypes.c_int32), ("res0", ctypes.c_double),
+                ("res_final", ctypes.c_double), ("n_cells", ctypes.c_int64), ("n_resid_evals", ctypes.c_int64),
+                ("t_queue_ms", ctypes.c_double), ("t_solve_ms", ctypes.c_double), ("t_total_ms", ctypes.c_double),
+                ("footprint_bytes", ctypes.c_size_t)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("queued", ctypes.c_int32), ("active", ctypes.c_int32), ("done", ctypes.c_int32),
+                ("bytes_in_use", ctypes.c_size_t), ("budget", ctypes.c_size_t),
+                ("cell_resid_evals", ctypes.c_int64)]
 
 
 _lib = None
@@ -97,6 +120,15 @@ def load_library():
         "hgks_kernel_times": (i32, [vp, vp, vp, ctypes.POINTER(i32), i32]),
         "hgks_last_error": (ctypes.c_char_p, [vp]),
         "hgks_destroy": (None, [vp]),
+        "hgks_estimate_bytes": (ctypes.c_size_t, [i64, i64, ctypes.POINTER(Options)]),
+        "hgks_server_create": (i32, [ctypes.c_size_t, i32, ctypes.POINTER(vp)]),
+        "hgks_server_submit": (i32, [vp, ctypes.POINTER(Request), ctypes.POINTER(i64)]),
+        "hgks_server_poll": (i32, [vp, i64, ctypes.POINTER(i32), ctypes.POINTER(Result)]),
+        "hgks_server_wait": (i32, [vp, i64, ctypes.POINTER(Result)]),
+        "hgks_server_get_state": (i32, [vp, i64, vp]),
+        "hgks_server_release": (i32, [vp, i64]),
+        "hgks_server_stats": (i32, [vp, ctypes.POINTER(ServerStats)]),
+        "hgks_server_destroy": (None, [vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -227,3 +259,81 @@ class Solver:
         n = ctypes.c_int32()
         self._check(self._L.hgks_kernel_times(self.h, names, ms, ctypes.byref(n), 8))
         return {names[k].decode(): ms[k] for k in range(n.value)}
+
+
+def estimate_bytes(n_tets, n_bfaces, **opts):
+    return int(load_library().hgks_estimate_bytes(int(n_tets), int(n_bfaces), ctypes.byref(default_options(**opts))))
+
+
+class Server:
+    """Continuous-batching server of steady solves (see include/hgks.h)."""
+
+    def __init__(self, hbm_budget_bytes, max_slots):
+        self._L = load_library()
+        h = ctypes.c_void_p()
+        st = self._L.hgks_server_create(int(hbm_budget_bytes), int(max_slots), ctypes.byref(h))
+        if st != 0:
+            raise HgksError(st, "server create failed")
+        self.h = h
+        self._keep = {}
+
+    def submit(self, mesh, kinds: dict, prim, drop=1e-8, max_steps=1000, **opts):
+        xyz, tets, bf, bt = mesh.arrays()
+        tags = np.array(sorted(kinds), dtype=np.int32)
+        knd = np.array([kinds[t] for t in sorted(kinds)], dtype=np.int32)
+        r = Request()
+        r.n_nodes, r.xyz, r.n_tets, r.tet2node = len(xyz), xyz.ctypes.data, len(tets), tets.ctypes.data
+        r.n_bfaces, r.bface2node, r.bface_tag = len(bf), bf.ctypes.data, bt.ctypes.data
+        r.n_bc, r.bc_tag, r.bc_kind = len(tags), tags.ctypes.data, knd.ctypes.data
+        for k in range(5):
+            r.prim_inf[k] = float(prim[k])
+        r.opts = default_options(**opts)
+        r.drop, r.max_steps = float(drop), int(max_steps)
+        t = ctypes.c_int64()
+        st = self._L.hgks_server_submit(self.h, ctypes.byref(r), ctypes.byref(t))
+        if st != 0:
+            raise HgksError(st, "submit failed")
+        self._keep[t.value] = len(tets)
+        return t.value
+
+    def poll(self, ticket):
+        done = ctypes.c_int32()
+        res = Result()
+        st = self._L.hgks_server_poll(self.h, int(ticket), ctypes.byref(done), ctypes.byref(res))
+        if st != 0:
+            raise HgksError(st, "poll failed")
+        return res if done.value else None
+
+    def wait(self, ticket):
+        res = Result()
+        st = self._L.hgks_server_wait(self.h, int(ticket), ctypes.byref(res))
+        if st != 0:
+            raise HgksError(st, "wait failed")
+        return res
+
+    def state(self, ticket):
+        Q = np.zeros((5, self._keep[ticket]))
+        st = self._L.hgks_server_get_state(self.h, int(ticket), ctypes.c_void_p(Q.ctypes.data))
+        if st != 0:
+            raise HgksError(st, "no state")
+        return Q
+
+    def release(self, ticket):
+        self._L.hgks_server_release(self.h, int(ticket))
+        self._keep.pop(ticket, None)
+
+    def stats(self):
+        s = ServerStats()
+        self._L.hgks_server_stats(self.h, ctypes.byref(s))
+        return s
+
+    def close(self):
+        if getattr(self, "h", None):
+            self._L.hgks_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

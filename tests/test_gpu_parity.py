@@ -45,7 +45,7 @@ def built(oracle_lib):
 @pytest.mark.parametrize("case", list(C.CASES))
 def test_residual_parity(built, case):
     m, prim, o, s = built(case)
-    Q = C.state_for(o.N, prim[1], seed=2, amp=0.02) if False else perturbed_state(o.N, prim, amp=0.02, seed=2)
+    Q = perturbed_state(o.N, prim, amp=0.02, seed=2)
     G = _grads(case, o.N)
     hw = G is not None
     Ro = o.residual(Q, G=G, want_grad=hw)
@@ -121,9 +121,14 @@ def test_residual_deterministic(built):
 
 def test_implicit_steps_c1(oracle_lib):
     """The configuration-1 run: 10 implicit steps of the FP64 WENO scheme.
-    Both sides run the same GMRES; what differs is round-off.  With a fixed
-    FD step sigma = 1e-4 the FD products differ by ~1e-16/(sigma |v|) ~ 1e-10
-    relative, so the fields must agree to 1e-9 relative after 10 steps."""
+    The step map is sensitive: in the oracle alone a 1e-13 relative change of
+    the start state grows to ~1.5e-8 after 2 steps and ~1e-6 after 4 (GMRES
+    stops after a fixed 30 iterations, so its output is not a contraction of
+    its input).  So the two trajectories are compared one step at a time: each
+    GPU step starts from the GPU's own state, the oracle takes the same step
+    from that state, and with the fixed FD step sigma = 1e-4 the two updates
+    agree to ~1e-10 relative (round-off / sigma).  The whole trajectories must
+    still reach the same residual level."""
     from paper_2304_09485_amd import hgks
     m = mesh_for_config("c1")
     prim = freestream_prim(0.3)
@@ -131,19 +136,24 @@ def test_implicit_steps_c1(oracle_lib):
     o = oracle_lib.Oracle(m, kinds, prim, fd_sigma=1e-4)
     s = hgks.Solver(m, kinds, prim, fd_sigma=1e-4)
     Q0 = perturbed_state(o.N, prim, seed=1)
-    Qo = Q0.copy()
     s.set_state(Q0)
+    Qfree = Q0.copy()
     oracle_lib.set_threads(16)
     try:
         for k in range(10):
+            Qo = s.get_state()
             st, io = o.implicit_step(Qo)
             ig = s.implicit_step()
             assert st == 0 and ig.n_resid_evals == io.n_resid_evals == 33
             Qg = s.get_state()
             err = np.abs(Qg - Qo).max() / np.abs(Qo).max()
-            print(f"step {k + 1}: res gpu {ig.res:.6e} orc {io.res:.6e} field err {err:.3e}")
+            _, ifree = o.implicit_step(Qfree)
+            print(f"step {k + 1}: res gpu {ig.res:.6e} orc {io.res:.6e} one-step err {err:.3e} "
+                  f"free-running oracle res {ifree.res:.6e}")
             assert ig.res == pytest.approx(io.res, rel=1e-9)
             assert err <= 1e-9
+        assert ig.res == pytest.approx(ifree.res, rel=0.05)
+        assert ig.res < 0.2 * 0.1935766
     finally:
         oracle_lib.set_threads(1)
 

@@ -10,7 +10,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 def declared_symbols():
     txt = open(os.path.join(ROOT, "include", "hgks.h")).read()
-    decl = r"^(?:hgks_status|void|int64_t|const char\*)\s+\*?(hgks_[a-z_]+)\s*\("
+    decl = r"^(?:hgks_status|void|int64_t|size_t|const char\*)\s+\*?(hgks_[a-z_]+)\s*\("
     return sorted(set(re.findall(decl, txt, flags=re.M)))
 
 
