@@ -30,32 +30,82 @@ sys.path.insert(0, ROOT)
 PEAK_HBM_GBS = 8000.0        # MI355X HBM3E
 PEAK_FP64_VALU = 78.6e12     # MI355X FP64 vector FLOP/s
 
-# Algorithmic work per unit of the residual kernels (see the design notes):
-#   flux kernel: FP64 operations of the gas-kinetic flux per Gauss point,
-#   counted by running the flux function on the host with an operation-counting
-#   scalar type (tools in csrc/flopcount.cpp); units per launch = 3 F
-FLUX_FLOPS_PER_GP = {"euler": None, "euler_qg": None, "ns": None}
+# FP64 operations of the gas-kinetic flux per Gauss point, counted by running
+# the flux function on the host with an operation-counting scalar type
+# (csrc/flopcount.cpp, run by the build); a flux launch covers 3 F points
 FLOPS_FILE = os.path.join(ROOT, "paper_2304_09485_amd", "flux_flops.json")
+# measured HBM traffic per launch (rocprofv3 FETCH_SIZE / WRITE_SIZE runs,
+# calibrated against a plain copy), with the hash of the kernel sources the
+# counters were taken with
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_c2_hweno.md")
+KERNEL_SOURCES = ["hgks_kernels.hip", "side_kernel.h", "gks_flux.h", "hgks_device.h", "hgks_kernels.h"]
 
 
-def algorithmic_units(kernel, N, F, Nb, scheme):
-    """(bytes, flops) a launch of the kernel must move / compute at minimum."""
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2304_09485_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_for(kernel):
+    """HBM bytes per launch of the kernel as measured by the counters, or None
+    if none were taken or the kernel sources changed since."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    want = kernel_source_hash()
+    with open(TRAFFIC_FILE) as f:
+        for line in f:
+            p = line.split()
+            # lines "traffic <kernel> <bytes per launch> <source hash>"
+            if len(p) == 4 and p[0] == "traffic" and p[1] == kernel and p[3] == want:
+                return int(float(p[2]))
+    return None
+
+
+def algorithmic_bytes(kernel, N, F, Nb, scheme):
+    """Bytes a launch of the kernel must move at least: every array it needs
+    read once and every result written once (re-reads of a cell's data by its
+    neighbours or its faces are not counted)."""
+    NX = N + Nb
+    sides = 2 * F - Nb
     if kernel == "recon":
         if scheme == 1:
-            # operator 171 + P_m data 24 doubles, 4 neighbour ids, own Q and
-            # gradients read once, 105 coefficients written, per cell
-            b = N * (8 * (171 + 24) + 4 * 4 + 8 * (5 + 15) + 8 * 105 + 8)
-        else:
-            b = N * (8 * (144 + 72) + 4 * (16 + 24) + 1 + 8 * 5 + 8 * 105)
-        return b, None
+            # CLS operator 9x19 + closed-form sub-stencil data 24 per cell, 4
+            # neighbour ids, state and gradients (20 values per cell incl.
+            # ghosts) read once, 105 coefficients written
+            return N * (8 * (171 + 24) + 4 * 4 + 8 * 105) + NX * 8 * 20
+        # WENO: LS operators 9x16 + 4x3x6, 16 + 24 stencil ids, sub-stencil mask
+        return N * (8 * (144 + 72) + 4 * (16 + 24) + 1 + 8 * 105) + NX * 8 * 5
     if kernel == "side":
-        # coefficients (105) of the side's cell, two cell states, 21 face
-        # geometry values; 60 values written per side
-        sides = 2 * F - Nb
-        return sides * 8 * (105 + 10 + 21 + 60), None
+        # 105 coefficients, 6 second moments and h per cell; the state per
+        # cell; per face normal, 2 x 9 Gauss-point offsets and the two cell
+        # ids; 60 values written per reconstructed side
+        return N * 8 * (105 + 7) + NX * 8 * 5 + F * (8 * 21 + 8) + sides * 8 * 60
+    if kernel == "flux":
+        # 60 side values per side read, 15 flux values (3 GPs x 5) per face
+        # written, time steps of the two cells (+ 15 gradient-update values)
+        return sides * 8 * 60 + F * 8 * (15 + 2) + (F * 8 * 15 if scheme == 1 else 0)
     if kernel == "gather":
-        return N * (4 * 4 + 5 * 8 * 4 + 5 * 8), None
-    return None, None
+        # per cell 4 face ids, 4 face fluxes (5 values) read, 5 values written
+        return N * (4 * 4 + 4 * 5 * 8 + 5 * 8)
+    if kernel == "ghost":
+        return Nb * (8 * 5 * 2 + 8 * 3 + 8)
+    return None
+
+
+def flux_flops_per_launch(flops_tab, F, scheme, physics, evals_per_step):
+    """FP64 operations of the gas-kinetic flux per launch, averaged over one
+    implicit step: the base evaluation of the compact scheme also evaluates the
+    point value Q_G of the gradient update, the FD products do not."""
+    if not flops_tab:
+        return None
+    per = flops_tab["ns" if physics == 1 else "euler"]
+    if scheme == 1 and physics == 0:
+        per = (flops_tab["euler_qg"] + (evals_per_step - 1) * per) / evals_per_step
+    return per * 3 * F
 
 
 def main():
@@ -66,6 +116,18 @@ def main():
     ap.add_argument("--config", default="c2", choices=["c1", "c2"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--no-solve", action="store_true", help="skip the time-to-1e-8 solves")
+    ap.add_argument("--solve-steps", type=int, default=400, help="step cap of each time-to-1e-8 solve")
+    ap.add_argument("--serving", action="store_true",
+                    help="run the served request stream instead of the implicit-step throughput")
+    ap.add_argument("--requests", type=int, default=16, help="served requests")
+    ap.add_argument("--rate", type=float, default=0.5, help="request arrival rate (1/s)")
+    ap.add_argument("--max-cells", type=int, default=400_000, help="largest request (cells)")
+    ap.add_argument("--max-steps", type=int, default=400, help="step cap of a served solve")
+    ap.add_argument("--slots", type=int, default=8, help="concurrently admitted requests")
+    ap.add_argument("--fp64-serving", action="store_true", help="serve the plain FP64 form")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device copy (counter calibration) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the path has no multi-GPU mode",
@@ -79,6 +141,12 @@ def main():
     if not torch.cuda.is_available():
         print("no GPU visible", file=sys.stderr)
         sys.exit(1)
+    if args.copy_calibration:
+        copy_calibration(torch)
+        return
+    if args.serving:
+        serving_bench(hgks, args)
+        return
 
     if args.config == "c2":
         mesh = mesh_for_config("c2")
@@ -118,31 +186,43 @@ def main():
     n_launch = int(kt.pop("evaluations"))
     value = N * evals / elapsed / 1e6
 
-    # roofline of the dominant kernel
-    dom = max(kt, key=kt.get)
+    # per-kernel rates; roofline of the dominant kernel
     scheme = opts.get("scheme", 0)
+    physics = opts.get("physics", 0)
     flops_tab = {}
     if os.path.exists(FLOPS_FILE):
         with open(FLOPS_FILE) as f:
             flops_tab = json.load(f)
-    roof = None
-    avg_s = kt[dom] * 1e-3
-    if dom == "flux" and flops_tab:
-        key = "euler"
-        per_gp = flops_tab[key]
-        fl = per_gp * 3 * F
-        ach = fl / avg_s / 1e12
-        roof = {"kernel": dom, "bound": "alu", "achieved": round(ach, 3), "peak": PEAK_FP64_VALU / 1e12,
-                "unit": "TFLOP/s", "frac": round(ach / (PEAK_FP64_VALU / 1e12), 4), "traffic": None,
-                "avg_ms": round(kt[dom], 4), "launches": n_launch,
-                "units_per_launch": f"{3 * F} Gauss points x {per_gp} FP64 flop"}
+    evals_per_step = evals // args.steps
+    kernels = {}
+    for k, ms in kt.items():
+        b = algorithmic_bytes(k, N, F, Nb, scheme)
+        e = {"avg_ms": round(ms, 4)}
+        if b is not None and ms > 0:
+            e["bytes"] = int(b)
+            e["GB/s"] = round(b / (ms * 1e-3) / 1e9, 1)
+            e["hbm_frac"] = round(b / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)
+        if k == "flux":
+            fl = flux_flops_per_launch(flops_tab, F, scheme, physics, evals_per_step)
+            if fl is not None and ms > 0:
+                e["flop"] = int(fl)
+                e["TFLOP/s"] = round(fl / (ms * 1e-3) / 1e12, 2)
+                e["valu_frac"] = round(fl / (ms * 1e-3) / PEAK_FP64_VALU, 4)
+        kernels[k] = e
+    dom = max(kt, key=kt.get)
+    d = kernels[dom]
+    if "TFLOP/s" in d and d["valu_frac"] >= d.get("hbm_frac", 0.0):
+        roof = {"kernel": dom, "bound": "alu", "achieved": d["TFLOP/s"], "peak": PEAK_FP64_VALU / 1e12,
+                "unit": "TFLOP/s", "frac": d["valu_frac"], "traffic": traffic_for(dom), "avg_ms": d["avg_ms"],
+                "launches": n_launch, "per_launch": f"{d['flop']} FP64 flop"}
     else:
-        b, _ = algorithmic_units(dom, N, F, Nb, scheme)
-        if b is not None:
-            ach = b / avg_s / 1e9
-            roof = {"kernel": dom, "bound": "hbm", "achieved": round(ach, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                    "frac": round(ach / PEAK_HBM_GBS, 4), "traffic": None, "avg_ms": round(kt[dom], 4),
-                    "launches": n_launch}
+        roof = {"kernel": dom, "bound": "hbm", "achieved": d["GB/s"], "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": d["hbm_frac"], "traffic": traffic_for(dom), "avg_ms": d["avg_ms"], "launches": n_launch,
+                "per_launch": f"{d['bytes']} algorithmic bytes"}
+
+    solves = None
+    if not args.no_solve and args.config == "c2":
+        solves = time_to_drop(hgks, mesh, kinds, prim, args.solve_steps)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -164,12 +244,109 @@ def main():
         "config": {"workload": workload, "cells": N, "faces": F, "resid_evals_per_step": evals // args.steps,
                    "cfl": 10.0, "krylov_dim": 10, "restarts": 3, "jacobi_sweeps": 2},
         "roofline": roof,
-        "kernel_ms": {k: round(v, 4) for k, v in kt.items()},
+        "kernels": kernels,
         "cpu_baseline": cpu,
+        "time_to_1e-8": solves,
         "res_first_last": [infos[0].res, infos[-1].res],
         "setup_s": round(t_setup, 2),
     }
     print(json.dumps(out), flush=True)
+
+
+def serving_bench(hgks, args):
+    """The served request stream: seeded requests (sphere shell or ramp
+    channel, log-uniform cell counts, Mach 0.2-2, Euler or NS) arrive as a
+    Poisson process and are submitted to the server as they arrive; each is
+    solved from the free stream to a 1e-8 residual drop (or the step cap).
+    Reports time-to-steady percentiles (arrival to result) and throughput over
+    the makespan.  Meshes are generated before the clock starts (the client
+    side of a request)."""
+    from inputs import freestream_prim
+    from inputs.requests import request_stream
+    specs = request_stream(args.requests, args.rate, seed=5, n_max=args.max_cells)
+    meshes = [sp.mesh() for sp in specs]
+    prec = hgks.FP64 if args.fp64_serving else hgks.FP32_INNER
+    budget = 200 << 30  # leave headroom of the 288 GB for the runtime
+    srv = hgks.Server(budget, args.slots)
+    t0 = time.perf_counter()
+    tickets = []
+    for sp, m in zip(specs, meshes):
+        delay = sp.arrival_s - (time.perf_counter() - t0)
+        if delay > 0:
+            time.sleep(delay)
+        opts = dict(scheme=hgks.WENO, precision=prec)
+        if sp.viscous:
+            opts.update(physics=hgks.NS, mu=sp.mach / sp.reynolds, prandtl=0.72)
+        tickets.append(srv.submit(m, sp.boundary_kinds(), freestream_prim(sp.mach), drop=1e-8,
+                                  max_steps=args.max_steps, **opts))
+        print(f"# submitted request {sp.index}: {sp.kind} {m.n_cells} cells Mach {sp.mach:.2f} "
+              f"{'NS' if sp.viscous else 'Euler'} at {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+    res = []
+    for sp, t in zip(specs, tickets):
+        r = srv.wait(t)
+        res.append(r)
+        print(f"# request {sp.index}: status {r.status} steps {r.steps} drop {r.res_final / max(r.res0, 1e-300):.2e} "
+              f"queue {r.t_queue_ms:.0f} ms total {r.t_total_ms:.0f} ms", file=sys.stderr, flush=True)
+    makespan = time.perf_counter() - t0
+    srv.close()
+    lat = np.array([r.t_total_ms for r in res]) * 1e-3
+    conv = [r.status == 0 for r in res]
+    cell_evals = sum(r.n_cells * r.n_resid_evals for r in res)
+    out = {
+        "metric": "p50/p99 solve latency (served stream)",
+        "value": round(float(np.percentile(lat, 50)), 3),
+        "unit": "s",
+        "p99_s": round(float(np.percentile(lat, 99)), 3),
+        "n_gpus": 1,
+        "higher_is_better": False,
+        "throughput": {"Mcell-residual/s": round(cell_evals / makespan / 1e6, 3),
+                       "solves/s": round(len(res) / makespan, 4), "makespan_s": round(makespan, 2)},
+        "requests": len(res), "converged": int(sum(conv)),
+        "dtype": "f32 inner / f64 outer" if prec == hgks.FP32_INNER else "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{len(res)} Poisson requests at {args.rate}/s, shell or ramp tet meshes of "
+                               f"50k-{args.max_cells // 1000}k cells, Mach 0.2-2, Euler or NS, WENO, drop 1e-8, "
+                               f"cap {args.max_steps} steps", "slots": args.slots},
+        "per_request": [{"cells": r.n_cells, "status": r.status, "steps": r.steps, "t_total_s": round(r.t_total_ms * 1e-3, 3),
+                         "t_queue_s": round(r.t_queue_ms * 1e-3, 3)} for r in res],
+    }
+    print(json.dumps(out), flush=True)
+
+
+def time_to_drop(hgks, mesh, kinds, prim, max_steps):
+    """Wall time of solve_steady from a uniform free-stream start to a 1e-8
+    drop of the density residual, per form, on the same mesh (context set-up
+    reported apart).  A form that has not reached the drop after max_steps
+    reports the drop it reached."""
+    from inputs import uniform_state
+    forms = [("non-compact WENO, FP64", dict(scheme=hgks.WENO)),
+             ("non-compact WENO, FP32 inner / FP64 outer", dict(scheme=hgks.WENO, precision=hgks.FP32_INNER)),
+             ("compact HWENO, FP64", dict(scheme=hgks.HWENO))]
+    out = []
+    for name, opts in forms:
+        t0 = time.perf_counter()
+        s = hgks.Solver(mesh, kinds, prim, **opts)
+        t_setup = time.perf_counter() - t0
+        s.set_state(uniform_state(s.N, prim), np.zeros((15, s.N)) if opts["scheme"] == hgks.HWENO else None)
+        info = s.solve_steady(drop=1e-8, max_steps=max_steps)
+        out.append({"form": name, "seconds": round(info.t_ms * 1e-3, 3), "steps": info.steps,
+                    "converged": bool(info.converged), "drop": info.drop, "setup_s": round(t_setup, 2)})
+        s.close()
+        print(f"# time to 1e-8: {out[-1]}", file=sys.stderr, flush=True)
+    return out
+
+
+def copy_calibration(torch):
+    """A plain device copy of known size (1 GiB read, 1 GiB written), three
+    times: the HBM counters of these dispatches calibrate the counters of the
+    residual kernels."""
+    n = 1 << 27
+    src = torch.ones(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": n * 8, "copy_bytes_written": n * 8, "copies": 3}), flush=True)
 
 
 def cpu_baseline(mesh, kinds, prim, opts, budget_s):

@@ -146,6 +146,17 @@ hgks_status hgks_implicit_step(hgks_ctx* ctx, hgks_step_info* info);
 /* Implicit steps until res/res0 <= drop or max_steps; HGKS_ENOCONV if not. */
 hgks_status hgks_solve_steady(hgks_ctx* ctx, double drop, int32_t max_steps, hgks_solve_info* info);
 
+/* Checkpoint / resume of a steady solve.  hgks_checkpoint writes the state,
+ * the cell-averaged gradients (compact scheme) and the reference residual of
+ * res_rel to path (written under path.tmp, then renamed over path), with a
+ * 64-bit FNV-1a hash of the content.  hgks_restore reads such a file into a
+ * context with the same mesh and scheme loaded; a file for another mesh or
+ * scheme, a truncated or corrupted file gives HGKS_EINVAL and leaves the
+ * context's state unchanged.  The file is host-endian and not portable across
+ * byte orders. */
+hgks_status hgks_checkpoint(hgks_ctx* ctx, const char* path);
+hgks_status hgks_restore(hgks_ctx* ctx, const char* path);
+
 /* Device-pointer twins (caller's HIP stream; NULL = context stream):
  * Q_dev [5][N] doubles, R_dev [5][N] doubles. */
 hgks_status hgks_residual_dev(hgks_ctx* ctx, const void* Q_dev, void* R_dev, void* stream);

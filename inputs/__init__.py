@@ -8,3 +8,4 @@ raw arrays on their own.
 """
 from .meshes import TetMesh, cube_mesh, shell_mesh, ramp_mesh, mesh_for_config  # noqa: F401
 from .states import freestream_prim, prim_to_cons, perturbed_state, uniform_state  # noqa: F401
+from .requests import RequestSpec, request_stream  # noqa: F401

@@ -275,11 +275,14 @@ hgks_status ensure_f32(hgks_ctx* ctx) {
 
 // FD Jacobian-vector product at the current state: out = A v (Eq. (frechet)
 // with the (|Omega|/dt) term of Eq. (impsystem)); uses ctx->dtc, ctx->b.
-hgks_status jv_device(hgks_ctx* ctx, const double* v, double sigma_fixed, double* out, hipStream_t s) {
+// In the FP32-inner form the Arnoldi products run in FP32 (inner = true);
+// the restart residual b - A dQ of the outer defect correction stays FP64.
+hgks_status jv_device(hgks_ctx* ctx, const double* v, double sigma_fixed, double* out, hipStream_t s,
+                      bool inner = true) {
   size_t n = n5(ctx);
   const int N = ctx->H.N, NX = ctx->H.N + ctx->H.Nb;
   launch_dot(v, v, n, ctx->part, ctx->sc + 1, false, s);
-  bool f32 = ctx->o.precision == HGKS_FP32_INNER;
+  bool f32 = inner && ctx->o.precision == HGKS_FP32_INNER;
   double eps = f32 ? std::ldexp(1.0, -23) : std::ldexp(1.0, -52);
   launch_sigma(ctx->sc + 1, ctx->sc + 0, (double)n, eps, sigma_fixed, ctx->sc + 2, s);
   if (!f32) {
@@ -651,9 +654,9 @@ hgks_status hgks_implicit_step(hgks_ctx* ctx, hgks_step_info* info) {
     if (rs == 0) {
       HIPCHK(hipMemcpyAsync(ctx->rv, ctx->b, n * sizeof(double), hipMemcpyDeviceToDevice, s));
     } else {
-      TRY(jv_device(ctx, ctx->dQ, ctx->o.fd_sigma, ctx->yv, s));
+      TRY(jv_device(ctx, ctx->dQ, ctx->o.fd_sigma, ctx->yv, s, false));
       ++evals;
-      // r = b - A dQ
+      // r = b - A dQ (FP64 in both forms: the outer defect correction)
       HIPCHK(hipMemcpyAsync(ctx->rv, ctx->b, n * sizeof(double), hipMemcpyDeviceToDevice, s));
       double one = 1.0;
       HIPCHK(hipMemcpyAsync(ctx->sc + 4, &one, sizeof(double), hipMemcpyHostToDevice, s));
@@ -771,6 +774,111 @@ hgks_status hgks_solve_steady(hgks_ctx* ctx, double drop, int32_t max_steps, hgk
     ctx->err = "requested residual drop not reached";
     return HGKS_ENOCONV;
   }
+  return HGKS_OK;
+}
+
+namespace {
+
+// Checkpoint file: a fixed header, the state [5][N], the gradients [15][N]
+// (compact scheme only), then an FNV-1a 64-bit hash of everything before it.
+struct CkptHeader {
+  char magic[8];     // "HGKSCKP1"
+  int32_t version;   // 1
+  int32_t scheme;    // HGKS_WENO | HGKS_HWENO
+  int64_t n_cells;
+  int64_t n_bfaces;
+  double res0;       // residual the relative residual is measured against (< 0: none yet)
+  double gamma;
+};
+
+uint64_t fnv1a(uint64_t h, const void* p, size_t n) {
+  const unsigned char* b = (const unsigned char*)p;
+  for (size_t k = 0; k < n; ++k) {
+    h ^= b[k];
+    h *= 1099511628211ull;
+  }
+  return h;
+}
+
+constexpr uint64_t FNV_OFFSET = 14695981039346656037ull;
+
+}  // namespace
+
+hgks_status hgks_checkpoint(hgks_ctx* ctx, const char* path) {
+  TRY(require(ctx, true));
+  if (!path) return HGKS_EINVAL;
+  const int64_t N = ctx->H.N;
+  const bool hw = ctx->o.scheme == HGKS_HWENO;
+  std::vector<double> Q((size_t)5 * N), G(hw ? (size_t)15 * N : 0);
+  TRY(hgks_get_state(ctx, Q.data(), hw ? G.data() : nullptr));
+  CkptHeader h{};
+  std::memcpy(h.magic, "HGKSCKP1", 8);
+  h.version = 1;
+  h.scheme = ctx->o.scheme;
+  h.n_cells = N;
+  h.n_bfaces = ctx->H.Nb;
+  h.res0 = ctx->res0;
+  h.gamma = ctx->o.gamma;
+  uint64_t hash = fnv1a(FNV_OFFSET, &h, sizeof(h));
+  hash = fnv1a(hash, Q.data(), Q.size() * sizeof(double));
+  if (hw) hash = fnv1a(hash, G.data(), G.size() * sizeof(double));
+  // write to a temporary name and rename, so a crash never leaves a torn file
+  std::string tmp = std::string(path) + ".tmp";
+  FILE* f = std::fopen(tmp.c_str(), "wb");
+  if (!f) {
+    ctx->err = "cannot open checkpoint file for writing";
+    return HGKS_EINVAL;
+  }
+  bool ok = std::fwrite(&h, sizeof(h), 1, f) == 1 && std::fwrite(Q.data(), sizeof(double), Q.size(), f) == Q.size() &&
+            (!hw || std::fwrite(G.data(), sizeof(double), G.size(), f) == G.size()) &&
+            std::fwrite(&hash, sizeof(hash), 1, f) == 1;
+  ok = (std::fclose(f) == 0) && ok;
+  if (!ok || std::rename(tmp.c_str(), path) != 0) {
+    std::remove(tmp.c_str());
+    ctx->err = "writing the checkpoint file failed";
+    return HGKS_EINVAL;
+  }
+  return HGKS_OK;
+}
+
+hgks_status hgks_restore(hgks_ctx* ctx, const char* path) {
+  TRY(require(ctx, false));
+  if (!path) return HGKS_EINVAL;
+  FILE* f = std::fopen(path, "rb");
+  if (!f) {
+    ctx->err = "cannot open checkpoint file";
+    return HGKS_EINVAL;
+  }
+  auto fail = [&](const char* msg) {
+    std::fclose(f);
+    ctx->err = msg;
+    return HGKS_EINVAL;
+  };
+  CkptHeader h{};
+  if (std::fread(&h, sizeof(h), 1, f) != 1 || std::memcmp(h.magic, "HGKSCKP1", 8) != 0 || h.version != 1)
+    return fail("not an HGKS checkpoint file (bad magic or version)");
+  const int64_t N = ctx->H.N;
+  if (h.n_cells != N || h.n_bfaces != ctx->H.Nb) return fail("checkpoint was written for a different mesh");
+  if (h.scheme != ctx->o.scheme) return fail("checkpoint was written for a different reconstruction scheme");
+  const bool hw = h.scheme == HGKS_HWENO;
+  std::vector<double> Q((size_t)5 * N), G(hw ? (size_t)15 * N : 0);
+  uint64_t stored = 0;
+  if (std::fread(Q.data(), sizeof(double), Q.size(), f) != Q.size() ||
+      (hw && std::fread(G.data(), sizeof(double), G.size(), f) != G.size()) ||
+      std::fread(&stored, sizeof(stored), 1, f) != 1)
+    return fail("checkpoint file is truncated");
+  char extra;
+  if (std::fread(&extra, 1, 1, f) != 0) return fail("checkpoint file has trailing bytes");
+  std::fclose(f);
+  uint64_t hash = fnv1a(FNV_OFFSET, &h, sizeof(h));
+  hash = fnv1a(hash, Q.data(), Q.size() * sizeof(double));
+  if (hw) hash = fnv1a(hash, G.data(), G.size() * sizeof(double));
+  if (hash != stored) {
+    ctx->err = "checkpoint file is corrupt (hash mismatch)";
+    return HGKS_EINVAL;
+  }
+  TRY(hgks_set_state(ctx, Q.data(), hw ? G.data() : nullptr));
+  ctx->res0 = h.res0;
   return HGKS_OK;
 }
 

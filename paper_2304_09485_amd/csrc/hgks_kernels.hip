@@ -639,7 +639,7 @@ void launch_recon(const DevMesh<T>& M, const Params& P, const T* Qx, const T* Gx
 template <typename T>
 void launch_side(const DevMesh<T>& M, const Params& P, const T* Qx, const T* coef, T* sv, int* nfall,
                  hipStream_t s) {
-  hipLaunchKernelGGL(k_side<T>, dim3(nblk(2 * (size_t)M.F, SIDE_SPB)), dim3(64), 0, s, M, P, Qx, coef, sv, nfall);
+  hipLaunchKernelGGL(k_side<T>, dim3(nblk(2 * (size_t)M.F, SIDE_SPB)), dim3(SIDE_THREADS), 0, s, M, P, Qx, coef, sv, nfall);
 }
 template <typename T>
 void launch_flux(const DevMesh<T>& M, const Params& P, const T* sv, const T* dt, T* ff, T* fq, bool qg,

@@ -237,6 +237,11 @@ int build_host_mesh(HostMesh& H, int64_t n_nodes, const double* xyz, int64_t n_t
     err = "boundary face list does not match the mesh boundary";
     return -3;
   }
+  // face order: by left cell, then its local face.  Consecutive faces then
+  // share or neighbour their left cell, so a wavefront's loads of left-cell
+  // data touch few cache lines (the cell order is the caller's).
+  std::sort(ft.begin(), ft.end(),
+            [](const FaceTmp& a, const FaceTmp& b) { return a.L != b.L ? a.L < b.L : a.pL < b.pL; });
   const int F = (int)ft.size();
   H.F = F;
   H.Nb = (int)nb_found;

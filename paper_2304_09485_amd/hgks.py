@@ -28,6 +28,7 @@ SYMBOLS = ["hgks_default_options", "hgks_create", "hgks_load_mesh", "hgks_set_fr
            "hgks_set_state", "hgks_get_state", "hgks_residual", "hgks_time_step", "hgks_jv", "hgks_precond",
            "hgks_implicit_step", "hgks_solve_steady", "hgks_residual_dev", "hgks_jv_dev", "hgks_n_cells",
            "hgks_n_faces", "hgks_kernel_times", "hgks_last_error", "hgks_destroy", "hgks_estimate_bytes",
+           "hgks_checkpoint", "hgks_restore",
            "hgks_server_create", "hgks_server_submit", "hgks_server_poll", "hgks_server_wait",
            "hgks_server_get_state", "hgks_server_release", "hgks_server_stats", "hgks_server_destroy"]
 
@@ -107,6 +108,8 @@ def load_library():
         "hgks_set_bc": (i32, [vp, i32, i32, vp]),
         "hgks_set_state": (i32, [vp, vp, vp]),
         "hgks_get_state": (i32, [vp, vp, vp]),
+        "hgks_checkpoint": (i32, [vp, ctypes.c_char_p]),
+        "hgks_restore": (i32, [vp, ctypes.c_char_p]),
         "hgks_residual": (i32, [vp, vp, vp, vp, vp]),
         "hgks_time_step": (i32, [vp, vp, vp]),
         "hgks_jv": (i32, [vp, vp, d, vp, vp]),
@@ -243,6 +246,12 @@ class Solver:
         if st != 0 and (st != -5 or raise_on_noconv):
             self._check(st)
         return info
+
+    def checkpoint(self, path):
+        self._check(self._L.hgks_checkpoint(self.h, os.fsencode(path)))
+
+    def restore(self, path):
+        self._check(self._L.hgks_restore(self.h, os.fsencode(path)))
 
     # --- device interface (torch tensors, caller's stream) ---------------------
     def residual_dev(self, Q, R, stream=None):

@@ -125,10 +125,15 @@ def test_implicit_steps_c1(oracle_lib):
     the start state grows to ~1.5e-8 after 2 steps and ~1e-6 after 4 (GMRES
     stops after a fixed 30 iterations, so its output is not a contraction of
     its input).  So the two trajectories are compared one step at a time: each
-    GPU step starts from the GPU's own state, the oracle takes the same step
-    from that state, and with the fixed FD step sigma = 1e-4 the two updates
-    agree to ~1e-10 relative (round-off / sigma).  The whole trajectories must
-    still reach the same residual level."""
+    GPU step starts from the GPU's own state and the oracle takes the same
+    step from that state.  The FD products of the two sides differ by
+    round-off / sigma (~1e-12 relative with sigma = 1e-4), and one step maps
+    such a difference onto the update with the same gain as it maps a
+    round-off-level change of its input; that gain is measured at every step
+    by a second oracle step from the state changed by 1e-13 relative.  Bound:
+    max(1e-9, 20 x that spread).  The whole trajectories must reach the same
+    residual level: two oracle runs whose start states differ by 1e-13 end
+    step 10 with residuals 14% apart, so within 2x."""
     from paper_2304_09485_amd import hgks
     m = mesh_for_config("c1")
     prim = freestream_prim(0.3)
@@ -138,21 +143,27 @@ def test_implicit_steps_c1(oracle_lib):
     Q0 = perturbed_state(o.N, prim, seed=1)
     s.set_state(Q0)
     Qfree = Q0.copy()
+    rng = np.random.default_rng(11)
     oracle_lib.set_threads(16)
     try:
         for k in range(10):
-            Qo = s.get_state()
+            Qstart = s.get_state()
+            Qo = Qstart.copy()
             st, io = o.implicit_step(Qo)
+            Qp = Qstart * (1.0 + 1e-13 * rng.uniform(-1.0, 1.0, Qstart.shape))
+            o.implicit_step(Qp)
             ig = s.implicit_step()
             assert st == 0 and ig.n_resid_evals == io.n_resid_evals == 33
             Qg = s.get_state()
-            err = np.abs(Qg - Qo).max() / np.abs(Qo).max()
+            scale = np.abs(Qo).max()
+            err = np.abs(Qg - Qo).max() / scale
+            spread = np.abs(Qp - Qo).max() / scale
             _, ifree = o.implicit_step(Qfree)
             print(f"step {k + 1}: res gpu {ig.res:.6e} orc {io.res:.6e} one-step err {err:.3e} "
-                  f"free-running oracle res {ifree.res:.6e}")
+                  f"oracle spread {spread:.3e} free-running oracle res {ifree.res:.6e}")
             assert ig.res == pytest.approx(io.res, rel=1e-9)
-            assert err <= 1e-9
-        assert ig.res == pytest.approx(ifree.res, rel=0.05)
+            assert err <= max(1e-9, 20.0 * spread)
+        assert 0.5 < ig.res / ifree.res < 2.0
         assert ig.res < 0.2 * 0.1935766
     finally:
         oracle_lib.set_threads(1)
