@@ -261,10 +261,11 @@ hgks_status ensure_f32(hgks_ctx* ctx) {
   DevMesh<float>& Mf = ctx->Mf;
   const DevMesh<double>& M = ctx->M;
   Mf.N = M.N; Mf.F = M.F; Mf.Nb = M.Nb; Mf.NX = M.NX;
-  Mf.fL = M.fL; Mf.fR = M.fR; Mf.fkind = M.fkind; Mf.cface = M.cface; Mf.gowner = M.gowner; Mf.gface = M.gface;
+  Mf.fL = M.fL; Mf.fR = M.fR; Mf.ford = M.ford; Mf.rpos = M.rpos; Mf.fkind = M.fkind; Mf.cface = M.cface; Mf.gowner = M.gowner; Mf.gface = M.gface;
   Mf.stn = M.stn; Mf.sstn = M.sstn; Mf.smask = M.smask; Mf.nb4 = M.nb4;
   TRY(upload_mesh_fp<float>(ctx, Mf));
   TRY(alloc_work<float>(ctx, ctx->W32));
+
   ctx->Qp32 = ctx->A.get<float>((size_t)5 * M.NX);
   if (!ctx->Qp32) return HGKS_ENOMEM;
   ctx->have_f32 = true;
@@ -465,6 +466,8 @@ hgks_status hgks_load_mesh(hgks_ctx* ctx, int64_t n_nodes, const double* xyz, in
   M.NX = H.N + H.Nb;
   TRY(upload(ctx, H.fL, M.fL));
   TRY(upload(ctx, H.fR, M.fR));
+  TRY(upload(ctx, H.ford, M.ford));
+  TRY(upload(ctx, H.rpos, M.rpos));
   TRY(upload(ctx, H.cface, M.cface));
   TRY(upload(ctx, H.gowner, M.gowner));
   TRY(upload(ctx, H.gface, M.gface));

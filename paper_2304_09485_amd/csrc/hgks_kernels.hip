@@ -131,81 +131,110 @@ __global__ void __launch_bounds__(256) k_ghost(DevMesh<T> M, Params P, T* __rest
 template <typename T>
 __global__ void __launch_bounds__(256) k_recon_weno(DevMesh<T> M, const T* __restrict__ Qx,
                                                     T* __restrict__ coef) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= M.N) return;
   const int N = M.N, NX = M.NX;
-  int st[16], ss[24];
+  T q0[5];
 #pragma unroll
-  for (int j = 0; j < 16; ++j) st[j] = M.stn[j * N + i];
+  for (int v = 0; v < 5; ++v) q0[v] = Qx[(size_t)v * NX + i];
+  // differences to the 16 cells of the big stencil, all 5 variables: each
+  // operator row is then read once and applied to the 5 variables
+  T dq[5][16];
 #pragma unroll
-  for (int r = 0; r < 24; ++r) ss[r] = M.sstn[r * N + i];
-  for (int v = 0; v < 5; ++v) {
-    const T* Qv = Qx + (size_t)v * NX;
-    T q0 = Qv[i];
-    T dq[16];
+  for (int j = 0; j < 16; ++j) {
+    const int c = M.stn[j * N + i];
 #pragma unroll
-    for (int j = 0; j < 16; ++j) dq[j] = Qv[st[j]] - q0;
+    for (int v = 0; v < 5; ++v) dq[v][j] = Qx[(size_t)v * NX + c] - q0[v];
+  }
 #pragma unroll
-    for (int k = 0; k < 9; ++k) {
-      T acc = T(0);
+  for (int k = 0; k < 9; ++k) {
+    T acc[5] = {T(0), T(0), T(0), T(0), T(0)};
 #pragma unroll
-      for (int j = 0; j < 16; ++j) acc += M.opA[(size_t)(k * 16 + j) * N + i] * dq[j];
-      coef[(size_t)(k * 5 + v) * N + i] = acc;
+    for (int j = 0; j < 16; ++j) {
+      const T o = M.opA[(size_t)(k * 16 + j) * N + i];
+#pragma unroll
+      for (int v = 0; v < 5; ++v) acc[v] += o * dq[v][j];
     }
 #pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      T ds[6];
+    for (int v = 0; v < 5; ++v) coef[(size_t)(k * 5 + v) * N + i] = acc[v];
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  // sub-stencil gradients (6 members each)
 #pragma unroll
-      for (int r = 0; r < 6; ++r) ds[r] = Qv[ss[s * 6 + r]] - q0;
+  for (int s = 0; s < 4; ++s) {
+    T ds[5][6];
 #pragma unroll
-      for (int t = 0; t < 3; ++t) {
-        T acc = T(0);
+    for (int r = 0; r < 6; ++r) {
+      const int c = M.sstn[(s * 6 + r) * N + i];
 #pragma unroll
-        for (int r = 0; r < 6; ++r) acc += M.opB[(size_t)((s * 3 + t) * 6 + r) * N + i] * ds[r];
-        coef[(size_t)((9 + s * 3 + t) * 5 + v) * N + i] = acc;
+      for (int v = 0; v < 5; ++v) ds[v][r] = Qx[(size_t)v * NX + c] - q0[v];
+    }
+#pragma unroll
+    for (int t = 0; t < 3; ++t) {
+      T acc[5] = {T(0), T(0), T(0), T(0), T(0)};
+#pragma unroll
+      for (int r = 0; r < 6; ++r) {
+        const T o = M.opB[(size_t)((s * 3 + t) * 6 + r) * N + i];
+#pragma unroll
+        for (int v = 0; v < 5; ++v) acc[v] += o * ds[v][r];
       }
+#pragma unroll
+      for (int v = 0; v < 5; ++v) coef[(size_t)((9 + s * 3 + t) * 5 + v) * N + i] = acc[v];
     }
+    __builtin_amdgcn_sched_barrier(0);
   }
 }
 
 template <typename T>
 __global__ void __launch_bounds__(256) k_recon_hweno(DevMesh<T> M, const T* __restrict__ Qx,
                                                      const T* __restrict__ Gx, T* __restrict__ coef) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= M.N) return;
   const int N = M.N, NX = M.NX;
   int nb[4];
 #pragma unroll
   for (int k = 0; k < 4; ++k) nb[k] = M.nb4[k * N + i];
-  T h = M.h[i];
-  for (int v = 0; v < 5; ++v) {
-    T q0 = Qx[(size_t)v * NX + i];
-    T x[19];
+  const T h = M.h[i];
+  // the 19 data of the compact stencil for all 5 variables: 4 neighbour
+  // differences, own gradient, the 4 neighbours' gradients
+  T x[5][19];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) x[k] = Qx[(size_t)v * NX + nb[k]] - q0;
+  for (int v = 0; v < 5; ++v) {
+    const T q0 = Qx[(size_t)v * NX + i];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) x[v][k] = Qx[(size_t)v * NX + nb[k]] - q0;
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-      x[4 + d] = Gx[(size_t)(v * 3 + d) * NX + i];
+      x[v][4 + d] = Gx[(size_t)(v * 3 + d) * NX + i];
 #pragma unroll
-      for (int k = 0; k < 4; ++k) x[7 + 3 * k + d] = Gx[(size_t)(v * 3 + d) * NX + nb[k]];
+      for (int k = 0; k < 4; ++k) x[v][7 + 3 * k + d] = Gx[(size_t)(v * 3 + d) * NX + nb[k]];
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < 9; ++k) {
+    T acc[5] = {T(0), T(0), T(0), T(0), T(0)};
+#pragma unroll
+    for (int j = 0; j < 19; ++j) {
+      const T o = M.opH[(size_t)(k * 19 + j) * N + i];
+#pragma unroll
+      for (int v = 0; v < 5; ++v) acc[v] += o * x[v][j];
     }
 #pragma unroll
-    for (int k = 0; k < 9; ++k) {
-      T acc = T(0);
+    for (int v = 0; v < 5; ++v) coef[(size_t)(k * 5 + v) * N + i] = acc[v];
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  // P_m on {i, i_m}: the constrained minimiser has a closed form
 #pragma unroll
-      for (int j = 0; j < 19; ++j) acc += M.opH[(size_t)(k * 19 + j) * N + i] * x[j];
-      coef[(size_t)(k * 5 + v) * N + i] = acc;
-    }
-    // P_m on {i, i_m}: the constrained minimiser has a closed form
+  for (int s = 0; s < 4; ++s) {
+    const T wi = M.hsub[(size_t)(s * 6 + 0) * N + i], wm = M.hsub[(size_t)(s * 6 + 1) * N + i];
+    const T d0 = M.hsub[(size_t)(s * 6 + 2) * N + i], d1 = M.hsub[(size_t)(s * 6 + 3) * N + i];
+    const T d2 = M.hsub[(size_t)(s * 6 + 4) * N + i], id2 = M.hsub[(size_t)(s * 6 + 5) * N + i];
 #pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      T wi = M.hsub[(size_t)(s * 6 + 0) * N + i], wm = M.hsub[(size_t)(s * 6 + 1) * N + i];
-      T d0 = M.hsub[(size_t)(s * 6 + 2) * N + i], d1 = M.hsub[(size_t)(s * 6 + 3) * N + i];
-      T d2 = M.hsub[(size_t)(s * 6 + 4) * N + i], id2 = M.hsub[(size_t)(s * 6 + 5) * N + i];
-      T g0 = wi * x[4] + wm * x[7 + 3 * s];
-      T g1 = wi * x[5] + wm * x[8 + 3 * s];
-      T g2 = wi * x[6] + wm * x[9 + 3 * s];
-      T lam = (x[s] - (d0 * g0 + d1 * g1 + d2 * g2)) * id2;
+    for (int v = 0; v < 5; ++v) {
+      const T g0 = wi * x[v][4] + wm * x[v][7 + 3 * s];
+      const T g1 = wi * x[v][5] + wm * x[v][8 + 3 * s];
+      const T g2 = wi * x[v][6] + wm * x[v][9 + 3 * s];
+      const T lam = (x[v][s] - (d0 * g0 + d1 * g1 + d2 * g2)) * id2;
       coef[(size_t)((9 + s * 3 + 0) * 5 + v) * N + i] = h * (g0 + lam * d0);
       coef[(size_t)((9 + s * 3 + 1) * 5 + v) * N + i] = h * (g1 + lam * d1);
       coef[(size_t)((9 + s * 3 + 2) * 5 + v) * N + i] = h * (g2 + lam * d2);
@@ -306,11 +335,12 @@ __global__ void __launch_bounds__(64) k_flux(DevMesh<T> M, Params P, const T* __
                  ui[0] * t2[0] + ui[1] * t2[1] + ui[2] * t2[2]};
       boundary_right(M.fkind[f], Wl, dWl, ul, T(P.rhoinf), T(P.pinf), fp.gamma, Wr, dWr);
     } else {
+      const size_t rc = (size_t)F + M.rpos[f];  // column of the right side
 #pragma unroll
       for (int v = 0; v < 5; ++v) {
-        Wr[v] = sv[(size_t)((gp * 4 + 0) * 5 + v) * ld + F + f];
+        Wr[v] = sv[(size_t)((gp * 4 + 0) * 5 + v) * ld + rc];
 #pragma unroll
-        for (int d = 0; d < 3; ++d) dWr[d][v] = sv[(size_t)((gp * 4 + 1 + d) * 5 + v) * ld + F + f];
+        for (int d = 0; d < 3; ++d) dWr[d][v] = sv[(size_t)((gp * 4 + 1 + d) * 5 + v) * ld + rc];
       }
     }
     gks_flux<T, QG>(Wl, dWl, Wr, dWr, dtf, fp, Fg, Qg);

@@ -5,7 +5,8 @@
 // components are taken in turn (projection of the side cell's 21 coefficient
 // vectors, smoothness indicators, nonlinear weights, combined polynomial at
 // the Gauss points) and accumulated into the 60 outputs through R*.
-// sv layout [60][2F], row (g*4+d)*5+v, column side*F+f.
+// sv layout [60][2F], row (g*4+d)*5+v; column f for the left side of face f,
+// column F + rpos[f] for its right side.
 // Included inside namespace hgks of hgks_kernels.hip.
 #pragma once
 
@@ -20,7 +21,9 @@ __global__ void __launch_bounds__(128) k_side(DevMesh<T> M, Params P, const T* _
   const int F = M.F, N = M.N, NX = M.NX;
   if (sidx >= 2 * F) return;
   int side = sidx >= F;
-  int f = side ? sidx - F : sidx;
+  // left sides in face order, right sides in right-cell order (column F + k
+  // holds the right side of face ford[k])
+  int f = side ? M.ford[sidx - F] : sidx;
   int L = M.fL[f], R = M.fR[f];
   if (side && R >= N) return;
   int i = side ? R : L, j = side ? L : R;
