@@ -125,7 +125,8 @@ def main():
     ap.add_argument("--max-cells", type=int, default=400_000, help="largest request (cells)")
     ap.add_argument("--max-steps", type=int, default=400, help="step cap of a served solve")
     ap.add_argument("--slots", type=int, default=8, help="concurrently admitted requests")
-    ap.add_argument("--fp64-serving", action="store_true", help="serve the plain FP64 form")
+    ap.add_argument("--fp32-inner-serving", action="store_true",
+                    help="serve the FP32-inner form (default: plain FP64)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (counter calibration) and exit")
     args = ap.parse_args()
@@ -265,7 +266,7 @@ def serving_bench(hgks, args):
     from inputs.requests import request_stream
     specs = request_stream(args.requests, args.rate, seed=5, n_max=args.max_cells)
     meshes = [sp.mesh() for sp in specs]
-    prec = hgks.FP64 if args.fp64_serving else hgks.FP32_INNER
+    prec = hgks.FP32_INNER if args.fp32_inner_serving else hgks.FP64
     budget = 200 << 30  # leave headroom of the 288 GB for the runtime
     srv = hgks.Server(budget, args.slots)
     t0 = time.perf_counter()
@@ -274,7 +275,9 @@ def serving_bench(hgks, args):
         delay = sp.arrival_s - (time.perf_counter() - t0)
         if delay > 0:
             time.sleep(delay)
-        opts = dict(scheme=hgks.WENO, precision=prec)
+        # impulsive starts (supersonic ramps, no-slip walls) ramp the CFL
+        # number from 1 to 10 over the first steps
+        opts = dict(scheme=hgks.WENO, precision=prec, cfl_start=1.0, cfl_growth=1.5)
         if sp.viscous:
             opts.update(physics=hgks.NS, mu=sp.mach / sp.reynolds, prandtl=0.72)
         tickets.append(srv.submit(m, sp.boundary_kinds(), freestream_prim(sp.mach), drop=1e-8,
@@ -321,6 +324,9 @@ def time_to_drop(hgks, mesh, kinds, prim, max_steps):
     from inputs import uniform_state
     forms = [("non-compact WENO, FP64", dict(scheme=hgks.WENO)),
              ("non-compact WENO, FP32 inner / FP64 outer", dict(scheme=hgks.WENO, precision=hgks.FP32_INNER)),
+             ("non-compact WENO, linear weights, FP64", dict(scheme=hgks.WENO, weights=hgks.WEIGHTS_LINEAR)),
+             ("non-compact WENO, linear weights, FP32 inner / FP64 outer",
+              dict(scheme=hgks.WENO, weights=hgks.WEIGHTS_LINEAR, precision=hgks.FP32_INNER)),
              ("compact HWENO, FP64", dict(scheme=hgks.HWENO))]
     out = []
     for name, opts in forms:

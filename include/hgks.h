@@ -69,6 +69,10 @@ typedef struct {
   double fd_sigma;       /* FD step of Eq. (frechet); 0 = sqrt(eps) max(1,rms Q)/rms v */
   double cfl_flux;       /* CFL number of the time interval the flux is averaged over
                             (Sec. 4.1); default 1; 0 = the implicit step's cfl */
+  double cfl_start;      /* hgks_solve_steady only: CFL of its first step, multiplied by
+                            cfl_growth after every step up to cfl; 0 (default) = cfl
+                            throughout, as in the paper */
+  double cfl_growth;     /* default 1.5 */
   void* stream;          /* hipStream_t to run on; NULL = library-owned stream */
 } hgks_options;
 

@@ -95,6 +95,7 @@ struct hgks_ctx {
   double* sc = nullptr;     // device scalars [64]
   int* flags = nullptr;     // [0] positivity fallbacks, [1] bad state
   double res0 = -1.0;
+  double cfl_now = 10.0;  // CFL of the local time steps (o.cfl, or the ramp of solve_steady)
   // timing of the residual kernels: a pool of event sextets recorded on the
   // stream, drained (one synchronisation) when full or when read
   bool prof = false;
@@ -149,7 +150,7 @@ void set_params(hgks_ctx* ctx) {
   P.weno_eps = o.weno_eps;
   P.mu = o.mu;
   P.prandtl = o.prandtl;
-  P.flux_scale = o.cfl_flux > 0.0 ? o.cfl_flux / o.cfl : 1.0;
+  P.flux_scale = o.cfl_flux > 0.0 ? o.cfl_flux / ctx->cfl_now : 1.0;
   P.rhoinf = ctx->prim_inf[0];
   P.uinf0 = ctx->prim_inf[1];
   P.uinf1 = ctx->prim_inf[2];
@@ -261,7 +262,7 @@ hgks_status ensure_f32(hgks_ctx* ctx) {
   DevMesh<float>& Mf = ctx->Mf;
   const DevMesh<double>& M = ctx->M;
   Mf.N = M.N; Mf.F = M.F; Mf.Nb = M.Nb; Mf.NX = M.NX;
-  Mf.fL = M.fL; Mf.fR = M.fR; Mf.ford = M.ford; Mf.rpos = M.rpos; Mf.fkind = M.fkind; Mf.cface = M.cface; Mf.gowner = M.gowner; Mf.gface = M.gface;
+  Mf.fL = M.fL; Mf.fR = M.fR; Mf.fkind = M.fkind; Mf.cface = M.cface; Mf.gowner = M.gowner; Mf.gface = M.gface;
   Mf.stn = M.stn; Mf.sstn = M.sstn; Mf.smask = M.smask; Mf.nb4 = M.nb4;
   TRY(upload_mesh_fp<float>(ctx, Mf));
   TRY(alloc_work<float>(ctx, ctx->W32));
@@ -320,7 +321,7 @@ hgks_status prepare_base(hgks_ctx* ctx, bool want_grad, hipStream_t s) {
   HIPCHK(hipMemsetAsync(ctx->flags, 0, 2 * sizeof(int), s));
   expand_state(ctx, ctx->Qc, s);
   launch_ghost<double>(ctx->M, ctx->P, ctx->W64.Qx, (double*)nullptr, s);
-  launch_dt<double>(ctx->M, ctx->P, ctx->o.cfl, ctx->W64.Qx, ctx->W64.dt, s);
+  launch_dt<double>(ctx->M, ctx->P, ctx->cfl_now, ctx->W64.Qx, ctx->W64.dt, s);
   residual_pipeline<double, double>(ctx, ctx->M, ctx->W64, ctx->W64.Qx, ctx->W64.dt, want_grad ? 2 : 0, ctx->b,
                                     (const double*)nullptr, (const double*)nullptr, (const double*)nullptr,
                                     want_grad ? ctx->Gnew : (double*)nullptr, s);
@@ -330,7 +331,7 @@ hgks_status prepare_base(hgks_ctx* ctx, bool want_grad, hipStream_t s) {
   if (ctx->o.precision == HGKS_FP32_INNER) {
     TRY(ensure_f32(ctx));
     launch_perturb<float>(ctx->Qc, nullptr, nullptr, N, NX, ctx->W32.Qx, s);
-    launch_dt<float>(ctx->Mf, ctx->P, ctx->o.cfl, ctx->W32.Qx, ctx->W32.dt, s);
+    launch_dt<float>(ctx->Mf, ctx->P, ctx->cfl_now, ctx->W32.Qx, ctx->W32.dt, s);
     residual_pipeline<float, double>(ctx, ctx->Mf, ctx->W32, ctx->W32.Qx, ctx->W32.dt, 0, ctx->b32,
                                      (const double*)nullptr, (const double*)nullptr, (const double*)nullptr,
                                      (double*)nullptr, s);
@@ -415,6 +416,8 @@ void hgks_default_options(hgks_options* o) {
   o->prandtl = 1.0;
   o->fd_sigma = 0.0;
   o->cfl_flux = 1.0;
+  o->cfl_start = 0.0;
+  o->cfl_growth = 1.5;
   o->stream = nullptr;
 }
 
@@ -429,6 +432,7 @@ hgks_status hgks_create(const hgks_options* opts, hgks_ctx** out) {
   hgks_ctx* ctx = new (std::nothrow) hgks_ctx;
   if (!ctx) return HGKS_ENOMEM;
   ctx->o = *opts;
+  ctx->cfl_now = opts->cfl;
   for (int k = 0; k < 256; ++k) ctx->kind_of_tag[k] = HGKS_FARFIELD;
   if (opts->stream) {
     ctx->stream = (hipStream_t)opts->stream;
@@ -466,8 +470,6 @@ hgks_status hgks_load_mesh(hgks_ctx* ctx, int64_t n_nodes, const double* xyz, in
   M.NX = H.N + H.Nb;
   TRY(upload(ctx, H.fL, M.fL));
   TRY(upload(ctx, H.fR, M.fR));
-  TRY(upload(ctx, H.ford, M.ford));
-  TRY(upload(ctx, H.rpos, M.rpos));
   TRY(upload(ctx, H.cface, M.cface));
   TRY(upload(ctx, H.gowner, M.gowner));
   TRY(upload(ctx, H.gface, M.gface));
@@ -603,7 +605,7 @@ hgks_status hgks_time_step(hgks_ctx* ctx, const double* Q, double* dt) {
     ctx->have_state = true;
   }
   expand_state(ctx, ctx->Qc, s);
-  launch_dt<double>(ctx->M, ctx->P, ctx->o.cfl, ctx->W64.Qx, ctx->W64.dt, s);
+  launch_dt<double>(ctx->M, ctx->P, ctx->cfl_now, ctx->W64.Qx, ctx->W64.dt, s);
   HIPCHK(hipMemcpyAsync(dt, ctx->W64.dt, (size_t)ctx->H.N * sizeof(double), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
   return HGKS_OK;
@@ -756,9 +758,17 @@ hgks_status hgks_solve_steady(hgks_ctx* ctx, double drop, int32_t max_steps, hgk
   hgks_solve_info si{};
   ctx->res0 = -1.0;
   hgks_status st = HGKS_OK;
+  // optional CFL ramp from an impulsive start
+  const bool ramp = ctx->o.cfl_start > 0.0 && ctx->o.cfl_start < ctx->o.cfl;
+  ctx->cfl_now = ramp ? ctx->o.cfl_start : ctx->o.cfl;
+  set_params(ctx);
   for (int k = 0; k < max_steps; ++k) {
     hgks_step_info s{};
     st = hgks_implicit_step(ctx, &s);
+    if (ramp && ctx->cfl_now < ctx->o.cfl) {
+      ctx->cfl_now = std::min(ctx->o.cfl, ctx->cfl_now * std::max(1.0, ctx->o.cfl_growth));
+      set_params(ctx);
+    }
     si.steps = k + 1;
     si.n_resid_evals += s.n_resid_evals;
     if (k == 0) si.res0 = s.res;
@@ -892,7 +902,7 @@ hgks_status hgks_residual_dev(hgks_ctx* ctx, const void* Q_dev, void* R_dev, voi
   TRY(sync_kinds(ctx));
   expand_state(ctx, (const double*)Q_dev, s);
   launch_ghost<double>(ctx->M, ctx->P, ctx->W64.Qx, (double*)nullptr, s);
-  launch_dt<double>(ctx->M, ctx->P, ctx->o.cfl, ctx->W64.Qx, ctx->W64.dt, s);
+  launch_dt<double>(ctx->M, ctx->P, ctx->cfl_now, ctx->W64.Qx, ctx->W64.dt, s);
   residual_pipeline<double, double>(ctx, ctx->M, ctx->W64, ctx->W64.Qx, ctx->W64.dt, 0, (double*)R_dev,
                                     (const double*)nullptr, (const double*)nullptr, (const double*)nullptr,
                                     (double*)nullptr, s);

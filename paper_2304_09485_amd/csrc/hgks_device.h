@@ -20,8 +20,6 @@ struct DevMesh {
   const T* m2s;        // [6][N] second central moments / h^2 (xx,yy,zz,xy,xz,yz)
   const int* fL;       // [F]
   const int* fR;       // [F]   >= N: ghost N+g
-  const int* ford;     // [F]   faces ordered by right cell (boundary faces last)
-  const int* rpos;     // [F]   position of a face in ford
   const int* fkind;    // [F]   boundary kind, -1 interior
   const T* fn;         // [3][F] unit normal L -> R
   const T* fS;         // [F]

@@ -335,7 +335,7 @@ __global__ void __launch_bounds__(64) k_flux(DevMesh<T> M, Params P, const T* __
                  ui[0] * t2[0] + ui[1] * t2[1] + ui[2] * t2[2]};
       boundary_right(M.fkind[f], Wl, dWl, ul, T(P.rhoinf), T(P.pinf), fp.gamma, Wr, dWr);
     } else {
-      const size_t rc = (size_t)F + M.rpos[f];  // column of the right side
+      const size_t rc = (size_t)F + f;  // column of the right side
 #pragma unroll
       for (int v = 0; v < 5; ++v) {
         Wr[v] = sv[(size_t)((gp * 4 + 0) * 5 + v) * ld + rc];

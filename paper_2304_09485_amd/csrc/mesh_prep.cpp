@@ -323,15 +323,6 @@ int build_host_mesh(HostMesh& H, int64_t n_nodes, const double* xyz, int64_t n_t
       ++g;
     }
   }
-  // faces ordered by right cell (boundary faces, whose right cell is a ghost,
-  // come last): the right sides are reconstructed in this order, so that a
-  // wavefront's loads of right-cell data are coalesced as well
-  H.ford.resize(F);
-  H.rpos.resize(F);
-  for (int f = 0; f < F; ++f) H.ford[f] = f;
-  std::sort(H.ford.begin(), H.ford.end(),
-            [&](int a, int b) { return H.fR[a] != H.fR[b] ? H.fR[a] < H.fR[b] : a < b; });
-  for (int k = 0; k < F; ++k) H.rpos[H.ford[k]] = k;
   H.h.resize(N);
   H.hdt.resize(N);
   H.m2s.resize((size_t)6 * N);

@@ -16,7 +16,6 @@ struct HostMesh {
   std::vector<double> cen;               // [3][N]
   // faces
   std::vector<int> fL, fR, ftag;         // ftag: boundary tag or -1
-  std::vector<int> ford, rpos;           // faces ordered by right cell, and the inverse
   std::vector<double> fn, fS, fxiL, fxiR;// fn [3][F], fxi [9][F]
   std::vector<int> cface;                // [4][N]
   // ghosts

@@ -5,8 +5,7 @@
 // components are taken in turn (projection of the side cell's 21 coefficient
 // vectors, smoothness indicators, nonlinear weights, combined polynomial at
 // the Gauss points) and accumulated into the 60 outputs through R*.
-// sv layout [60][2F], row (g*4+d)*5+v; column f for the left side of face f,
-// column F + rpos[f] for its right side.
+// sv layout [60][2F], row (g*4+d)*5+v, column side*F+f.
 // Included inside namespace hgks of hgks_kernels.hip.
 #pragma once
 
@@ -21,9 +20,7 @@ __global__ void __launch_bounds__(128) k_side(DevMesh<T> M, Params P, const T* _
   const int F = M.F, N = M.N, NX = M.NX;
   if (sidx >= 2 * F) return;
   int side = sidx >= F;
-  // left sides in face order, right sides in right-cell order (column F + k
-  // holds the right side of face ford[k])
-  int f = side ? M.ford[sidx - F] : sidx;
+  int f = side ? sidx - F : sidx;
   int L = M.fL[f], R = M.fR[f];
   if (side && R >= N) return;
   int i = side ? R : L, j = side ? L : R;
@@ -52,17 +49,7 @@ __global__ void __launch_bounds__(128) k_side(DevMesh<T> M, Params P, const T* _
   T p = (g - T(1)) * (qs[4] - T(0.5) * rho * q2);
   T c = sqrt(g * p / rho);
   T H = (qs[4] + p) / rho;
-  T Rv[5][5] = {{T(1), T(1), T(0), T(0), T(1)},
-                {u - c, u, T(0), T(0), u + c},
-                {vv, vv, T(1), T(0), vv},
-                {w, w, T(0), T(1), w},
-                {H - u * c, T(0.5) * q2, vv, w, H + u * c}};
-  T b1 = (g - T(1)) / (c * c), b2 = T(0.5) * b1 * q2, ic = T(1) / c;
-  T Lv[5][5] = {{T(0.5) * (b2 + u * ic), T(0.5) * (-b1 * u - ic), T(-0.5) * b1 * vv, T(-0.5) * b1 * w, T(0.5) * b1},
-                {T(1) - b2, b1 * u, b1 * vv, b1 * w, -b1},
-                {-vv, T(0), T(1), T(0), T(0)},
-                {-w, T(0), T(0), T(1), T(0)},
-                {T(0.5) * (b2 - u * ic), T(0.5) * (-b1 * u + ic), T(-0.5) * b1 * vv, T(-0.5) * b1 * w, T(0.5) * b1}};
+  const T b1 = (g - T(1)) / (c * c), b2 = T(0.5) * b1 * q2, ic = T(1) / c;
   const T hh = M.h[i];
   const T ih = T(1) / hh;
   T m2[6];
@@ -84,11 +71,40 @@ __global__ void __launch_bounds__(128) k_side(DevMesh<T> M, Params P, const T* _
 #pragma unroll
       for (int v = 0; v < 5; ++v) out[a][d][v] = T(0);
   for (int cc = 0; cc < 5; ++cc) {
+    // row cc of L* = R*^{-1} and column cc of R* (x-split Euler eigenvectors
+    // at Q*, columns u-c, u, u, u, u+c), built from the eigen-system scalars
+    // (no per-lane matrices: indexing those by cc would put them in scratch)
+    T l[5], r[5];
+    switch (cc) {
+      case 0:
+        l[0] = T(0.5) * (b2 + u * ic); l[1] = T(0.5) * (-b1 * u - ic); l[2] = T(-0.5) * b1 * vv;
+        l[3] = T(-0.5) * b1 * w; l[4] = T(0.5) * b1;
+        r[0] = T(1); r[1] = u - c; r[2] = vv; r[3] = w; r[4] = H - u * c;
+        break;
+      case 1:
+        l[0] = T(1) - b2; l[1] = b1 * u; l[2] = b1 * vv; l[3] = b1 * w; l[4] = -b1;
+        r[0] = T(1); r[1] = u; r[2] = vv; r[3] = w; r[4] = T(0.5) * q2;
+        break;
+      case 2:
+        l[0] = -vv; l[1] = T(0); l[2] = T(1); l[3] = T(0); l[4] = T(0);
+        r[0] = T(0); r[1] = T(0); r[2] = T(1); r[3] = T(0); r[4] = vv;
+        break;
+      case 3:
+        l[0] = -w; l[1] = T(0); l[2] = T(0); l[3] = T(1); l[4] = T(0);
+        r[0] = T(0); r[1] = T(0); r[2] = T(0); r[3] = T(1); r[4] = w;
+        break;
+      default:
+        l[0] = T(0.5) * (b2 - u * ic); l[1] = T(0.5) * (-b1 * u + ic); l[2] = T(-0.5) * b1 * vv;
+        l[3] = T(-0.5) * b1 * w; l[4] = T(0.5) * b1;
+        r[0] = T(1); r[1] = u + c; r[2] = vv; r[3] = w; r[4] = H + u * c;
+        break;
+    }
     // row cc of T = L* . Rot
     T tc[5];
-    tc[0] = Lv[cc][0];
-    tc[4] = Lv[cc][4];
-    for (int d = 0; d < 3; ++d) tc[1 + d] = Lv[cc][1] * e[0][d] + Lv[cc][2] * e[1][d] + Lv[cc][3] * e[2][d];
+    tc[0] = l[0];
+    tc[4] = l[4];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) tc[1 + d] = l[1] * e[0][d] + l[2] * e[1][d] + l[3] * e[2][d];
     T q0 = tc[0] * qi[0] + tc[1] * qi[1] + tc[2] * qi[2] + tc[3] * qi[3] + tc[4] * qi[4];
     T a[9], b[4][3];
 #pragma unroll
@@ -167,7 +183,7 @@ __global__ void __launch_bounds__(128) k_side(DevMesh<T> M, Params P, const T* _
 #pragma unroll
       for (int d = 0; d < 4; ++d)
 #pragma unroll
-        for (int v = 0; v < 5; ++v) out[gp][d][v] += Rv[v][cc] * dd[d];
+        for (int v = 0; v < 5; ++v) out[gp][d][v] += r[v] * dd[d];
     }
   }
   bool ok = phys_ok(out[0][0], g) && phys_ok(out[1][0], g) && phys_ok(out[2][0], g);

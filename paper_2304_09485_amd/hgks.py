@@ -46,7 +46,8 @@ class Options(ctypes.Structure):
                 ("gamma", ctypes.c_double), ("cfl", ctypes.c_double), ("tau_eps", ctypes.c_double),
                 ("tau_C", ctypes.c_double), ("gamma_lin", ctypes.c_double), ("weno_eps", ctypes.c_double),
                 ("mu", ctypes.c_double), ("prandtl", ctypes.c_double), ("fd_sigma", ctypes.c_double),
-                ("cfl_flux", ctypes.c_double), ("stream", ctypes.c_void_p)]
+                ("cfl_flux", ctypes.c_double), ("cfl_start", ctypes.c_double), ("cfl_growth", ctypes.c_double),
+                ("stream", ctypes.c_void_p)]
 
 
 class StepInfo(ctypes.Structure):

@@ -1,0 +1,73 @@
+"""Converged fields: the steady state the HIP path reaches is a steady state of
+the oracle, and the mixed-precision form reaches the same drop.
+
+The 202,752-tet sphere shell (inviscid Mach 0.5, slip wall, far field,
+non-compact WENO) converges to a 1e-8 residual drop in about 160 implicit
+steps on the GPU.  The oracle then certifies the result at full size: its own
+residual at the GPU's converged state has dropped by the same factor (up to
+the round-off of the two residual sums) from its residual at the uniform
+start, and one oracle implicit step from that state
+moves it by less than 1e-9 relative (the state is a fixed point of the
+oracle's iteration to that tolerance).
+"""
+import numpy as np
+import pytest
+
+from inputs import freestream_prim, mesh_for_config, uniform_state
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def c2():
+    return mesh_for_config("c2")
+
+
+def _solve(hgks, mesh, **opts):
+    prim = freestream_prim(0.5)
+    s = hgks.Solver(mesh, {1: hgks.SLIP_WALL, 2: hgks.FARFIELD}, prim, **opts)
+    s.set_state(uniform_state(s.N, prim))
+    info = s.solve_steady(drop=1e-8, max_steps=400)
+    Q = s.get_state()
+    s.close()
+    return info, Q
+
+
+def test_converged_state_is_an_oracle_steady_state(oracle_lib, c2):
+    from paper_2304_09485_amd import hgks
+    info, Q = _solve(hgks, c2)
+    print(f"GPU: {info.steps} steps, drop {info.drop:.3e}, {info.t_ms / 1e3:.2f} s")
+    assert info.converged and info.drop <= 1e-8
+    prim = freestream_prim(0.5)
+    oracle_lib.set_threads(16)
+    try:
+        o = oracle_lib.Oracle(c2, {1: 1, 2: 0}, prim)
+        r0 = o.res_norm(o.residual(uniform_state(o.N, prim)))
+        r1 = o.res_norm(o.residual(Q))
+        print(f"oracle: residual drop at the GPU's state {r1 / r0:.3e}")
+        # per cell the two residuals differ by round-off, ~1e-15 x the cell's
+        # face fluxes; summed over 202,752 cells that is ~1e-9 of the L1
+        # norm's units, about 10 % of the converged residual: allow 2e-8
+        assert r1 / r0 <= 2e-8
+        Qo = Q.copy()
+        st, io = o.implicit_step(Qo)
+        move = np.abs(Qo - Q).max() / np.abs(Q).max()
+        print(f"oracle step from the GPU's state: status {st}, relative move {move:.3e}")
+        assert st == 0 and move <= 1e-9
+    finally:
+        oracle_lib.set_threads(1)
+
+
+def test_fp32_inner_reaches_the_same_drop_with_linear_weights(c2):
+    """With linear weights the FP32-inner / FP64-outer form converges like the
+    plain FP64 form: same 1e-8 drop, step counts within 5 %, and the two
+    converged states agree to the accuracy the drop allows."""
+    from paper_2304_09485_amd import hgks
+    i64, Q64 = _solve(hgks, c2, weights=hgks.WEIGHTS_LINEAR)
+    i32, Q32 = _solve(hgks, c2, weights=hgks.WEIGHTS_LINEAR, precision=hgks.FP32_INNER)
+    diff = np.abs(Q64 - Q32).max() / np.abs(Q64).max()
+    print(f"FP64: {i64.steps} steps {i64.t_ms / 1e3:.2f} s; FP32-inner: {i32.steps} steps {i32.t_ms / 1e3:.2f} s; "
+          f"field difference {diff:.3e}")
+    assert i64.converged and i32.converged
+    assert abs(i32.steps - i64.steps) <= 0.05 * i64.steps + 1
+    assert diff <= 1e-6
