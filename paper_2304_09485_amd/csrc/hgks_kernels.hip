@@ -19,6 +19,18 @@
 
 namespace hgks {
 
+// Workgroups are dispatched to the 8 XCDs of the chip in turn (workgroup b to
+// XCD b mod 8), and each XCD has its own L2.  Kernels whose neighbouring
+// workgroups read neighbouring cache lines map the dispatch index to a
+// logical block so that each XCD works on one contiguous range of blocks:
+// a bijection of [0, nb).
+constexpr int NUM_XCD = 8;
+__device__ __forceinline__ int xcd_block() {
+  const int nb = (int)gridDim.x, b = (int)blockIdx.x;
+  const int q = nb / NUM_XCD, r = nb % NUM_XCD, x = b % NUM_XCD;
+  return x * q + min(x, r) + b / NUM_XCD;
+}
+
 // ---------------------------------------------------------------------------
 // boundary states
 // ---------------------------------------------------------------------------
@@ -302,7 +314,7 @@ __global__ void __launch_bounds__(64) k_flux(DevMesh<T> M, Params P, const T* __
   __shared__ T red[QG ? 10 : 5][64];
   const int F = M.F, N = M.N;
   const int lane = threadIdx.x;
-  const int f = blockIdx.x * FLUX_FPB + lane / 3;
+  const int f = xcd_block() * FLUX_FPB + lane / 3;  // contiguous face ranges per XCD
   const int gp = lane % 3;
   const bool active = lane < 3 * FLUX_FPB && f < F;
   T Fg[5] = {0, 0, 0, 0, 0}, Qg[5] = {0, 0, 0, 0, 0};

@@ -16,7 +16,7 @@ template <typename T>
 __global__ void __launch_bounds__(128) k_side(DevMesh<T> M, Params P, const T* __restrict__ Qx,
                                               const T* __restrict__ coef, T* __restrict__ sv,
                                               int* __restrict__ nfall) {
-  int sidx = blockIdx.x * blockDim.x + threadIdx.x;
+  int sidx = xcd_block() * blockDim.x + threadIdx.x;  // contiguous side ranges per XCD
   const int F = M.F, N = M.N, NX = M.NX;
   if (sidx >= 2 * F) return;
   int side = sidx >= F;
