@@ -85,9 +85,11 @@ def algorithmic_bytes(kernel, N, F, Nb, scheme):
         # ids; 60 values written per reconstructed side
         return N * 8 * (105 + 7) + NX * 8 * 5 + F * (8 * 21 + 8) + sides * 8 * 60
     if kernel == "flux":
-        # 60 side values per side read, 15 flux values (3 GPs x 5) per face
-        # written, time steps of the two cells (+ 15 gradient-update values)
-        return sides * 8 * 60 + F * 8 * (15 + 2) + (F * 8 * 15 if scheme == 1 else 0)
+        # 60 side values per reconstructed side read; per face the two cell
+        # ids, the two cells' time steps, 5 face-flux values written (the
+        # base evaluation of the compact scheme, 1 launch in 33, also writes
+        # 5 point-value sums: not counted)
+        return sides * 8 * 60 + F * (8 + 8 * 2 + 8 * 5)
     if kernel == "gather":
         # per cell 4 face ids, 4 face fluxes (5 values) read, 5 values written
         return N * (4 * 4 + 4 * 5 * 8 + 5 * 8)
