@@ -654,6 +654,7 @@ hgks_status hgks_implicit_step(hgks_ctx* ctx, hgks_step_info* info) {
   HIPCHK(hipMemsetAsync(ctx->dQ, 0, n * sizeof(double), s));
   const int m = ctx->o.krylov_dim;
   double beta0 = -1.0, last = 0.0;
+  bool nonfinite = false;  // a NaN/Inf in the residual or the preconditioned residual
   double* hc = ctx->sc + 8;  // device column of H (m+1 entries)
   for (int rs = 0; rs < ctx->o.restarts; ++rs) {
     if (rs == 0) {
@@ -673,6 +674,10 @@ hgks_status hgks_implicit_step(hgks_ctx* ctx, hgks_step_info* info) {
     HIPCHK(hipMemcpyAsync(&beta, ctx->sc + 5, sizeof(double), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     if (beta0 < 0) beta0 = beta;
+    if (!std::isfinite(beta)) {
+      nonfinite = true;
+      break;
+    }
     if (!(beta > 0.0)) break;
     launch_scale_inv(ctx->wv, ctx->V, n, ctx->sc + 5, s);
     std::vector<double> H((size_t)(m + 1) * m, 0.0), cs(m), sn(m), gv(m + 1, 0.0);
@@ -693,7 +698,11 @@ hgks_status hgks_implicit_step(hgks_ctx* ctx, hgks_step_info* info) {
       std::vector<double> col(j + 2);
       HIPCHK(hipMemcpyAsync(col.data(), hc, (j + 2) * sizeof(double), hipMemcpyDeviceToHost, s));
       HIPCHK(hipStreamSynchronize(s));
-      for (int i = 0; i <= j + 1; ++i) H[(size_t)i * m + j] = col[i];
+      for (int i = 0; i <= j + 1; ++i) {
+        if (!std::isfinite(col[i])) nonfinite = true;
+        H[(size_t)i * m + j] = col[i];
+      }
+      if (nonfinite) break;  // an FD product produced NaN/Inf: no update from this cycle
       double hn = col[j + 1];
       // Givens rotations (host, FP64)
       for (int i = 0; i < j; ++i) {
@@ -713,6 +722,7 @@ hgks_status hgks_implicit_step(hgks_ctx* ctx, hgks_step_info* info) {
       if (hn <= 1e-14 * beta) break;  // happy breakdown
       launch_scale_inv(ctx->wv, ctx->V + (size_t)(j + 1) * n, n, hc + j + 1, s);
     }
+    if (nonfinite) break;
     std::vector<double> y(jdone, 0.0);
     for (int i = jdone - 1; i >= 0; --i) {
       double sacc = gv[i];
@@ -723,6 +733,15 @@ hgks_status hgks_implicit_step(hgks_ctx* ctx, hgks_step_info* info) {
     launch_combine(ctx->V, ctx->sc + 48, jdone, n, ctx->dQ, ctx->dQ, s);
     last = std::fabs(gv[jdone]);
     HIPCHK(hipStreamSynchronize(s));  // y is a host array
+  }
+  // res_abs was read back before the first restart's synchronisation
+  if (nonfinite || !std::isfinite(res_abs)) {
+    if (info) {
+      info->res = res_abs / ctx->H.total_volume;
+      info->n_resid_evals = evals;
+    }
+    ctx->err = "non-finite residual (NaN or Inf in L(Q^n) or its GMRES solve); the state was not updated";
+    return HGKS_ESTATE;
   }
   // Q^{n+1} = Q^n + dQ
   double one = 1.0;
