@@ -54,7 +54,8 @@ class Options(ctypes.Structure):
                 ("jacobi_sweeps", ctypes.c_int32), ("gamma", ctypes.c_double), ("cfl", ctypes.c_double),
                 ("tau_eps", ctypes.c_double), ("tau_C", ctypes.c_double), ("gamma_lin", ctypes.c_double),
                 ("weno_eps", ctypes.c_double), ("mu", ctypes.c_double), ("prandtl", ctypes.c_double),
-                ("fd_sigma", ctypes.c_double), ("cfl_flux", ctypes.c_double)]
+                ("fd_sigma", ctypes.c_double), ("cfl_flux", ctypes.c_double), ("jv_mode", ctypes.c_int32),
+                ("pad", ctypes.c_int32)]
 
 
 class StepInfo(ctypes.Structure):
@@ -96,6 +97,7 @@ def _declare(L):
     L.orc_euler_jn.argtypes = [_d, _vp, _vp, _vp, _vp]
     L.orc_diag.argtypes = [_vp, _vp, _vp, _vp]
     L.orc_precond.argtypes = [_vp, _vp, _vp, _vp, _vp]
+    L.orc_amatvec.argtypes = [_vp, _vp, _vp, _vp, _vp]
     L.orc_jv.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, _d, _vp]
     L.orc_jv.restype = _d
     L.orc_implicit_step.argtypes = [_vp, _vp, _vp, _P(StepInfo)]
@@ -115,7 +117,7 @@ def _f64(a):
 def default_options(**kw) -> Options:
     o = Options(scheme=WENO, physics=EULER, weights=0, krylov_dim=10, restarts=3, jacobi_sweeps=2,
                 gamma=1.4, cfl=10.0, tau_eps=0.1, tau_C=1.0, gamma_lin=0.025, weno_eps=1e-8,
-                mu=0.0, prandtl=1.0, fd_sigma=0.0, cfl_flux=1.0)
+                mu=0.0, prandtl=1.0, fd_sigma=0.0, cfl_flux=1.0, jv_mode=0)
     for k, v in kw.items():
         setattr(o, k, v)
     return o
@@ -229,6 +231,13 @@ class Oracle:
         Q, dt, r = _f64(Q), _f64(dt), _f64(r)
         out = np.zeros((5, self.N))
         _load().orc_precond(self.h, _ptr(Q), _ptr(dt), _ptr(r), _ptr(out))
+        return out
+
+    def amatvec(self, Q, dt, x):
+        """A x with the approximate matrix of Eq. (deri-matrix)."""
+        Q, dt, x = _f64(Q), _f64(dt), _f64(x)
+        out = np.zeros((5, self.N))
+        _load().orc_amatvec(self.h, _ptr(Q), _ptr(dt), _ptr(x), _ptr(out))
         return out
 
     def jv(self, Q, dt, b, v, sigma=0.0, G=None):

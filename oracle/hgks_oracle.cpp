@@ -1078,6 +1078,34 @@ static void precond(const orc_ctx& C, const double* Q, const double* dt, const d
   std::copy(b.begin(), b.end(), out);
 }
 
+// A x with the approximate matrix of Eq. (deri-matrix): the diagonal D plus
+// the off-diagonal blocks 1/2 S_f (J_n(Q_j) - |lambda_f| I) of interior faces
+static void amatvec(const orc_ctx& C, const double* Q, const double* dt, const double* x, double* out) {
+  int N = C.N;
+  std::vector<double> D(N), lam(C.faces.size());
+  diag(C, Q, dt, D.data());
+  for (size_t f = 0; f < C.faces.size(); ++f) lam[f] = face_lambda(C, Q, (int)f);
+  for (int i = 0; i < N; ++i) {
+    V5 acc;
+    for (int v = 0; v < 5; ++v) acc[v] = D[i] * x[(size_t)v * N + i];
+    for (int p = 0; p < 4; ++p) {
+      const Face& f = C.faces[C.cf[i][p]];
+      if (f.R < 0) continue;  // boundary off-diagonal dropped (A23)
+      int j = f.L == i ? f.R : f.L;
+      V3 nout = f.L == i ? f.n : scl(-1.0, f.n);
+      V5 qj, xj;
+      for (int v = 0; v < 5; ++v) {
+        qj[v] = Q[(size_t)v * N + j];
+        xj[v] = x[(size_t)v * N + j];
+      }
+      V5 jx = euler_jn(C.o.gamma, qj, nout, xj);
+      double l = lam[C.cf[i][p]];
+      for (int v = 0; v < 5; ++v) acc[v] += 0.5 * f.S * (jx[v] - l * xj[v]);
+    }
+    for (int v = 0; v < 5; ++v) out[(size_t)v * N + i] = acc[v];
+  }
+}
+
 static double rms(const double* x, size_t n) {
   double s = 0.0;
   for (size_t k = 0; k < n; ++k) s += x[k] * x[k];
@@ -1302,8 +1330,12 @@ static int implicit_step(const orc_ctx& C, double* Q, double* G, orc_step_info* 
     if (rs == 0) {
       r = b;  // Delta Q^(0) = 0
     } else {
-      jv(C, Q, G, dt.data(), b.data(), dQ.data(), C.o.fd_sigma, y.data());
-      ++evals;
+      if (C.o.jv_mode == 1) {
+        amatvec(C, Q, dt.data(), dQ.data(), y.data());
+      } else {
+        jv(C, Q, G, dt.data(), b.data(), dQ.data(), C.o.fd_sigma, y.data());
+        ++evals;
+      }
       for (size_t k = 0; k < n; ++k) r[k] = b[k] - y[k];
     }
     precond(C, Q, dt.data(), r.data(), rh.data());
@@ -1315,8 +1347,12 @@ static int implicit_step(const orc_ctx& C, double* Q, double* G, orc_step_info* 
     gvec[0] = beta;
     int jdone = 0;
     for (int j = 0; j < m; ++j) {
-      jv(C, Q, G, dt.data(), b.data(), V[j].data(), C.o.fd_sigma, y.data());
-      ++evals;
+      if (C.o.jv_mode == 1) {
+        amatvec(C, Q, dt.data(), V[j].data(), y.data());
+      } else {
+        jv(C, Q, G, dt.data(), b.data(), V[j].data(), C.o.fd_sigma, y.data());
+        ++evals;
+      }
       precond(C, Q, dt.data(), y.data(), w.data());
       for (int i = 0; i <= j; ++i) {
         double h = dotv(w, V[i]);
@@ -1516,5 +1552,8 @@ int32_t orc_implicit_step(const orc_ctx* C, double* Q, double* G, orc_step_info*
   return implicit_step(*C, Q, G, info);
 }
 double orc_res_norm(const orc_ctx* C, const double* R) { return res_norm(*C, R); }
+void orc_amatvec(const orc_ctx* C, const double* Q, const double* dt, const double* x, double* out) {
+  amatvec(*C, Q, dt, x, out);
+}
 
 }  // extern "C"

@@ -38,6 +38,9 @@ typedef struct {
   double prandtl;        /* NS */
   double fd_sigma;       /* 0 = automatic */
   double cfl_flux;       /* CFL of the flux time average; 0 = same as cfl */
+  int32_t jv_mode;       /* GMRES operator: 0 FD product of Eq. (frechet), 1 the approximate
+                            matrix A of Eq. (deri-matrix) */
+  int32_t pad;
 } orc_options;
 
 /* boundary kinds */
@@ -102,6 +105,8 @@ void orc_euler_jn(double gamma, const double* Q, const double* n, const double* 
 /* approximate-matrix pieces of Eq. (deri-matrix): D[N] and Jacobi P^{-1} */
 void orc_diag(const orc_ctx*, const double* Q, const double* dt, double* D);
 void orc_precond(const orc_ctx*, const double* Q, const double* dt, const double* r, double* out);
+/* A x with A = D + L + U of Eq. (deri-matrix) (boundary off-diagonal blocks dropped) */
+void orc_amatvec(const orc_ctx*, const double* Q, const double* dt, const double* x, double* out);
 
 /* FD Jacobian-vector product (|Omega|/dt) v - (L(Q + sigma v) - b)/sigma;
  * sigma <= 0 -> automatic; returns the sigma used */

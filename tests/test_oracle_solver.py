@@ -123,6 +123,52 @@ def test_jacobi_preconditioner(oracle_lib):
     for _ in range(2):
         x = (r - offdiag(x)) / D
     np.testing.assert_allclose(o.precond(Q, dt, r), x, rtol=1e-12, atol=1e-14 * np.abs(x).max())
+    # the approximate matrix itself (the GMRES operator of the paper's solver)
+    y = np.random.default_rng(1).normal(size=(5, N))
+    Ay = D * y + offdiag(y)
+    np.testing.assert_allclose(o.amatvec(Q, dt, y), Ay, rtol=1e-12, atol=1e-14 * np.abs(Ay).max())
+
+
+def test_gmres_on_the_approximate_matrix_equals_dense_solve(oracle_lib):
+    """With the paper's operator (Eq. (deri-matrix)) GMRES is a linear solve:
+    at full Krylov dimension one restart reproduces a dense solve of
+    A dQ = L(Q^n), A assembled column by column from an independent
+    complex-step Euler Jacobian, and evaluates the residual once."""
+    m = cube_mesh(1, jitter=0.1, seed=4)
+    prim = freestream_prim(0.3)
+    kinds = {t: oracle_lib.SUP_OUT for t in range(1, 7)}
+    o = oracle_lib.Oracle(m, kinds, prim, jv_mode=1, krylov_dim=30, restarts=1)
+    Q = perturbed_state(o.N, prim, amp=0.05, seed=3)
+    dt = o.dt(Q)
+    b = o.residual(Q, dt=dt)
+    vol = o.geometry()[0]
+    L, R, S, n, gp = o.faces()
+    N = o.N
+
+    def lam(a, c, nn):
+        ra, Ua, pa = I.prim(Q[:, a])
+        rb, Ub, pb = I.prim(Q[:, c])
+        rho, U, p = (ra + rb) / 2, (Ua + Ub) / 2, (pa + pb) / 2
+        return abs(U @ nn) + np.sqrt(1.4 * p / rho)
+    lam_f = np.array([lam(L[f], R[f] if R[f] >= 0 else L[f], n[:, f]) for f in range(len(L))])
+    D = vol / dt
+    np.add.at(D, L, 0.5 * lam_f * S)
+    np.add.at(D, R[R >= 0], 0.5 * lam_f[R >= 0] * S[R >= 0])
+    A = np.zeros((5 * N, 5 * N))
+    for k in range(5 * N):
+        e = np.zeros((5, N))
+        e.flat[k] = 1.0
+        out = D * e
+        for f in np.where(R >= 0)[0]:
+            a, c = L[f], R[f]
+            out[:, a] += 0.5 * S[f] * (I.euler_jn_cs(Q[:, c], n[:, f], e[:, c]) - lam_f[f] * e[:, c])
+            out[:, c] += 0.5 * S[f] * (I.euler_jn_cs(Q[:, a], -n[:, f], e[:, a]) - lam_f[f] * e[:, a])
+        A[:, k] = out.ravel()
+    ref = np.linalg.solve(A, b.ravel())
+    Q1 = Q.copy()
+    st, info = o.implicit_step(Q1)
+    assert st == 0 and info.n_resid_evals == 1 and info.gmres_rel < 1e-10
+    np.testing.assert_allclose((Q1 - Q).ravel(), ref, rtol=0, atol=1e-9 * np.abs(ref).max())
 
 
 def test_gmres_full_dimension_equals_dense_solve(oracle_lib):
