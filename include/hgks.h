@@ -46,6 +46,11 @@ enum { HGKS_WENO = 0, HGKS_HWENO = 1 };              /* Sec. 3.2 / Sec. 3.3 */
 enum { HGKS_EULER = 0, HGKS_NS = 1 };                /* collision time of Sec. 5 */
 enum { HGKS_FP64 = 0, HGKS_FP32_INNER = 1 };         /* arithmetic of the GMRES inner operator */
 enum { HGKS_WEIGHTS_NONLINEAR = 0, HGKS_WEIGHTS_LINEAR = 1 }; /* Sec. 3.4 */
+/* GMRES operator of the implicit step: the matrix-free FD product of the
+ * high-order residual, Eq. (frechet), or the first-order approximate matrix
+ * A of Eq. (deri-matrix), applied without being stored (the paper's solver,
+ * Sec. 4.2: one high-order residual evaluation per step) */
+enum { HGKS_JV_FD = 0, HGKS_JV_APPROX = 1 };
 enum { HGKS_FARFIELD = 0, HGKS_SLIP_WALL = 1, HGKS_NOSLIP_ADIABATIC = 2,
        HGKS_SUP_IN = 3, HGKS_SUP_OUT = 4 };          /* Sec. 5 boundary conditions */
 
@@ -57,7 +62,7 @@ typedef struct {
   int32_t krylov_dim;    /* 10, Sec. 5 (at most 32) */
   int32_t restarts;      /* 3, Sec. 5 */
   int32_t jacobi_sweeps; /* 2, Sec. 5 */
-  int32_t reserved;
+  int32_t jv_mode;       /* GMRES operator: HGKS_JV_FD (default) or HGKS_JV_APPROX */
   double gamma;          /* 1.4 */
   double cfl;            /* 10 */
   double tau_eps;        /* 0.1, inviscid collision time, Sec. 5 */
@@ -137,7 +142,9 @@ hgks_status hgks_time_step(hgks_ctx* ctx, const double* Q, double* dt);
 /* Finite-difference Jacobian-vector product of Eq. (frechet) at the current
  * state with the time step frozen at its value for the current state:
  * Av = (|Omega|/dt) v - (L(Q + sigma v) - L(Q)) / sigma.  sigma <= 0 selects
- * the automatic step.  Host arrays [5][N].  *sigma_used may be NULL. */
+ * the automatic step.  Host arrays [5][N].  *sigma_used may be NULL.
+ * With jv_mode = HGKS_JV_APPROX it returns A v with the approximate matrix
+ * of Eq. (deri-matrix) instead (*sigma_used = 0). */
 hgks_status hgks_jv(hgks_ctx* ctx, const double* v, double sigma, double* Av, double* sigma_used);
 
 /* Jacobi preconditioner of Eq. (precond) built on the approximate matrix of

@@ -281,6 +281,13 @@ hgks_status ensure_f32(hgks_ctx* ctx) {
 // the restart residual b - A dQ of the outer defect correction stays FP64.
 hgks_status jv_device(hgks_ctx* ctx, const double* v, double sigma_fixed, double* out, hipStream_t s,
                       bool inner = true) {
+  if (ctx->o.jv_mode == HGKS_JV_APPROX) {
+    // the approximate matrix at the base point (W64.Qx = Q^n, lam, D)
+    launch_amatvec<double>(ctx->M, ctx->P, ctx->W64.Qx, ctx->lam, ctx->D, v, out, s);
+    const double zero = 0.0;
+    HIPCHK(hipMemcpyAsync(ctx->sc + 2, &zero, sizeof(double), hipMemcpyHostToDevice, s));
+    return HGKS_OK;
+  }
   size_t n = n5(ctx);
   const int N = ctx->H.N, NX = ctx->H.N + ctx->H.Nb;
   launch_dot(v, v, n, ctx->part, ctx->sc + 1, false, s);
@@ -328,7 +335,7 @@ hgks_status prepare_base(hgks_ctx* ctx, bool want_grad, hipStream_t s) {
   // the pipeline rewrote the ghosts of W64.Qx from Q^n: still the base point
   launch_lambda_diag<double>(ctx->M, ctx->P, ctx->W64.Qx, ctx->W64.dt, ctx->lam, ctx->D, s);
   launch_dot(ctx->Qc, ctx->Qc, n5(ctx), ctx->part, ctx->sc + 0, false, s);
-  if (ctx->o.precision == HGKS_FP32_INNER) {
+  if (ctx->o.precision == HGKS_FP32_INNER && ctx->o.jv_mode == HGKS_JV_FD) {
     TRY(ensure_f32(ctx));
     launch_perturb<float>(ctx->Qc, nullptr, nullptr, N, NX, ctx->W32.Qx, s);
     launch_dt<float>(ctx->Mf, ctx->P, ctx->cfl_now, ctx->W32.Qx, ctx->W32.dt, s);
@@ -426,7 +433,7 @@ hgks_status hgks_create(const hgks_options* opts, hgks_ctx** out) {
   *out = nullptr;
   if (opts->krylov_dim < 1 || opts->krylov_dim > MAXM || opts->restarts < 1 || opts->jacobi_sweeps < 0 ||
       !(opts->gamma > 1.0) || !(opts->cfl > 0.0) || opts->scheme < 0 || opts->scheme > 1 || opts->physics < 0 ||
-      opts->physics > 1 || opts->precision < 0 || opts->precision > 1 ||
+      opts->physics > 1 || opts->precision < 0 || opts->precision > 1 || opts->jv_mode < 0 || opts->jv_mode > 1 ||
       (opts->physics == HGKS_NS && !(opts->mu > 0.0 && opts->prandtl > 0.0)))
     return HGKS_EINVAL;
   hgks_ctx* ctx = new (std::nothrow) hgks_ctx;
@@ -646,7 +653,8 @@ hgks_status hgks_implicit_step(hgks_ctx* ctx, hgks_step_info* info) {
   const int N = ctx->H.N;
   const bool hw = ctx->o.scheme == HGKS_HWENO;
   TRY(prepare_base(ctx, hw, s));
-  int64_t evals = ctx->o.precision == HGKS_FP32_INNER ? 2 : 1;
+  const bool fd = ctx->o.jv_mode == HGKS_JV_FD;
+  int64_t evals = (fd && ctx->o.precision == HGKS_FP32_INNER) ? 2 : 1;
   // residual norm of the base point (L1 density residual / total volume)
   launch_abssum(ctx->b, (size_t)N, ctx->part, ctx->sc + 3, s);
   double res_abs = 0.0;
@@ -661,7 +669,7 @@ hgks_status hgks_implicit_step(hgks_ctx* ctx, hgks_step_info* info) {
       HIPCHK(hipMemcpyAsync(ctx->rv, ctx->b, n * sizeof(double), hipMemcpyDeviceToDevice, s));
     } else {
       TRY(jv_device(ctx, ctx->dQ, ctx->o.fd_sigma, ctx->yv, s, false));
-      ++evals;
+      if (fd) ++evals;
       // r = b - A dQ (FP64 in both forms: the outer defect correction)
       HIPCHK(hipMemcpyAsync(ctx->rv, ctx->b, n * sizeof(double), hipMemcpyDeviceToDevice, s));
       double one = 1.0;
@@ -686,7 +694,7 @@ hgks_status hgks_implicit_step(hgks_ctx* ctx, hgks_step_info* info) {
     for (int j = 0; j < m; ++j) {
       double* vj = ctx->V + (size_t)j * n;
       TRY(jv_device(ctx, vj, ctx->o.fd_sigma, ctx->yv, s));
-      ++evals;
+      if (fd) ++evals;
       precond_device(ctx, ctx->yv, ctx->wv, s);
       // modified Gram-Schmidt
       for (int i = 0; i <= j; ++i) {

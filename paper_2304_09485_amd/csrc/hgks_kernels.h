@@ -23,6 +23,9 @@ template <typename T>
 void launch_jacobi(const DevMesh<T>&, const Params&, const T* Qx, const T* lam, const T* D, const double* r,
                    const double* xo, double* xn, hipStream_t);
 template <typename T>
+void launch_amatvec(const DevMesh<T>&, const Params&, const T* Qx, const T* lam, const T* D, const double* x,
+                    double* out, hipStream_t);
+template <typename T>
 void launch_perturb(const double* Q, const double* v, const double* sigma, int N, int NX, T* Qp, hipStream_t);
 template <typename T> void launch_check(const T* Qx, int N, int NX, double gamma, int* bad, hipStream_t);
 

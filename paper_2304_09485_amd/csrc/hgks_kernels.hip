@@ -515,6 +515,40 @@ __device__ __forceinline__ void euler_jn(T g, const T q[5], const T n[3], const 
 }
 
 // x_new = D^{-1} (r - (L+U) x_old); x_old == nullptr gives D^{-1} r
+// A x with the approximate matrix of Eq. (deri-matrix): D_i x_i plus the
+// off-diagonal blocks 1/2 S_f (J_n(Q_j) - |lambda_f|) x_j of the cell's
+// interior faces (boundary off-diagonal blocks dropped)
+template <typename T>
+__global__ void __launch_bounds__(256) k_amatvec(DevMesh<T> M, Params P, const T* __restrict__ Qx,
+                                                 const T* __restrict__ lam, const T* __restrict__ D,
+                                                 const double* __restrict__ x, double* __restrict__ out) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int N = M.N, NX = M.NX, F = M.F;
+  if (i >= N) return;
+  const T g = T(P.gamma);
+  T acc[5];
+  for (int v = 0; v < 5; ++v) acc[v] = D[i] * T(x[(size_t)v * N + i]);
+#pragma unroll
+  for (int p = 0; p < 4; ++p) {
+    int cf = M.cface[p * N + i];
+    int f = (cf > 0 ? cf : -cf) - 1;
+    int L = M.fL[f], R = M.fR[f];
+    if (R >= N) continue;
+    int jn = cf > 0 ? R : L;
+    T s = cf > 0 ? T(1) : T(-1);
+    T n[3] = {s * M.fn[f], s * M.fn[F + f], s * M.fn[2 * F + f]};
+    T qj[5], xj[5], jx[5];
+    for (int v = 0; v < 5; ++v) {
+      qj[v] = Qx[(size_t)v * NX + jn];
+      xj[v] = T(x[(size_t)v * N + jn]);
+    }
+    euler_jn(g, qj, n, xj, jx);
+    T hs = T(0.5) * M.fS[f], l = lam[f];
+    for (int v = 0; v < 5; ++v) acc[v] += hs * (jx[v] - l * xj[v]);
+  }
+  for (int v = 0; v < 5; ++v) out[(size_t)v * N + i] = double(acc[v]);
+}
+
 template <typename T>
 __global__ void __launch_bounds__(256) k_jacobi(DevMesh<T> M, Params P, const T* __restrict__ Qx,
                                                 const T* __restrict__ lam, const T* __restrict__ D,
@@ -719,6 +753,11 @@ void launch_jacobi(const DevMesh<T>& M, const Params& P, const T* Qx, const T* l
   hipLaunchKernelGGL(k_jacobi<T>, dim3(nblk(M.N, 256)), dim3(256), 0, s, M, P, Qx, lam, D, r, xo, xn);
 }
 template <typename T>
+void launch_amatvec(const DevMesh<T>& M, const Params& P, const T* Qx, const T* lam, const T* D, const double* x,
+                    double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_amatvec<T>, dim3(nblk(M.N, 256)), dim3(256), 0, s, M, P, Qx, lam, D, x, out);
+}
+template <typename T>
 void launch_perturb(const double* Q, const double* v, const double* sigma, int N, int NX, T* Qp, hipStream_t s) {
   hipLaunchKernelGGL(k_perturb<T>, dim3(nblk(N, 256)), dim3(256), 0, s, Q, v, sigma, N, NX, Qp);
 }
@@ -764,6 +803,8 @@ void launch_sigma(const double* vv, const double* qq, double n, double eps, doub
   template void launch_lambda_diag<T>(const DevMesh<T>&, const Params&, const T*, const T*, T*, T*, hipStream_t); \
   template void launch_jacobi<T>(const DevMesh<T>&, const Params&, const T*, const T*, const T*, const double*,   \
                                  const double*, double*, hipStream_t);                                           \
+  template void launch_amatvec<T>(const DevMesh<T>&, const Params&, const T*, const T*, const T*, const double*,  \
+                                  double*, hipStream_t);                                                         \
   template void launch_perturb<T>(const double*, const double*, const double*, int, int, T*, hipStream_t);        \
   template void launch_check<T>(const T*, int, int, double, int*, hipStream_t);
 HGKS_INST(double)
