@@ -23,9 +23,9 @@ struct VWX {
   T v[6], w[6], x2, x4;
 };
 
+// r = 1/(2 lam), computed once per Maxwellian by the caller
 template <typename T>
-HGKS_HD void vwx_table(VWX<T>& M, T V, T W, T lam, T K) {
-  T r = T(0.5) / lam;
+HGKS_HD void vwx_table(VWX<T>& M, T V, T W, T r, T K) {
   M.v[0] = T(1);
   M.v[1] = V;
   M.w[0] = T(1);
@@ -42,8 +42,7 @@ HGKS_HD void vwx_table(VWX<T>& M, T V, T W, T lam, T K) {
 // u-moments <u^k>, k < 8, from <u^0> and <u^1> (recurrence valid for the
 // full space and both half spaces)
 template <typename T>
-HGKS_HD void u_table(T u[8], T U, T lam, T u0, T u1) {
-  T r = T(0.5) / lam;
+HGKS_HD void u_table(T u[8], T U, T r, T u0, T u1) {
   u[0] = u0;
   u[1] = u1;
 #pragma unroll
@@ -185,16 +184,17 @@ HGKS_HD void gmom(const T u[8], const GSum<T>& G, T s, T out[5]) {
 // Closed-form solution of <a psi> = b (normalised moments of the full-space
 // Maxwellian with velocity (U,V,W), lam = rho/(2p), K internal dof): solved
 // in the peculiar-velocity basis where the moment matrix is block diagonal.
+// (r = 1/(2 lam) and ik3 = 1/(K + 3) are passed in: no division here)
 template <typename T>
-HGKS_HD void micro_slope(const T b[5], T U, T V, T W, T lam, T K, T a[5]) {
+HGKS_HD void micro_slope(const T b[5], T U, T V, T W, T lam, T r, T K, T ik3, T a[5]) {
   T q2 = U * U + V * V + W * W;
   T d1 = b[0];
   T d2 = b[1] - U * b[0];
   T d3 = b[2] - V * b[0];
   T d4 = b[3] - W * b[0];
   T d5 = b[4] - U * b[1] - V * b[2] - W * b[3] + T(0.5) * q2 * b[0];
-  T a5 = T(4) * lam * lam / (K + T(3)) * (T(2) * d5 - (K + T(3)) / (T(2) * lam) * d1);
-  T al0 = d1 - (K + T(3)) / (T(4) * lam) * a5;
+  T a5 = T(4) * lam * lam * ik3 * (T(2) * d5 - (K + T(3)) * r * d1);
+  T al0 = d1 - T(0.5) * (K + T(3)) * r * a5;
   a[4] = a5;
   a[1] = T(2) * lam * d2 - U * a5;
   a[2] = T(2) * lam * d3 - V * a5;
@@ -215,7 +215,7 @@ struct FluxParams {
 // flux moments (k = 1) into F, density moments (k = 0) into Ph (NS) and the
 // point-value moments with the second coefficient set into QG.
 template <typename T, bool NS, bool QG>
-HGKS_HD void term(const VWX<T>& M, const T uh[8], const T uf[8], T rho, T U, T V, T W, T lam, T K,
+HGKS_HD void term(const VWX<T>& M, const T uh[8], const T uf[8], T rho, T U, T V, T W, T lam, T r, T K, T ik3,
                   const T an[5], const T at1[5], const T at2[5], T ce, T cs, T cA, T de, T ds, T dA, T F[5],
                   T Ph[5], T Qg[5]) {
   GSum<T> Ga;
@@ -230,7 +230,7 @@ HGKS_HD void term(const VWX<T>& M, const T uh[8], const T uf[8], T rho, T U, T V
   {
     T rhs[5] = {0, 0, 0, 0, 0};
     gmom<0>(uf, Ga, T(-1), rhs);
-    micro_slope(rhs, U, V, W, lam, K, A);
+    micro_slope(rhs, U, V, W, lam, r, K, ik3, A);
   }
   if (QG) {
     T c[23];
@@ -276,13 +276,15 @@ template <typename T, bool want_qg>
 HGKS_HD void gks_flux(const T Wl[5], const T dWl[3][5], const T Wr[5], const T dWr[3][5], T dt,
                       const FluxParams<T>& P, T F[5], T QG[5]) {
   const T g = P.gamma, K = P.K;
-  // primitive variables of both sides
-  T rl = Wl[0], Ul = Wl[1] / rl, Vl = Wl[2] / rl, Wwl = Wl[3] / rl;
+  const T ik3 = T(1) / (K + T(3));
+  // primitive variables of both sides; per Maxwellian the factor 1/(2 lam)
+  // of the moment recurrences is formed once
+  T rl = Wl[0], il = T(1) / rl, Ul = Wl[1] * il, Vl = Wl[2] * il, Wwl = Wl[3] * il;
   T pl = (g - T(1)) * (Wl[4] - T(0.5) * rl * (Ul * Ul + Vl * Vl + Wwl * Wwl));
-  T ll = rl / (T(2) * pl);
-  T rr = Wr[0], Ur = Wr[1] / rr, Vr = Wr[2] / rr, Wwr = Wr[3] / rr;
+  T ll = rl / (T(2) * pl), hl = pl * il;  // lam and 1/(2 lam) = p/rho
+  T rr = Wr[0], ir = T(1) / rr, Ur = Wr[1] * ir, Vr = Wr[2] * ir, Wwr = Wr[3] * ir;
   T pr = (g - T(1)) * (Wr[4] - T(0.5) * rr * (Ur * Ur + Vr * Vr + Wwr * Wwr));
-  T lr = rr / (T(2) * pr);
+  T lr = rr / (T(2) * pr), hr = pr * ir;
   T ul0, ul1, ur0, ur1;  // half-space base moments: u > 0 left, u < 0 right
   half_base(Ul, ll, +1, ul0, ul1);
   half_base(Ur, lr, -1, ur0, ur1);
@@ -292,24 +294,24 @@ HGKS_HD void gks_flux(const T Wl[5], const T dWl[3][5], const T Wr[5], const T d
   {
     VWX<T> M;
     T u[8];
-    vwx_table(M, Vl, Wwl, ll, K);
-    u_table(u, Ul, ll, ul0, ul1);
+    vwx_table(M, Vl, Wwl, hl, K);
+    u_table(u, Ul, hl, ul0, ul1);
     Q0[0] += rl * u[0];
     Q0[1] += rl * u[1];
     Q0[2] += rl * u[0] * M.v[1];
     Q0[3] += rl * u[0] * M.w[1];
     Q0[4] += rl * T(0.5) * (u[2] + u[0] * (M.v[2] + M.w[2] + M.x2));
-    vwx_table(M, Vr, Wwr, lr, K);
-    u_table(u, Ur, lr, ur0, ur1);
+    vwx_table(M, Vr, Wwr, hr, K);
+    u_table(u, Ur, hr, ur0, ur1);
     Q0[0] += rr * u[0];
     Q0[1] += rr * u[1];
     Q0[2] += rr * u[0] * M.v[1];
     Q0[3] += rr * u[0] * M.w[1];
     Q0[4] += rr * T(0.5) * (u[2] + u[0] * (M.v[2] + M.w[2] + M.x2));
   }
-  T r0 = Q0[0], U0 = Q0[1] / r0, V0 = Q0[2] / r0, W0 = Q0[3] / r0;
+  T r0 = Q0[0], i0 = T(1) / r0, U0 = Q0[1] * i0, V0 = Q0[2] * i0, W0 = Q0[3] * i0;
   T p0 = (g - T(1)) * (Q0[4] - T(0.5) * r0 * (U0 * U0 + V0 * V0 + W0 * W0));
-  T l0 = r0 / (T(2) * p0);
+  T l0 = r0 / (T(2) * p0), h0 = p0 * i0;
 
   // collision time (Sec. 5) and the time coefficients of Eq. (flux),
   // integrated over [0, dt] and divided by dt
@@ -334,7 +336,6 @@ HGKS_HD void gks_flux(const T Wl[5], const T dWl[3][5], const T Wr[5], const T d
   // the kinetic-weighted derivatives of Q0
   T al[3][5], ar[3][5], ab[3][5];
   {
-    T il = T(1) / rl, ir = T(1) / rr;
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
       T bl[5], br[5];
@@ -343,8 +344,8 @@ HGKS_HD void gks_flux(const T Wl[5], const T dWl[3][5], const T Wr[5], const T d
         bl[k] = dWl[d][k] * il;
         br[k] = dWr[d][k] * ir;
       }
-      micro_slope(bl, Ul, Vl, Wwl, ll, K, al[d]);
-      micro_slope(br, Ur, Vr, Wwr, lr, K, ar[d]);
+      micro_slope(bl, Ul, Vl, Wwl, ll, hl, K, ik3, al[d]);
+      micro_slope(br, Ur, Vr, Wwr, lr, hr, K, ik3, ar[d]);
     }
   }
   {
@@ -355,20 +356,19 @@ HGKS_HD void gks_flux(const T Wl[5], const T dWl[3][5], const T Wr[5], const T d
       for (int k = 0; k < 5; ++k) dq[d][k] = T(0);
     VWX<T> M;
     T u[8];
-    vwx_table(M, Vl, Wwl, ll, K);
-    u_table(u, Ul, ll, ul0, ul1);
+    vwx_table(M, Vl, Wwl, hl, K);
+    u_table(u, Ul, hl, ul0, ul1);
 #pragma unroll
     for (int d = 0; d < 3; ++d) apsi_mom(M, u, al[d], rl, dq[d]);
-    vwx_table(M, Vr, Wwr, lr, K);
-    u_table(u, Ur, lr, ur0, ur1);
+    vwx_table(M, Vr, Wwr, hr, K);
+    u_table(u, Ur, hr, ur0, ur1);
 #pragma unroll
     for (int d = 0; d < 3; ++d) apsi_mom(M, u, ar[d], rr, dq[d]);
-    T i0 = T(1) / r0;
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
 #pragma unroll
       for (int k = 0; k < 5; ++k) dq[d][k] *= i0;
-      micro_slope(dq[d], U0, V0, W0, l0, K, ab[d]);
+      micro_slope(dq[d], U0, V0, W0, l0, h0, K, ik3, ab[d]);
     }
   }
 #pragma unroll
@@ -380,40 +380,40 @@ HGKS_HD void gks_flux(const T Wl[5], const T dWl[3][5], const T Wr[5], const T d
   {
     VWX<T> M;
     T uh[8], uf[8];
-    vwx_table(M, Vl, Wwl, ll, K);
-    u_table(uh, Ul, ll, ul0, ul1);
-    u_table(uf, Ul, ll, T(1), Ul);
+    vwx_table(M, Vl, Wwl, hl, K);
+    u_table(uh, Ul, hl, ul0, ul1);
+    u_table(uf, Ul, hl, T(1), Ul);
     if (P.physics)
-      term<T, true, want_qg>(M, uh, uf, rl, Ul, Vl, Wwl, ll, K, al[0], al[1], al[2], c4, c5, c6, d4, d5, d6, F, Ph,
+      term<T, true, want_qg>(M, uh, uf, rl, Ul, Vl, Wwl, ll, hl, K, ik3, al[0], al[1], al[2], c4, c5, c6, d4, d5, d6, F, Ph,
                              Qg);
     else
-      term<T, false, want_qg>(M, uh, uf, rl, Ul, Vl, Wwl, ll, K, al[0], al[1], al[2], c4, c5, c6, d4, d5, d6, F, Ph,
+      term<T, false, want_qg>(M, uh, uf, rl, Ul, Vl, Wwl, ll, hl, K, ik3, al[0], al[1], al[2], c4, c5, c6, d4, d5, d6, F, Ph,
                               Qg);
   }
   {
     VWX<T> M;
     T uh[8], uf[8];
-    vwx_table(M, Vr, Wwr, lr, K);
-    u_table(uh, Ur, lr, ur0, ur1);
-    u_table(uf, Ur, lr, T(1), Ur);
+    vwx_table(M, Vr, Wwr, hr, K);
+    u_table(uh, Ur, hr, ur0, ur1);
+    u_table(uf, Ur, hr, T(1), Ur);
     if (P.physics)
-      term<T, true, want_qg>(M, uh, uf, rr, Ur, Vr, Wwr, lr, K, ar[0], ar[1], ar[2], c4, c5, c6, d4, d5, d6, F, Ph,
+      term<T, true, want_qg>(M, uh, uf, rr, Ur, Vr, Wwr, lr, hr, K, ik3, ar[0], ar[1], ar[2], c4, c5, c6, d4, d5, d6, F, Ph,
                              Qg);
     else
-      term<T, false, want_qg>(M, uh, uf, rr, Ur, Vr, Wwr, lr, K, ar[0], ar[1], ar[2], c4, c5, c6, d4, d5, d6, F, Ph,
+      term<T, false, want_qg>(M, uh, uf, rr, Ur, Vr, Wwr, lr, hr, K, ik3, ar[0], ar[1], ar[2], c4, c5, c6, d4, d5, d6, F, Ph,
                               Qg);
   }
   // equilibrium term: full-space moments of g0
   {
     VWX<T> M;
     T u[8];
-    vwx_table(M, V0, W0, l0, K);
-    u_table(u, U0, l0, T(1), U0);
+    vwx_table(M, V0, W0, h0, K);
+    u_table(u, U0, h0, T(1), U0);
     // (no point-value contribution: its coefficients d1..d3 vanish at t^n)
     if (P.physics)
-      term<T, true, false>(M, u, u, r0, U0, V0, W0, l0, K, ab[0], ab[1], ab[2], c1, c2, c3, d1, d2, d3, F, Ph, Qg);
+      term<T, true, false>(M, u, u, r0, U0, V0, W0, l0, h0, K, ik3, ab[0], ab[1], ab[2], c1, c2, c3, d1, d2, d3, F, Ph, Qg);
     else
-      term<T, false, false>(M, u, u, r0, U0, V0, W0, l0, K, ab[0], ab[1], ab[2], c1, c2, c3, d1, d2, d3, F, Ph, Qg);
+      term<T, false, false>(M, u, u, r0, U0, V0, W0, l0, h0, K, ik3, ab[0], ab[1], ab[2], c1, c2, c3, d1, d2, d3, F, Ph, Qg);
   }
   if (P.physics) {
     // heat flux relative to U0 carried by the time-averaged f, rescaled to Pr

@@ -64,6 +64,6 @@ void hgks_hostcheck_flux_f32(const double* Wl, const double* dWl, const double* 
 
 void hgks_hostcheck_slope(const double* b, double U, double V, double W, double lam, double K, double* a) {
   double bb[5] = {b[0], b[1], b[2], b[3], b[4]};
-  hgks::micro_slope(bb, U, V, W, lam, K, a);
+  hgks::micro_slope(bb, U, V, W, lam, 0.5 / lam, K, 1.0 / (K + 3.0), a);
 }
 }
