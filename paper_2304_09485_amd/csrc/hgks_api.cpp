@@ -513,7 +513,7 @@ hgks_status hgks_load_mesh(hgks_ctx* ctx, int64_t n_nodes, const double* xyz, in
   ctx->part = ctx->A.get<double>(REDUCE_PARTS);
   ctx->sc = ctx->A.get<double>(64 + MAXM + 1);
   ctx->flags = ctx->A.get<int>(4);
-  if (!ctx->Qc || !ctx->dtc || !ctx->b || !ctx->V || !ctx->flags || !ctx->sc) {
+  if (!ctx->Qc || !ctx->dtc || !ctx->b || !ctx->V || !ctx->flags || !ctx->sc || !ctx->part) {
     ctx->err = "device allocation failed";
     return HGKS_ENOMEM;
   }
@@ -696,13 +696,14 @@ hgks_status hgks_implicit_step(hgks_ctx* ctx, hgks_step_info* info) {
       TRY(jv_device(ctx, vj, ctx->o.fd_sigma, ctx->yv, s));
       if (fd) ++evals;
       precond_device(ctx, ctx->yv, ctx->wv, s);
-      // modified Gram-Schmidt
+      // modified Gram-Schmidt: h_0 = (w, v_0); then per i: w -= h_i v_i and
+      // h_{i+1} = (w, v_{i+1}) in one pass, the last pass giving |w|
+      launch_dot(ctx->wv, ctx->V, n, ctx->part, hc, false, s);
       for (int i = 0; i <= j; ++i) {
         const double* vi = ctx->V + (size_t)i * n;
-        launch_dot(ctx->wv, vi, n, ctx->part, hc + i, false, s);
-        launch_axpy_dev(vi, ctx->wv, n, hc + i, -1.0, s);
+        const double* next = i < j ? ctx->V + (size_t)(i + 1) * n : nullptr;
+        launch_axpy_dot(vi, ctx->wv, n, hc + i, next, ctx->part, hc + i + 1, s);
       }
-      launch_dot(ctx->wv, ctx->wv, n, ctx->part, hc + j + 1, true, s);
       std::vector<double> col(j + 2);
       HIPCHK(hipMemcpyAsync(col.data(), hc, (j + 2) * sizeof(double), hipMemcpyDeviceToHost, s));
       HIPCHK(hipStreamSynchronize(s));

@@ -31,6 +31,10 @@ template <typename T> void launch_check(const T* Qx, int N, int NX, double gamma
 
 void launch_dot(const double* x, const double* y, size_t n, double* part, double* out, bool sqrt_out, hipStream_t);
 void launch_abssum(const double* x, size_t n, double* part, double* out, hipStream_t);
+// w -= a[0] v; out = w.z, or |w| if z is null (one modified Gram-Schmidt step
+// and the next inner product in one pass)
+void launch_axpy_dot(const double* v, double* w, size_t n, const double* a, const double* z, double* part,
+                     double* out, hipStream_t);
 void launch_axpy_dev(const double* x, double* y, size_t n, const double* a, double sgn, hipStream_t);
 void launch_scale_inv(const double* x, double* y, size_t n, const double* a, hipStream_t);
 void launch_combine(const double* V, const double* c, int nv, size_t n, const double* x, double* y, hipStream_t);
@@ -38,6 +42,6 @@ void launch_convert(const double* src, float* dst, size_t n, hipStream_t);
 void launch_sigma(const double* vv, const double* qq, double n, double eps, double fixed, double* sigma,
                   hipStream_t);
 
-constexpr int REDUCE_PARTS = 1024;
+constexpr int REDUCE_PARTS = 1024;  // partials of a reduction
 
 }  // namespace hgks

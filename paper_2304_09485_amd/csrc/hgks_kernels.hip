@@ -601,7 +601,9 @@ __device__ __forceinline__ double block_sum(double x) {
   return sh[0];
 }
 
-// part[blockIdx] = sum over a fixed strided slice of op(x, y)
+// part[blockIdx] = sum over a fixed strided slice of op(x, y) (OP 0: x.y,
+// 1: |x|); a second one-block kernel sums the partials in block order, so the
+// summation order does not depend on scheduling
 template <int OP>
 __global__ void __launch_bounds__(RB) k_reduce_part(const double* __restrict__ x, const double* __restrict__ y,
                                                     size_t n, double* __restrict__ part) {
@@ -621,6 +623,23 @@ __global__ void __launch_bounds__(RB) k_reduce_final(const double* __restrict__ 
   for (int k = threadIdx.x; k < RGRID; k += RB) s += part[k];
   double t = block_sum(s);
   if (threadIdx.x == 0) out[0] = SQRT ? sqrt(t) : t;
+}
+
+// one modified Gram-Schmidt step fused with the partials of the next inner
+// product: w -= a[0] v, then part = block partials of w.z (z = the next basis
+// vector, or w itself for the norm)
+__global__ void __launch_bounds__(RB) k_axpy_dot_part(const double* __restrict__ v, double* __restrict__ w, size_t n,
+                                                      const double* __restrict__ a, const double* __restrict__ z,
+                                                      double* __restrict__ part) {
+  const double h = a[0];
+  double s = 0.0;
+  for (size_t k = (size_t)blockIdx.x * RB + threadIdx.x; k < n; k += (size_t)RGRID * RB) {
+    double wk = w[k] - h * v[k];
+    w[k] = wk;
+    s += wk * (z ? z[k] : wk);
+  }
+  double t = block_sum(s);
+  if (threadIdx.x == 0) part[blockIdx.x] = t;
 }
 
 // y += alpha * x, alpha = sgn * a[0] (or * 1/a[0] if INV)
@@ -776,6 +795,14 @@ void launch_dot(const double* x, const double* y, size_t n, double* part, double
 void launch_abssum(const double* x, size_t n, double* part, double* out, hipStream_t s) {
   hipLaunchKernelGGL(k_reduce_part<1>, dim3(RGRID), dim3(RB), 0, s, x, x, n, part);
   hipLaunchKernelGGL(k_reduce_final<false>, dim3(1), dim3(RB), 0, s, part, out);
+}
+void launch_axpy_dot(const double* v, double* w, size_t n, const double* a, const double* z, double* part, double* out,
+                     hipStream_t s) {
+  hipLaunchKernelGGL(k_axpy_dot_part, dim3(RGRID), dim3(RB), 0, s, v, w, n, a, z ? z : w, part);
+  if (z)
+    hipLaunchKernelGGL(k_reduce_final<false>, dim3(1), dim3(RB), 0, s, part, out);
+  else
+    hipLaunchKernelGGL(k_reduce_final<true>, dim3(1), dim3(RB), 0, s, part, out);
 }
 void launch_axpy_dev(const double* x, double* y, size_t n, const double* a, double sgn, hipStream_t s) {
   hipLaunchKernelGGL(k_axpy_dev, dim3(nblk(n, 256)), dim3(256), 0, s, x, y, n, a, sgn);
