@@ -108,8 +108,9 @@ void hgks_default_options(hgks_options* opts);
 hgks_status hgks_create(const hgks_options* opts, hgks_ctx** out);
 
 /* Load a tetrahedral mesh: xyz [n_nodes][3], tet2node [n_tets][4] (any
- * orientation of positive volume; a tet's local face p is the one opposite
- * its local vertex p, Sec. 3.1), boundary triangles bface2node [n_bfaces][3]
+ * positively oriented: det(x1-x0, x2-x0, x3-x0) > 0; a tet's local face p is
+ * the one opposite its local vertex p, Sec. 3.1), boundary triangles
+ * bface2node [n_bfaces][3]
  * with integer tags bface_tag [n_bfaces] (0 <= tag < 256).  Builds faces,
  * geometry, ghost cells, stencils and the least-squares operators and uploads
  * them.  HGKS_EMESH on a bad mesh. */

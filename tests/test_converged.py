@@ -71,3 +71,27 @@ def test_fp32_inner_reaches_the_same_drop_with_linear_weights(c2):
     assert i64.converged and i32.converged
     assert abs(i32.steps - i64.steps) <= 0.05 * i64.steps + 1
     assert diff <= 1e-6
+
+
+def test_fp32_inner_product_matches_fp64_at_fixed_step():
+    """The FP32 inner FD product against the FP64 one at the same step
+    sigma = 1e-2 on the configuration-1 cube: each FP32 residual is within
+    ~2e-5 of the flux scale (the FP32 flux bound of the host check), so the
+    FD difference is within 2 x 2e-5 x flux scale / sigma = 4e-3 x flux scale
+    of the FP64 product; |Av| is of the order of the flux scale here."""
+    from paper_2304_09485_amd import hgks
+    from inputs import perturbed_state
+    m = mesh_for_config("c1")
+    prim = freestream_prim(0.3)
+    kinds = {t: hgks.FARFIELD for t in range(1, 7)}
+    s64 = hgks.Solver(m, kinds, prim)
+    s32 = hgks.Solver(m, kinds, prim, precision=hgks.FP32_INNER)
+    Q = perturbed_state(s64.N, prim, amp=0.02, seed=2)
+    s64.set_state(Q)
+    s32.set_state(Q)
+    v = np.random.default_rng(3).normal(size=(5, s64.N))
+    a64, _ = s64.jv(v, 1e-2)
+    a32, sg = s32.jv(v, 1e-2)
+    rel = np.abs(a32 - a64).max() / np.abs(a64).max()
+    print(f"FP32-inner vs FP64 product at sigma 1e-2: {rel:.2e} relative")
+    assert sg == 1e-2 and rel <= 4e-3
