@@ -926,9 +926,47 @@ static void boundary_right(const orc_ctx& C, const Face& f, const V5& Wl, const 
 
 // Face flux (global frame, integrated over the face, oriented L -> R) and the
 // face sum of Gauss-point values for the gradient update.
+// First-order kinetic flux vector splitting: free transport of the two
+// half-space Maxwellians of the cell averages, F = rho_l <u psi>_{u>0} +
+// rho_r <u psi>_{u<0} (no collision term, no slopes); the point value of the
+// gradient update is rho_l <psi>_{u>0} + rho_r <psi>_{u<0}.
+static void kfvs_point(const orc_ctx& C, const V5& Wl, const V5& Wr, V5& F, V5* QG) {
+  const double g = C.o.gamma, K = C.K;
+  Prim l = to_prim(Wl, g), r = to_prim(Wr, g);
+  Moments Ml, Mr;
+  Ml.init(l.U, l.V, l.W, l.lam, K, +1);
+  Mr.init(r.U, r.V, r.W, r.lam, K, -1);
+  V5 fl = Ml.psi(1, 0, 0, 0), fr = Mr.psi(1, 0, 0, 0);
+  for (int k = 0; k < 5; ++k) F[k] = l.rho * fl[k] + r.rho * fr[k];
+  if (QG) {
+    V5 ql = Ml.psi(0, 0, 0, 0), qr = Mr.psi(0, 0, 0, 0);
+    for (int k = 0; k < 5; ++k) (*QG)[k] = l.rho * ql[k] + r.rho * qr[k];
+  }
+}
+
 static int face_flux(const orc_ctx& C, const double* Q, const double* G, const double* dt, int fidx,
                      V5& Fout, V5* QGout) {
   const Face& f = C.faces[fidx];
+  if (C.o.first_order) {
+    // the cell averages in the local frame; the right state of a boundary
+    // face from the boundary condition
+    V5 Wl = to_local(state_of(C, Q, f.L), f), Wr, dW0[3], dWr[3];
+    for (int d = 0; d < 3; ++d) dW0[d] = {0, 0, 0, 0, 0};
+    if (f.R < 0) {
+      boundary_right(C, f, Wl, dW0, Wr, dWr);
+    } else {
+      Wr = to_local(state_of(C, Q, f.R), f);
+    }
+    V5 Fl, QGl;
+    kfvs_point(C, Wl, Wr, Fl, QGout ? &QGl : nullptr);
+    V5 Fg = to_global(Fl, f);
+    for (int v = 0; v < 5; ++v) Fout[v] = f.S * Fg[v];
+    if (QGout) {
+      V5 Qg = to_global(QGl, f);
+      for (int v = 0; v < 5; ++v) (*QGout)[v] = f.S * Qg[v];
+    }
+    return 0;
+  }
   double sl[3][4][5], sr[3][4][5];
   int fb = side_values(C, Q, G, fidx, 0, sl);
   bool bnd = f.R < 0;
@@ -1507,6 +1545,17 @@ void orc_gks_point(const orc_ctx* C, const double* Wl, const double* dWl, const 
   }
   V5 f, q;
   gks_point(*C, l, dl, r, dr, dt, f, QG ? &q : nullptr);
+  for (int k = 0; k < 5; ++k) F[k] = f[k];
+  if (QG)
+    for (int k = 0; k < 5; ++k) QG[k] = q[k];
+}
+void orc_kfvs_point(const orc_ctx* C, const double* Wl, const double* Wr, double* F, double* QG) {
+  V5 l, r, f, q;
+  for (int k = 0; k < 5; ++k) {
+    l[k] = Wl[k];
+    r[k] = Wr[k];
+  }
+  kfvs_point(*C, l, r, f, QG ? &q : nullptr);
   for (int k = 0; k < 5; ++k) F[k] = f[k];
   if (QG)
     for (int k = 0; k < 5; ++k) QG[k] = q[k];

@@ -40,7 +40,8 @@ typedef struct {
   double cfl_flux;       /* CFL of the flux time average; 0 = same as cfl */
   int32_t jv_mode;       /* GMRES operator: 0 FD product of Eq. (frechet), 1 the approximate
                             matrix A of Eq. (deri-matrix) */
-  int32_t pad;
+  int32_t first_order;   /* 1: first-order KFVS flux of the cell averages (Sec. 5, the
+                            supersonic sphere retested with a first-order flux) */
 } orc_options;
 
 /* boundary kinds */
@@ -91,6 +92,11 @@ void orc_face_frame(const orc_ctx*, int64_t f, double* out9);
  * Outputs F[5] and, if QG != NULL, the point value Q(x_G, dt) of Eq. (point). */
 void orc_gks_point(const orc_ctx*, const double* Wl, const double* dWl, const double* Wr,
                    const double* dWr, double dt, double* F, double* QG);
+
+/* first-order KFVS flux of two local-frame conserved states (cell averages):
+ * F[5] and, if QG != NULL, the half-space density moments rho_l <psi>_{u>0} +
+ * rho_r <psi>_{u<0} */
+void orc_kfvs_point(const orc_ctx*, const double* Wl, const double* Wr, double* F, double* QG);
 
 /* normalised Maxwellian velocity moments <u^a v^b w^c xi^(2d)> (half: +1 u>0,
  * -1 u<0, 0 full) and slope solve <a psi> = b of Sec. 2 */

@@ -247,3 +247,114 @@ def test_tangent_rotation_invariance(orc):
     F = o.gks_point(Wl, dl, Wr, dr, 0.02)
     F2 = o.gks_point(rot_state(Wl), rot_der(dl), rot_state(Wr), rot_der(dr), 0.02)
     np.testing.assert_allclose(F2, rot_state(F), rtol=1e-11, atol=1e-13)
+
+
+# ---------------------------------------------------------------------------
+# first-order KFVS flux (the Mach 3 sphere retest of Sec. 5): free transport of
+# the two half-space Maxwellians of the cell averages
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("seed", range(3))
+def test_kfvs_point_vs_quadrature(orc, seed):
+    """F = rho_l <u psi>_{u>0} + rho_r <u psi>_{u<0} and the half-space
+    density moments, against the tensor quadrature of the two half spaces."""
+    rng = np.random.default_rng(40 + seed)
+    Wl = I.cons(rng.uniform(0.5, 2), rng.uniform(-1.5, 1.5, 3), rng.uniform(0.3, 2))
+    Wr = I.cons(rng.uniform(0.5, 2), rng.uniform(-1.5, 1.5, 3), rng.uniform(0.3, 2))
+    rl, Ul, pl, ll = lam_of(Wl)
+    rr, Ur, pr, lr = lam_of(Wr)
+    ql, qr = VQuad(*Ul, ll, +1), VQuad(*Ur, lr, -1)
+    F, QG = orc(first_order=1).kfvs_point(Wl, Wr, want_qg=True)
+    np.testing.assert_allclose(F, rl * ql.E(ql.u) + rr * qr.E(qr.u), rtol=1e-11, atol=1e-13)
+    np.testing.assert_allclose(QG, rl * ql.E(1.0) + rr * qr.E(1.0), rtol=1e-11, atol=1e-13)
+
+
+def test_kfvs_special_cases(orc):
+    """Equal states: the two half spaces add up to the full Maxwellian, so the
+    flux is the Euler flux and the density moments the state itself.  A
+    Mach 8 stream moving away from the right state: the left state's u<0 tail
+    and the right state's u<0 half are below 1e-19 of the flux, so the flux
+    is the Euler flux of the left state."""
+    o = orc(first_order=1)
+    rng = np.random.default_rng(47)
+    for _ in range(4):
+        W = I.cons(rng.uniform(0.5, 2), rng.uniform(-1, 1, 3), rng.uniform(0.3, 2))
+        F, QG = o.kfvs_point(W, W, want_qg=True)
+        np.testing.assert_allclose(F, I.euler_flux(W, [1, 0, 0]), rtol=1e-13, atol=1e-14)
+        np.testing.assert_allclose(QG, W, rtol=1e-13, atol=1e-14)
+    c = np.sqrt(GAM * 1.0 / 1.2)
+    Wl = I.cons(1.2, [8.0 * c, 0.3, -0.2], 1.0)
+    Wr = I.cons(0.7, [9.0, 0.1, 0.0], 0.5)  # sound speed 1: the right state streams right at Mach 9
+    np.testing.assert_allclose(o.kfvs_point(Wl, Wr), I.euler_flux(Wl, [1, 0, 0]), rtol=1e-14, atol=0)
+
+
+def test_kfvs_is_free_transport_limit(orc):
+    """Zero slopes and tau >> dt: the collision-free limit of the gas-kinetic
+    flux of Eq. (flux) is the KFVS flux."""
+    Wl = I.cons(1.1, [0.4, -0.3, 0.2], 0.8)
+    Wr = I.cons(0.9, [-0.1, 0.2, 0.5], 1.1)
+    z = np.zeros((3, 5))
+    got = orc(tau_eps=1e12, tau_C=0.0).gks_point(Wl, z, Wr, z, 1e-3)
+    np.testing.assert_allclose(got, orc(first_order=1).kfvs_point(Wl, Wr), rtol=1e-10, atol=1e-13)
+
+
+def _faces_brute(mesh):
+    """Faces of a tet mesh by matching sorted node triples: (owner, neighbour
+    or -1, unit normal out of the owner, area)."""
+    xyz, tets = mesh.xyz, mesh.tets
+    seen, out = {}, []
+    for t, tet in enumerate(tets):
+        for p in range(4):
+            tri = np.delete(tet, p)
+            key = tuple(sorted(tri))
+            if key in seen:
+                out[seen[key]][1] = t
+                continue
+            a, b, c = xyz[tri]
+            nv = np.cross(b - a, c - a)
+            if nv @ (xyz[tet[p]] - a) > 0:
+                nv = -nv
+            seen[key] = len(out)
+            out.append([t, -1, nv / np.linalg.norm(nv), 0.5 * np.linalg.norm(nv)])
+    return out
+
+
+@pytest.mark.parametrize("mach", [0.5, 3.0])
+def test_kfvs_residual_brute_force(oracle_lib, mach):
+    """First-order residual of a jittered cube, supersonic inflow on every
+    boundary (right state = free stream): faces, normals and areas found by
+    brute force, a tangent frame of the test's own choosing, the flux from
+    the pinned point function; L_i = -sum of outward face fluxes times area."""
+    from inputs import cube_mesh, freestream_prim, perturbed_state
+    m = cube_mesh(2, jitter=0.15, seed=5)
+    prim = freestream_prim(mach)
+    o = oracle_lib.Oracle(m, {t: oracle_lib.SUP_IN for t in range(1, 7)}, prim, first_order=1)
+    Q = perturbed_state(o.N, prim, amp=0.05, seed=6)
+    qinf = I.cons(prim[0], prim[1:4], prim[4])
+    R = np.zeros((5, o.N))
+    for L, Rn, n, S in _faces_brute(m):
+        t1 = np.cross(n, [0.6, 0.0, 0.8]) if abs(n @ [0.6, 0.0, 0.8]) < 0.9 else np.cross(n, [0.0, 1.0, 0.0])
+        t1 /= np.linalg.norm(t1)
+        t2 = np.cross(n, t1)
+        Rot = np.array([n, t1, t2])
+        loc = lambda q: np.concatenate([[q[0]], Rot @ q[1:4], [q[4]]])  # noqa: E731
+        qr = Q[:, Rn] if Rn >= 0 else qinf
+        Fl = o.kfvs_point(loc(Q[:, L]), loc(qr))
+        Fg = np.concatenate([[Fl[0]], Rot.T @ Fl[1:4], [Fl[4]]])
+        R[:, L] -= S * Fg
+        if Rn >= 0:
+            R[:, Rn] += S * Fg
+    got = o.residual(Q)
+    np.testing.assert_allclose(got, R, rtol=0, atol=1e-13 * np.abs(R).max())
+
+
+def test_kfvs_free_stream_preserved(oracle_lib):
+    """A uniform free stream with far-field boundaries is a steady state of
+    the first-order residual (closed cells: the face normals times areas sum
+    to zero, and equal states give the Euler flux)."""
+    from inputs import cube_mesh, freestream_prim
+    m = cube_mesh(3, jitter=0.15, seed=8)
+    prim = freestream_prim(0.7, direction=(1.0, 0.4, -0.3))
+    o = oracle_lib.Oracle(m, {t: oracle_lib.FARFIELD for t in range(1, 7)}, prim, first_order=1)
+    q = I.cons(prim[0], prim[1:4], prim[4])
+    Q = np.repeat(q[:, None], o.N, axis=1)
+    assert np.abs(o.residual(Q)).max() < 1e-14
