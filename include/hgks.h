@@ -42,7 +42,11 @@ typedef enum {
   HGKS_EDEVICE = -6  /* HIP runtime error */
 } hgks_status;
 
-enum { HGKS_WENO = 0, HGKS_HWENO = 1 };              /* Sec. 3.2 / Sec. 3.3 */
+/* spatial scheme: non-compact WENO (Sec. 3.2), compact HWENO (Sec. 3.3), or
+ * the first-order kinetic flux vector splitting of the cell averages that the
+ * Mach 3 sphere case of Sec. 5 is retested with (no reconstruction, free
+ * transport of the two half-space Maxwellians; inviscid only) */
+enum { HGKS_WENO = 0, HGKS_HWENO = 1, HGKS_KFVS1 = 2 };
 enum { HGKS_EULER = 0, HGKS_NS = 1 };                /* collision time of Sec. 5 */
 enum { HGKS_FP64 = 0, HGKS_FP32_INNER = 1 };         /* arithmetic of the GMRES inner operator */
 enum { HGKS_WEIGHTS_NONLINEAR = 0, HGKS_WEIGHTS_LINEAR = 1 }; /* Sec. 3.4 */
@@ -55,7 +59,7 @@ enum { HGKS_FARFIELD = 0, HGKS_SLIP_WALL = 1, HGKS_NOSLIP_ADIABATIC = 2,
        HGKS_SUP_IN = 3, HGKS_SUP_OUT = 4 };          /* Sec. 5 boundary conditions */
 
 typedef struct {
-  int32_t scheme;        /* HGKS_WENO | HGKS_HWENO */
+  int32_t scheme;        /* HGKS_WENO | HGKS_HWENO | HGKS_KFVS1 */
   int32_t physics;       /* HGKS_EULER | HGKS_NS */
   int32_t precision;     /* HGKS_FP64 | HGKS_FP32_INNER */
   int32_t weights;       /* HGKS_WEIGHTS_NONLINEAR | HGKS_WEIGHTS_LINEAR */
@@ -104,7 +108,8 @@ typedef struct hgks_ctx hgks_ctx;
  * nonlinear weights, m = 10, 3 restarts, 2 Jacobi sweeps, CFL 10. */
 void hgks_default_options(hgks_options* opts);
 
-/* Create a context on the current HIP device.  opts is copied. */
+/* Create a context on the current HIP device.  opts is copied.  HGKS_EINVAL
+ * on an option out of range, and for HGKS_KFVS1 with HGKS_NS. */
 hgks_status hgks_create(const hgks_options* opts, hgks_ctx** out);
 
 /* Load a tetrahedral mesh: xyz [n_nodes][3], tet2node [n_tets][4] (any

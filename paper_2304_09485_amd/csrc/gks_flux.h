@@ -427,6 +427,35 @@ HGKS_HD void gks_flux(const T Wl[5], const T dWl[3][5], const T Wr[5], const T d
     for (int k = 0; k < 5; ++k) QG[k] = Qg[k];
 }
 
+// First-order kinetic flux vector splitting (the Mach 3 retest of Sec. 5):
+// the free transport of the two half-space Maxwellians of the side states,
+// F = rho_l <u psi>_{u>0} + rho_r <u psi>_{u<0}, with no collision term and
+// no slopes.  Per side, with h = 1/(2 lam):
+//   <v^2 + w^2 + xi^2> = V^2 + W^2 + (K + 2) h,  <u^2> and <u^3> from the
+//   recurrence of u_table.
+template <typename T>
+HGKS_HD void kfvs_flux(const T Wl[5], const T Wr[5], T g, T K, T F[5]) {
+#pragma unroll
+  for (int k = 0; k < 5; ++k) F[k] = T(0);
+#pragma unroll
+  for (int s = 0; s < 2; ++s) {
+    const T* W = s ? Wr : Wl;
+    T rho = W[0], irho = T(1) / rho, U = W[1] * irho, V = W[2] * irho, Ww = W[3] * irho;
+    T p = (g - T(1)) * (W[4] - T(0.5) * rho * (U * U + V * V + Ww * Ww));
+    T lam = rho / (T(2) * p), h = p * irho;
+    T u0, u1;
+    half_base(U, lam, s ? -1 : +1, u0, u1);
+    T u2 = U * u1 + h * u0;
+    T u3 = U * u2 + T(2) * h * u1;
+    T e = V * V + Ww * Ww + (K + T(2)) * h;
+    F[0] += rho * u1;
+    F[1] += rho * u2;
+    F[2] += rho * u1 * V;
+    F[3] += rho * u1 * Ww;
+    F[4] += rho * T(0.5) * (u3 + u1 * e);
+  }
+}
+
 #undef HGKS_HD
 
 }  // namespace hgks

@@ -197,7 +197,7 @@ hgks_status upload_mesh_fp(hgks_ctx* ctx, DevMesh<T>& M) {
   if (ctx->o.scheme == HGKS_HWENO) {
     TRY(upload_conv(ctx, H.opH, M.opH));
     TRY(upload_conv(ctx, H.hsub, M.hsub));
-  } else {
+  } else if (ctx->o.scheme == HGKS_WENO) {
     TRY(upload_conv(ctx, H.opA, M.opA));
     TRY(upload_conv(ctx, H.opB, M.opB));
   }
@@ -209,13 +209,15 @@ hgks_status alloc_work(hgks_ctx* ctx, Work<T>& w) {
   const HostMesh& H = ctx->H;
   size_t N = H.N, F = H.F, NX = H.N + H.Nb;
   w.Qx = ctx->A.get<T>(5 * NX);
-  w.coef = ctx->A.get<T>(105 * N);
-  w.sv = ctx->A.get<T>(60 * 2 * F);
+  // the first-order scheme has no reconstruction coefficients or side values
+  const bool ho = ctx->o.scheme != HGKS_KFVS1;
+  w.coef = ho ? ctx->A.get<T>(105 * N) : nullptr;
+  w.sv = ho ? ctx->A.get<T>(60 * 2 * F) : nullptr;
   w.ff = ctx->A.get<T>(5 * F);
   w.fq = ctx->A.get<T>(5 * F);
   w.dt = ctx->A.get<T>(N);
   w.Gx = ctx->o.scheme == HGKS_HWENO ? ctx->A.get<T>(15 * NX) : nullptr;
-  if (!w.Qx || !w.coef || !w.sv || !w.ff || !w.fq || !w.dt || (ctx->o.scheme == HGKS_HWENO && !w.Gx))
+  if (!w.Qx || (ho && (!w.coef || !w.sv)) || !w.ff || !w.fq || !w.dt || (ctx->o.scheme == HGKS_HWENO && !w.Gx))
     return HGKS_ENOMEM;
   return HGKS_OK;
 }
@@ -239,6 +241,17 @@ template <typename T, typename TO>
 void residual_pipeline(hgks_ctx* ctx, const DevMesh<T>& M, Work<T>& w, T* Qx, const T* dt, int mode, TO* out,
                        const TO* v, const TO* bb, const double* sigma, TO* gout, hipStream_t s) {
   hipEvent_t* ev = next_events(ctx);
+  if (ctx->o.scheme == HGKS_KFVS1) {
+    // first order: the flux of the cell averages, no ghost, recon or side
+    // stage (the four intervals before the flux stay empty)
+    for (int k = 0; k < 4; ++k)
+      if (ev) (void)hipEventRecord(ev[k], s);
+    launch_flux_kfvs<T>(M, ctx->P, Qx, w.ff, s);
+    if (ev) (void)hipEventRecord(ev[4], s);
+    launch_gather<T, TO>(M, mode, w.ff, w.fq, out, v, bb, dt, sigma, gout, s);
+    if (ev) (void)hipEventRecord(ev[5], s);
+    return;
+  }
   if (ev) (void)hipEventRecord(ev[0], s);
   launch_ghost<T>(M, ctx->P, Qx, (T*)nullptr, s);
   if (ev) (void)hipEventRecord(ev[1], s);
@@ -432,9 +445,10 @@ hgks_status hgks_create(const hgks_options* opts, hgks_ctx** out) {
   if (!opts || !out) return HGKS_EINVAL;
   *out = nullptr;
   if (opts->krylov_dim < 1 || opts->krylov_dim > MAXM || opts->restarts < 1 || opts->jacobi_sweeps < 0 ||
-      !(opts->gamma > 1.0) || !(opts->cfl > 0.0) || opts->scheme < 0 || opts->scheme > 1 || opts->physics < 0 ||
+      !(opts->gamma > 1.0) || !(opts->cfl > 0.0) || opts->scheme < 0 || opts->scheme > 2 || opts->physics < 0 ||
       opts->physics > 1 || opts->precision < 0 || opts->precision > 1 || opts->jv_mode < 0 || opts->jv_mode > 1 ||
-      (opts->physics == HGKS_NS && !(opts->mu > 0.0 && opts->prandtl > 0.0)))
+      (opts->physics == HGKS_NS && !(opts->mu > 0.0 && opts->prandtl > 0.0)) ||
+      (opts->physics == HGKS_NS && opts->scheme == HGKS_KFVS1))
     return HGKS_EINVAL;
   hgks_ctx* ctx = new (std::nothrow) hgks_ctx;
   if (!ctx) return HGKS_ENOMEM;
@@ -482,7 +496,7 @@ hgks_status hgks_load_mesh(hgks_ctx* ctx, int64_t n_nodes, const double* xyz, in
   TRY(upload(ctx, H.gface, M.gface));
   if (ctx->o.scheme == HGKS_HWENO) {
     TRY(upload(ctx, H.nb4, M.nb4));
-  } else {
+  } else if (ctx->o.scheme == HGKS_WENO) {
     TRY(upload(ctx, H.stn, M.stn));
     TRY(upload(ctx, H.sstn, M.sstn));
     TRY(upload(ctx, H.smask, M.smask));

@@ -13,6 +13,8 @@ template <typename T>
 void launch_side(const DevMesh<T>&, const Params&, const T* Qx, const T* coef, T* sv, int* nfall, hipStream_t);
 template <typename T>
 void launch_flux(const DevMesh<T>&, const Params&, const T* sv, const T* dt, T* ff, T* fq, bool qg, hipStream_t);
+template <typename T>
+void launch_flux_kfvs(const DevMesh<T>&, const Params&, const T* Qx, T* ff, hipStream_t);
 template <typename T, typename TO>
 void launch_gather(const DevMesh<T>&, int mode, const T* ff, const T* fq, TO* out, const TO* v, const TO* b,
                    const T* dt, const double* sigma, TO* gout, hipStream_t);

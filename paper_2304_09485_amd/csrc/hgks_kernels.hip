@@ -386,6 +386,55 @@ __global__ void __launch_bounds__(64) k_flux(DevMesh<T> M, Params P, const T* __
   }
 }
 
+// first-order KFVS flux: one thread per face, the cell averages of both
+// sides (boundary faces: the boundary state of the owner's average), rotated
+// into the face frame; ff as for k_flux
+template <typename T>
+__global__ void __launch_bounds__(256) k_flux_kfvs(DevMesh<T> M, Params P, const T* __restrict__ Qx,
+                                                   T* __restrict__ ff) {
+  const int F = M.F, N = M.N, NX = M.NX;
+  const int f = xcd_block() * blockDim.x + threadIdx.x;
+  if (f >= F) return;
+  const int L = M.fL[f], R = M.fR[f];
+  T n[3] = {M.fn[f], M.fn[F + f], M.fn[2 * F + f]}, t1[3], t2[3];
+  face_frame(n[0], n[1], n[2], t1, t2);
+  const T g = T(P.gamma);
+  T Wl[5], Wr[5];
+  {
+    T q[5];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) q[v] = Qx[(size_t)v * NX + L];
+    Wl[0] = q[0];
+    Wl[1] = q[1] * n[0] + q[2] * n[1] + q[3] * n[2];
+    Wl[2] = q[1] * t1[0] + q[2] * t1[1] + q[3] * t1[2];
+    Wl[3] = q[1] * t2[0] + q[2] * t2[1] + q[3] * t2[2];
+    Wl[4] = q[4];
+  }
+  if (R >= N) {
+    T ui[3] = {T(P.uinf0), T(P.uinf1), T(P.uinf2)};
+    T ul[3] = {ui[0] * n[0] + ui[1] * n[1] + ui[2] * n[2], ui[0] * t1[0] + ui[1] * t1[1] + ui[2] * t1[2],
+               ui[0] * t2[0] + ui[1] * t2[1] + ui[2] * t2[2]};
+    T d0[3][5] = {}, d1[3][5];
+    boundary_right(M.fkind[f], Wl, d0, ul, T(P.rhoinf), T(P.pinf), g, Wr, d1);
+  } else {
+    T q[5];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) q[v] = Qx[(size_t)v * NX + R];
+    Wr[0] = q[0];
+    Wr[1] = q[1] * n[0] + q[2] * n[1] + q[3] * n[2];
+    Wr[2] = q[1] * t1[0] + q[2] * t1[1] + q[3] * t1[2];
+    Wr[3] = q[1] * t2[0] + q[2] * t2[1] + q[3] * t2[2];
+    Wr[4] = q[4];
+  }
+  T Fs[5];
+  kfvs_flux(Wl, Wr, g, T(P.K), Fs);
+  const T S = M.fS[f];
+  ff[f] = S * Fs[0];
+  ff[4 * (size_t)F + f] = S * Fs[4];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) ff[(size_t)(1 + d) * F + f] = S * (Fs[1] * n[d] + Fs[2] * t1[d] + Fs[3] * t2[d]);
+}
+
 // ---------------------------------------------------------------------------
 // gather: L(Q_i) = - sum of outward face fluxes (Eq. (finite)); epilogues
 //   MODE 0: R = L(Q)
@@ -745,6 +794,10 @@ void launch_flux(const DevMesh<T>& M, const Params& P, const T* sv, const T* dt,
   else
     hipLaunchKernelGGL((k_flux<T, false>), grid, dim3(64), 0, s, M, P, sv, dt, ff, fq);
 }
+template <typename T>
+void launch_flux_kfvs(const DevMesh<T>& M, const Params& P, const T* Qx, T* ff, hipStream_t s) {
+  if (M.F) hipLaunchKernelGGL(k_flux_kfvs<T>, dim3(nblk(M.F, 256)), dim3(256), 0, s, M, P, Qx, ff);
+}
 template <typename T, typename TO>
 void launch_gather(const DevMesh<T>& M, int mode, const T* ff, const T* fq, TO* out, const TO* v, const TO* b,
                    const T* dt, const double* sigma, TO* gout, hipStream_t s) {
@@ -826,6 +879,7 @@ void launch_sigma(const double* vv, const double* qq, double n, double eps, doub
   template void launch_recon<T>(const DevMesh<T>&, const Params&, const T*, const T*, T*, hipStream_t);           \
   template void launch_side<T>(const DevMesh<T>&, const Params&, const T*, const T*, T*, int*, hipStream_t);      \
   template void launch_flux<T>(const DevMesh<T>&, const Params&, const T*, const T*, T*, T*, bool, hipStream_t);  \
+  template void launch_flux_kfvs<T>(const DevMesh<T>&, const Params&, const T*, T*, hipStream_t);           \
   template void launch_dt<T>(const DevMesh<T>&, const Params&, double, const T*, T*, hipStream_t);                \
   template void launch_lambda_diag<T>(const DevMesh<T>&, const Params&, const T*, const T*, T*, T*, hipStream_t); \
   template void launch_jacobi<T>(const DevMesh<T>&, const Params&, const T*, const T*, const T*, const double*,   \

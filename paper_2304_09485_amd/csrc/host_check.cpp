@@ -62,6 +62,15 @@ void hgks_hostcheck_flux_f32(const double* Wl, const double* dWl, const double* 
   for (int k = 0; k < 5; ++k) F[k] = f[k];
 }
 
+void hgks_hostcheck_kfvs(const double* Wl, const double* Wr, double gamma, double K, double* F) {
+  double l[5], r[5];
+  for (int k = 0; k < 5; ++k) {
+    l[k] = Wl[k];
+    r[k] = Wr[k];
+  }
+  hgks::kfvs_flux(l, r, gamma, K, F);
+}
+
 void hgks_hostcheck_slope(const double* b, double U, double V, double W, double lam, double K, double* a) {
   double bb[5] = {b[0], b[1], b[2], b[3], b[4]};
   hgks::micro_slope(bb, U, V, W, lam, 0.5 / lam, K, 1.0 / (K + 3.0), a);

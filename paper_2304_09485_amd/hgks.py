@@ -15,7 +15,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libhgks.so")
 
-WENO, HWENO = 0, 1
+WENO, HWENO, KFVS1 = 0, 1, 2
 EULER, NS = 0, 1
 FP64, FP32_INNER = 0, 1
 JV_FD, JV_APPROX = 0, 1

@@ -68,3 +68,18 @@ def test_device_flux_fp32(oracle_lib, hc):
         worst = max(worst, np.abs(F - Fo).max() / (np.abs(Fo).max() + 1.0))
     # FP32 evaluation of the same formula: a few hundred ulps of cancellation
     assert worst < 2e-5, worst
+
+
+def test_device_kfvs_matches_oracle(oracle_lib, hc):
+    """The first-order KFVS flux of the device code against the oracle's."""
+    from inputs import cube_mesh, freestream_prim
+    hc.hgks_hostcheck_kfvs.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double, ctypes.c_double,
+                                       ctypes.c_void_p]
+    o = oracle_lib.Oracle(cube_mesh(1), {t: 0 for t in range(1, 7)}, freestream_prim(0.5), first_order=1)
+    rng = np.random.default_rng(11)
+    for _ in range(200):
+        Wl, _, Wr, _ = _states(rng)
+        F = np.zeros(5)
+        hc.hgks_hostcheck_kfvs(_p(Wl), _p(Wr), 1.4, 2.0, _p(F))
+        Fo = o.kfvs_point(Wl, Wr)
+        np.testing.assert_allclose(F, Fo, rtol=0, atol=1e-14 * (np.abs(Fo).max() + 1.0))
