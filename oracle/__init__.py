@@ -55,7 +55,7 @@ class Options(ctypes.Structure):
                 ("tau_eps", ctypes.c_double), ("tau_C", ctypes.c_double), ("gamma_lin", ctypes.c_double),
                 ("weno_eps", ctypes.c_double), ("mu", ctypes.c_double), ("prandtl", ctypes.c_double),
                 ("fd_sigma", ctypes.c_double), ("cfl_flux", ctypes.c_double), ("jv_mode", ctypes.c_int32),
-                ("first_order", ctypes.c_int32)]
+                ("first_order", ctypes.c_int32), ("solver", ctypes.c_int32), ("pad", ctypes.c_int32)]
 
 
 class StepInfo(ctypes.Structure):
@@ -92,6 +92,9 @@ def _declare(L):
     L.orc_face_frame.argtypes = [_vp, _i64, _vp]
     L.orc_gks_point.argtypes = [_vp, _vp, _vp, _vp, _vp, _d, _vp, _vp]
     L.orc_kfvs_point.argtypes = [_vp, _vp, _vp, _vp, _vp]
+    L.orc_colours.argtypes = [_vp, _vp]
+    L.orc_colours.restype = _i32
+    L.orc_lusgs.argtypes = [_vp, _vp, _vp, _vp, _vp]
     L.orc_moment.argtypes = [_d, _d, _d, _d, _d, _i32, _i32, _i32, _i32, _i32]
     L.orc_moment.restype = _d
     L.orc_slope_solve.argtypes = [_d, _d, _d, _d, _d, _vp, _vp]
@@ -118,7 +121,7 @@ def _f64(a):
 def default_options(**kw) -> Options:
     o = Options(scheme=WENO, physics=EULER, weights=0, krylov_dim=10, restarts=3, jacobi_sweeps=2,
                 gamma=1.4, cfl=10.0, tau_eps=0.1, tau_C=1.0, gamma_lin=0.025, weno_eps=1e-8,
-                mu=0.0, prandtl=1.0, fd_sigma=0.0, cfl_flux=1.0, jv_mode=0, first_order=0)
+                mu=0.0, prandtl=1.0, fd_sigma=0.0, cfl_flux=1.0, jv_mode=0, first_order=0, solver=0)
     for k, v in kw.items():
         setattr(o, k, v)
     return o
@@ -228,6 +231,17 @@ class Oracle:
         QG = np.zeros(5) if want_qg else None
         _load().orc_kfvs_point(self.h, _ptr(Wl), _ptr(Wr), _ptr(F), _ptr(QG))
         return (F, QG) if want_qg else F
+
+    def colours(self):
+        col = np.zeros(self.N, dtype=np.int32)
+        n = _load().orc_colours(self.h, _ptr(col))
+        return col, int(n)
+
+    def lusgs(self, Q, dt, R):
+        Q, dt, R = _f64(Q), _f64(dt), _f64(R)
+        dQ = np.zeros((5, self.N))
+        _load().orc_lusgs(self.h, _ptr(Q), _ptr(dt), _ptr(R), _ptr(dQ))
+        return dQ
 
     def diag(self, Q, dt):
         Q, dt = _f64(Q), _f64(dt)

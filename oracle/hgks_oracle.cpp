@@ -1144,6 +1144,81 @@ static void amatvec(const orc_ctx& C, const double* Q, const double* dt, const d
   }
 }
 
+// Greedy colouring of the face-neighbour graph: cells in index order, each
+// takes the smallest colour that none of its already coloured neighbours has.
+// Cells of one colour share no face, so a Gauss-Seidel sweep may update a
+// whole colour at once.
+static int colour_cells(const orc_ctx& C, std::vector<int>& col) {
+  col.assign(C.N, -1);
+  int ncol = 0;
+  for (int i = 0; i < C.N; ++i) {
+    bool used[8] = {false, false, false, false, false, false, false, false};
+    for (int p = 0; p < 4; ++p) {
+      const Face& f = C.faces[C.cf[i][p]];
+      if (f.R < 0) continue;
+      int j = f.L == i ? f.R : f.L;
+      if (col[j] >= 0) used[col[j]] = true;
+    }
+    int c = 0;
+    while (used[c]) ++c;  // at most 4 neighbours: c <= 4
+    col[i] = c;
+    ncol = std::max(ncol, c + 1);
+  }
+  return ncol;
+}
+
+// LU-SGS of the approximate matrix A = D + L + U of Eq. (deri-matrix) (the
+// factorisation of Jameson and Yoon on an unstructured mesh, the LUSGS-WENO
+// solver the paper compares with in Sec. 5):
+//   (D + L) D^-1 (D + U) dQ = R,
+// L holding the off-diagonal blocks 1/2 S_f (J_n(Q_j) - |lambda_f| I) to the
+// neighbours j of lower colour, U those of higher colour.  Forward sweep:
+// (D + L) y = R in increasing colour; backward sweep: (D + U) dQ = D y in
+// decreasing colour, dQ_i = y_i - D_i^-1 (U dQ)_i.
+static void lusgs(const orc_ctx& C, const double* Q, const double* dt, const double* R, double* dQ) {
+  const int N = C.N;
+  std::vector<double> D(N), lam(C.faces.size()), y((size_t)5 * N);
+  diag(C, Q, dt, D.data());
+  for (size_t f = 0; f < C.faces.size(); ++f) lam[f] = face_lambda(C, Q, (int)f);
+  std::vector<int> col;
+  colour_cells(C, col);
+  std::vector<int> order(N);
+  for (int i = 0; i < N; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return col[a] < col[b]; });
+  // sum over the neighbours j with lower (sgn < 0) or higher (sgn > 0) colour
+  auto offdiag = [&](int i, const std::vector<double>& x, int sgn) {
+    V5 off{0, 0, 0, 0, 0};
+    for (int p = 0; p < 4; ++p) {
+      const Face& f = C.faces[C.cf[i][p]];
+      if (f.R < 0) continue;  // boundary off-diagonal dropped, as in A
+      int j = f.L == i ? f.R : f.L;
+      if ((sgn < 0) != (col[j] < col[i])) continue;
+      V3 nout = f.L == i ? f.n : scl(-1.0, f.n);
+      V5 qj, xj;
+      for (int v = 0; v < 5; ++v) {
+        qj[v] = Q[(size_t)v * N + j];
+        xj[v] = x[(size_t)v * N + j];
+      }
+      V5 jx = euler_jn(C.o.gamma, qj, nout, xj);
+      double l = lam[C.cf[i][p]];
+      for (int v = 0; v < 5; ++v) off[v] += 0.5 * f.S * (jx[v] - l * xj[v]);
+    }
+    return off;
+  };
+  for (int k = 0; k < N; ++k) {
+    int i = order[k];
+    V5 off = offdiag(i, y, -1);
+    for (int v = 0; v < 5; ++v) y[(size_t)v * N + i] = (R[(size_t)v * N + i] - off[v]) / D[i];
+  }
+  std::vector<double> x((size_t)5 * N, 0.0);
+  for (int k = N - 1; k >= 0; --k) {
+    int i = order[k];
+    V5 off = offdiag(i, x, +1);
+    for (int v = 0; v < 5; ++v) x[(size_t)v * N + i] = y[(size_t)v * N + i] - off[v] / D[i];
+  }
+  std::copy(x.begin(), x.end(), dQ);
+}
+
 static double rms(const double* x, size_t n) {
   double s = 0.0;
   for (size_t k = 0; k < n; ++k) s += x[k] * x[k];
@@ -1355,6 +1430,22 @@ static int implicit_step(const orc_ctx& C, double* Q, double* G, orc_step_info* 
   fb += residual(C, Q, G, dt.data(), b.data(), C.o.scheme == 1 ? Gn.data() : nullptr);
   ++evals;
   info->res = res_norm(C, b.data());
+  if (C.o.solver == 1) {
+    // one LU-SGS solve of the approximate system per step
+    std::vector<double> dQ(n);
+    lusgs(C, Q, dt.data(), b.data(), dQ.data());
+    for (size_t k = 0; k < n; ++k) Q[k] += dQ[k];
+    if (C.o.scheme == 1) std::copy(Gn.begin(), Gn.end(), G);
+    info->gmres_rel = 0.0;
+    info->n_resid_evals = evals;
+    info->n_fallbacks = fb;
+    for (int i = 0; i < N; ++i) {
+      V5 q;
+      for (int v = 0; v < 5; ++v) q[v] = Q[(size_t)v * N + i];
+      if (!physical(q, C.o.gamma)) return -4;
+    }
+    return 0;
+  }
   int m = C.o.krylov_dim;
   std::vector<double> dQ(n, 0.0), r(n), rh(n), w(n), y(n);
   std::vector<std::vector<double>> V(m + 1, std::vector<double>(n));
@@ -1601,6 +1692,15 @@ int32_t orc_implicit_step(const orc_ctx* C, double* Q, double* G, orc_step_info*
   return implicit_step(*C, Q, G, info);
 }
 double orc_res_norm(const orc_ctx* C, const double* R) { return res_norm(*C, R); }
+int32_t orc_colours(const orc_ctx* C, int32_t* col) {
+  std::vector<int> c;
+  int n = colour_cells(*C, c);
+  for (int i = 0; i < C->N; ++i) col[i] = c[i];
+  return n;
+}
+void orc_lusgs(const orc_ctx* C, const double* Q, const double* dt, const double* R, double* dQ) {
+  lusgs(*C, Q, dt, R, dQ);
+}
 void orc_amatvec(const orc_ctx* C, const double* Q, const double* dt, const double* x, double* out) {
   amatvec(*C, Q, dt, x, out);
 }

@@ -42,6 +42,9 @@ typedef struct {
                             matrix A of Eq. (deri-matrix) */
   int32_t first_order;   /* 1: first-order KFVS flux of the cell averages (Sec. 5, the
                             supersonic sphere retested with a first-order flux) */
+  int32_t solver;        /* implicit step: 0 GMRES, 1 LU-SGS of the approximate matrix (the
+                            LUSGS-WENO comparison solver of Sec. 5) */
+  int32_t pad;
 } orc_options;
 
 /* boundary kinds */
@@ -128,6 +131,15 @@ typedef struct {
 
 /* one implicit step (Algorithm 1 body); Q, gradQ updated in place */
 int32_t orc_implicit_step(const orc_ctx*, double* Q, double* gradQ, orc_step_info* info);
+
+/* greedy colouring of the cells' face-neighbour graph (col [N]); returns the
+ * number of colours */
+int32_t orc_colours(const orc_ctx*, int32_t* col);
+
+/* LU-SGS solve (D + L) D^-1 (D + U) dQ = R with the approximate matrix of
+ * Eq. (deri-matrix) at state Q and time steps dt; L / U hold the blocks to
+ * neighbours of lower / higher colour */
+void orc_lusgs(const orc_ctx*, const double* Q, const double* dt, const double* R, double* dQ);
 
 /* L1 density residual norm */
 double orc_res_norm(const orc_ctx*, const double* R);
