@@ -55,6 +55,13 @@ enum { HGKS_WEIGHTS_NONLINEAR = 0, HGKS_WEIGHTS_LINEAR = 1 }; /* Sec. 3.4 */
  * A of Eq. (deri-matrix), applied without being stored (the paper's solver,
  * Sec. 4.2: one high-order residual evaluation per step) */
 enum { HGKS_JV_FD = 0, HGKS_JV_APPROX = 1 };
+/* implicit solver of each step: restarted GMRES (Sec. 4.2) on the operator
+ * jv_mode selects, or one LU-SGS solve (D + L) D^-1 (D + U) dQ = L(Q^n) of the
+ * approximate matrix A = D + L + U of Eq. (deri-matrix), L / U being its
+ * blocks to neighbours of lower / higher colour in a greedy colouring of the
+ * cells (the LUSGS-WENO solver the paper compares with, Sec. 5); one residual
+ * evaluation per step, jv_mode / precision / krylov options unused */
+enum { HGKS_SOLVER_GMRES = 0, HGKS_SOLVER_LUSGS = 1 };
 enum { HGKS_FARFIELD = 0, HGKS_SLIP_WALL = 1, HGKS_NOSLIP_ADIABATIC = 2,
        HGKS_SUP_IN = 3, HGKS_SUP_OUT = 4 };          /* Sec. 5 boundary conditions */
 
@@ -67,6 +74,8 @@ typedef struct {
   int32_t restarts;      /* 3, Sec. 5 */
   int32_t jacobi_sweeps; /* 2, Sec. 5 */
   int32_t jv_mode;       /* GMRES operator: HGKS_JV_FD (default) or HGKS_JV_APPROX */
+  int32_t solver;        /* HGKS_SOLVER_GMRES (default) | HGKS_SOLVER_LUSGS */
+  int32_t reserved;      /* 0 */
   double gamma;          /* 1.4 */
   double cfl;            /* 10 */
   double tau_eps;        /* 0.1, inviscid collision time, Sec. 5 */

@@ -94,6 +94,7 @@ struct hgks_ctx {
   double* part = nullptr;   // reduction partials
   double* sc = nullptr;     // device scalars [64]
   int* flags = nullptr;     // [0] positivity fallbacks, [1] bad state
+  std::vector<int> cstart;  // LU-SGS colour classes: offsets into M.cord
   double res0 = -1.0;
   double cfl_now = 10.0;  // CFL of the local time steps (o.cfl, or the ramp of solve_steady)
   // timing of the residual kernels: a pool of event sextets recorded on the
@@ -277,6 +278,7 @@ hgks_status ensure_f32(hgks_ctx* ctx) {
   Mf.N = M.N; Mf.F = M.F; Mf.Nb = M.Nb; Mf.NX = M.NX;
   Mf.fL = M.fL; Mf.fR = M.fR; Mf.fkind = M.fkind; Mf.cface = M.cface; Mf.gowner = M.gowner; Mf.gface = M.gface;
   Mf.stn = M.stn; Mf.sstn = M.sstn; Mf.smask = M.smask; Mf.nb4 = M.nb4;
+  Mf.ccol = M.ccol; Mf.cord = M.cord;
   TRY(upload_mesh_fp<float>(ctx, Mf));
   TRY(alloc_work<float>(ctx, ctx->W32));
 
@@ -348,7 +350,7 @@ hgks_status prepare_base(hgks_ctx* ctx, bool want_grad, hipStream_t s) {
   // the pipeline rewrote the ghosts of W64.Qx from Q^n: still the base point
   launch_lambda_diag<double>(ctx->M, ctx->P, ctx->W64.Qx, ctx->W64.dt, ctx->lam, ctx->D, s);
   launch_dot(ctx->Qc, ctx->Qc, n5(ctx), ctx->part, ctx->sc + 0, false, s);
-  if (ctx->o.precision == HGKS_FP32_INNER && ctx->o.jv_mode == HGKS_JV_FD) {
+  if (ctx->o.precision == HGKS_FP32_INNER && ctx->o.jv_mode == HGKS_JV_FD && ctx->o.solver == HGKS_SOLVER_GMRES) {
     TRY(ensure_f32(ctx));
     launch_perturb<float>(ctx->Qc, nullptr, nullptr, N, NX, ctx->W32.Qx, s);
     launch_dt<float>(ctx->Mf, ctx->P, ctx->cfl_now, ctx->W32.Qx, ctx->W32.dt, s);
@@ -447,6 +449,7 @@ hgks_status hgks_create(const hgks_options* opts, hgks_ctx** out) {
   if (opts->krylov_dim < 1 || opts->krylov_dim > MAXM || opts->restarts < 1 || opts->jacobi_sweeps < 0 ||
       !(opts->gamma > 1.0) || !(opts->cfl > 0.0) || opts->scheme < 0 || opts->scheme > 2 || opts->physics < 0 ||
       opts->physics > 1 || opts->precision < 0 || opts->precision > 1 || opts->jv_mode < 0 || opts->jv_mode > 1 ||
+      opts->solver < HGKS_SOLVER_GMRES || opts->solver > HGKS_SOLVER_LUSGS ||
       (opts->physics == HGKS_NS && !(opts->mu > 0.0 && opts->prandtl > 0.0)) ||
       (opts->physics == HGKS_NS && opts->scheme == HGKS_KFVS1))
     return HGKS_EINVAL;
@@ -500,6 +503,12 @@ hgks_status hgks_load_mesh(hgks_ctx* ctx, int64_t n_nodes, const double* xyz, in
     TRY(upload(ctx, H.stn, M.stn));
     TRY(upload(ctx, H.sstn, M.sstn));
     TRY(upload(ctx, H.smask, M.smask));
+  }
+  if (ctx->o.solver == HGKS_SOLVER_LUSGS) {
+    std::vector<int> col, order;
+    colour_cells(H, col, order, ctx->cstart);
+    TRY(upload(ctx, col, M.ccol));
+    TRY(upload(ctx, order, M.cord));
   }
   ctx->d_fkind = ctx->A.get<int>(H.F);
   if (!ctx->d_fkind) return HGKS_ENOMEM;
@@ -667,18 +676,24 @@ hgks_status hgks_implicit_step(hgks_ctx* ctx, hgks_step_info* info) {
   const int N = ctx->H.N;
   const bool hw = ctx->o.scheme == HGKS_HWENO;
   TRY(prepare_base(ctx, hw, s));
-  const bool fd = ctx->o.jv_mode == HGKS_JV_FD;
+  const bool lusgs = ctx->o.solver == HGKS_SOLVER_LUSGS;
+  const bool fd = !lusgs && ctx->o.jv_mode == HGKS_JV_FD;
   int64_t evals = (fd && ctx->o.precision == HGKS_FP32_INNER) ? 2 : 1;
   // residual norm of the base point (L1 density residual / total volume)
   launch_abssum(ctx->b, (size_t)N, ctx->part, ctx->sc + 3, s);
   double res_abs = 0.0;
   HIPCHK(hipMemcpyAsync(&res_abs, ctx->sc + 3, sizeof(double), hipMemcpyDeviceToHost, s));
   HIPCHK(hipMemsetAsync(ctx->dQ, 0, n * sizeof(double), s));
+  // LU-SGS: one factorised solve of the approximate system, no GMRES cycles
+  if (lusgs) {
+    launch_lusgs<double>(ctx->M, ctx->P, ctx->W64.Qx, ctx->lam, ctx->D, ctx->cstart, ctx->b, ctx->yv, ctx->dQ, s);
+    HIPCHK(hipStreamSynchronize(s));  // res_abs is read below
+  }
   const int m = ctx->o.krylov_dim;
   double beta0 = -1.0, last = 0.0;
   bool nonfinite = false;  // a NaN/Inf in the residual or the preconditioned residual
   double* hc = ctx->sc + 8;  // device column of H (m+1 entries)
-  for (int rs = 0; rs < ctx->o.restarts; ++rs) {
+  for (int rs = 0; rs < (lusgs ? 0 : ctx->o.restarts); ++rs) {
     if (rs == 0) {
       HIPCHK(hipMemcpyAsync(ctx->rv, ctx->b, n * sizeof(double), hipMemcpyDeviceToDevice, s));
     } else {

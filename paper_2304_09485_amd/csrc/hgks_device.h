@@ -38,6 +38,9 @@ struct DevMesh {
   const int* nb4;      // [4][N] face neighbours (extended ids)
   const T* opH;        // [171][N] P0 operator: rows k*19+j, j<4 averages, j>=4 gradients
   const T* hsub;       // [24][N] per sub s: wi, wm, dx, dy, dz, 1/|d|^2
+  // LU-SGS
+  const int* ccol;     // [N]  colour of the cell
+  const int* cord;     // [N]  cell ids sorted by colour
 };
 
 struct Params {

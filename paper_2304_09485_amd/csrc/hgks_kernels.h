@@ -2,6 +2,8 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <vector>
+
 #include "hgks_device.h"
 
 namespace hgks {
@@ -27,6 +29,11 @@ void launch_jacobi(const DevMesh<T>&, const Params&, const T* Qx, const T* lam, 
 template <typename T>
 void launch_amatvec(const DevMesh<T>&, const Params&, const T* Qx, const T* lam, const T* D, const double* x,
                     double* out, hipStream_t);
+// LU-SGS: forward sweep over the colour classes start[c]..start[c+1] of
+// M.cord ((D + L) y = r), then backward (D + U) x = D y
+template <typename T>
+void launch_lusgs(const DevMesh<T>&, const Params&, const T* Qx, const T* lam, const T* D,
+                  const std::vector<int>& start, const double* r, double* y, double* x, hipStream_t);
 template <typename T>
 void launch_perturb(const double* Q, const double* v, const double* sigma, int N, int NX, T* Qp, hipStream_t);
 template <typename T> void launch_check(const T* Qx, int N, int NX, double gamma, int* bad, hipStream_t);

@@ -598,6 +598,50 @@ __global__ void __launch_bounds__(256) k_amatvec(DevMesh<T> M, Params P, const T
   for (int v = 0; v < 5; ++v) out[(size_t)v * N + i] = double(acc[v]);
 }
 
+// One colour class of an LU-SGS sweep (cells cord[c0 .. c0 + nc), colour
+// col): the off-diagonal blocks 1/2 S_f (J_n(Q_j) - |lambda_f|) of the
+// approximate matrix to the interior neighbours of lower (forward) or higher
+// (backward) colour, applied to their already final values in x;
+//   forward  x_i = (b_i - sum) / D_i        ((D + L) y = R, b = R)
+//   backward x_i = b_i - sum / D_i          ((D + U) dQ = D y, b = y)
+// Cells of one colour share no face, so the class updates in parallel.
+template <typename T, bool FWD>
+__global__ void __launch_bounds__(256) k_lusgs(DevMesh<T> M, Params P, const T* __restrict__ Qx,
+                                               const T* __restrict__ lam, const T* __restrict__ D, int c0, int nc,
+                                               int col, const double* __restrict__ b, double* x) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nc) return;
+  const int N = M.N, NX = M.NX, F = M.F;
+  const int i = M.cord[c0 + t];
+  const T g = T(P.gamma);
+  T off[5] = {0, 0, 0, 0, 0};
+#pragma unroll
+  for (int p = 0; p < 4; ++p) {
+    int cf = M.cface[p * N + i];
+    int f = (cf > 0 ? cf : -cf) - 1;
+    int L = M.fL[f], R = M.fR[f];
+    if (R >= N) continue;
+    int jn = cf > 0 ? R : L;
+    int cj = M.ccol[jn];
+    if (FWD ? cj > col : cj < col) continue;
+    T s = cf > 0 ? T(1) : T(-1);
+    T n[3] = {s * M.fn[f], s * M.fn[F + f], s * M.fn[2 * F + f]};
+    T qj[5], xj[5], jx[5];
+    for (int v = 0; v < 5; ++v) {
+      qj[v] = Qx[(size_t)v * NX + jn];
+      xj[v] = T(x[(size_t)v * N + jn]);
+    }
+    euler_jn(g, qj, n, xj, jx);
+    T hs = T(0.5) * M.fS[f], l = lam[f];
+    for (int v = 0; v < 5; ++v) off[v] += hs * (jx[v] - l * xj[v]);
+  }
+  const T d = D[i];
+  for (int v = 0; v < 5; ++v) {
+    T bv = T(b[(size_t)v * N + i]);
+    x[(size_t)v * N + i] = double(FWD ? (bv - off[v]) / d : bv - off[v] / d);
+  }
+}
+
 template <typename T>
 __global__ void __launch_bounds__(256) k_jacobi(DevMesh<T> M, Params P, const T* __restrict__ Qx,
                                                 const T* __restrict__ lam, const T* __restrict__ D,
@@ -830,6 +874,23 @@ void launch_amatvec(const DevMesh<T>& M, const Params& P, const T* Qx, const T* 
   hipLaunchKernelGGL(k_amatvec<T>, dim3(nblk(M.N, 256)), dim3(256), 0, s, M, P, Qx, lam, D, x, out);
 }
 template <typename T>
+void launch_lusgs(const DevMesh<T>& M, const Params& P, const T* Qx, const T* lam, const T* D,
+                  const std::vector<int>& start, const double* r, double* y, double* x, hipStream_t s) {
+  const int nc = (int)start.size() - 1;
+  for (int c = 0; c < nc; ++c) {
+    int cnt = start[c + 1] - start[c];
+    if (cnt)
+      hipLaunchKernelGGL((k_lusgs<T, true>), dim3(nblk(cnt, 256)), dim3(256), 0, s, M, P, Qx, lam, D, start[c], cnt,
+                         c, r, y);
+  }
+  for (int c = nc - 1; c >= 0; --c) {
+    int cnt = start[c + 1] - start[c];
+    if (cnt)
+      hipLaunchKernelGGL((k_lusgs<T, false>), dim3(nblk(cnt, 256)), dim3(256), 0, s, M, P, Qx, lam, D, start[c],
+                         cnt, c, (const double*)y, x);
+  }
+}
+template <typename T>
 void launch_perturb(const double* Q, const double* v, const double* sigma, int N, int NX, T* Qp, hipStream_t s) {
   hipLaunchKernelGGL(k_perturb<T>, dim3(nblk(N, 256)), dim3(256), 0, s, Q, v, sigma, N, NX, Qp);
 }
@@ -886,6 +947,8 @@ void launch_sigma(const double* vv, const double* qq, double n, double eps, doub
                                  const double*, double*, hipStream_t);                                           \
   template void launch_amatvec<T>(const DevMesh<T>&, const Params&, const T*, const T*, const T*, const double*,  \
                                   double*, hipStream_t);                                                         \
+  template void launch_lusgs<T>(const DevMesh<T>&, const Params&, const T*, const T*, const T*,                \
+                               const std::vector<int>&, const double*, double*, double*, hipStream_t);         \
   template void launch_perturb<T>(const double*, const double*, const double*, int, int, T*, hipStream_t);        \
   template void launch_check<T>(const T*, int, int, double, int*, hipStream_t);
 HGKS_INST(double)

@@ -173,6 +173,7 @@ size_t hgks_estimate_bytes(int64_t n_tets, int64_t n_bfaces, const hgks_options*
   bytes += 8.0 * (5 * N + 5 * NX + (hw ? 15 * NX : 0) + N + 10 * N + 15 * N + F + N + (m + 1) * 5 * N + 6 * 5 * N +
                   1024 + 128);
   if (f32) bytes += 4.0 * (fp + work + 5 * NX);
+  if (o && o->solver == HGKS_SOLVER_LUSGS) bytes += 4.0 * 2 * N;  // colours and colour order
   return (size_t)(bytes * 1.05) + ((size_t)16 << 20);
 }
 

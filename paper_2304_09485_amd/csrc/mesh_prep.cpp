@@ -492,4 +492,29 @@ int build_host_mesh(HostMesh& H, int64_t n_nodes, const double* xyz, int64_t n_t
   return 0;
 }
 
+int colour_cells(const HostMesh& H, std::vector<int>& col, std::vector<int>& order, std::vector<int>& start) {
+  const int N = H.N;
+  col.assign(N, -1);
+  int ncol = 0;
+  for (int i = 0; i < N; ++i) {
+    unsigned taken = 0;  // bit c: a coloured neighbour has colour c
+    for (int k = 0; k < 4; ++k) {
+      int j = H.nb4[(size_t)k * N + i];
+      if (j < N && col[j] >= 0) taken |= 1u << col[j];
+    }
+    int c = 0;
+    while (taken & (1u << c)) ++c;
+    col[i] = c;
+    if (c + 1 > ncol) ncol = c + 1;
+  }
+  // counting sort by colour keeps the index order within a colour
+  start.assign(ncol + 1, 0);
+  for (int i = 0; i < N; ++i) ++start[col[i] + 1];
+  for (int c = 0; c < ncol; ++c) start[c + 1] += start[c];
+  order.assign(N, 0);
+  std::vector<int> next(start.begin(), start.end() - 1);
+  for (int i = 0; i < N; ++i) order[next[col[i]]++] = i;
+  return ncol;
+}
+
 }  // namespace hgks

@@ -32,6 +32,12 @@ struct HostMesh {
   double total_volume = 0.0;
 };
 
+// Greedy colouring of the face-neighbour graph for the LU-SGS sweeps: cells
+// in index order each take the smallest colour no already coloured face
+// neighbour has (at most 5 colours for tets).  col [N]; order: cell ids sorted
+// by colour (stable); start [ncol + 1]: offsets of the colour classes in order.
+int colour_cells(const HostMesh& H, std::vector<int>& col, std::vector<int>& order, std::vector<int>& start);
+
 // Returns 0 on success, -3 (mesh error) or -1 (bad argument) with err set.
 int build_host_mesh(HostMesh& H, int64_t n_nodes, const double* xyz, int64_t n_tets, const int32_t* tet2node,
                     int64_t n_bf, const int32_t* bf, const int32_t* btag, std::string& err);

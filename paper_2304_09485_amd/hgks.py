@@ -19,6 +19,7 @@ WENO, HWENO, KFVS1 = 0, 1, 2
 EULER, NS = 0, 1
 FP64, FP32_INNER = 0, 1
 JV_FD, JV_APPROX = 0, 1
+SOLVER_GMRES, SOLVER_LUSGS = 0, 1
 WEIGHTS_NONLINEAR, WEIGHTS_LINEAR = 0, 1
 FARFIELD, SLIP_WALL, NOSLIP_ADIABATIC, SUP_IN, SUP_OUT = 0, 1, 2, 3, 4
 
@@ -43,8 +44,8 @@ class HgksError(RuntimeError):
 class Options(ctypes.Structure):
     _fields_ = [("scheme", ctypes.c_int32), ("physics", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("weights", ctypes.c_int32), ("krylov_dim", ctypes.c_int32), ("restarts", ctypes.c_int32),
-                ("jacobi_sweeps", ctypes.c_int32), ("jv_mode", ctypes.c_int32),
-                ("gamma", ctypes.c_double), ("cfl", ctypes.c_double), ("tau_eps", ctypes.c_double),
+                ("jacobi_sweeps", ctypes.c_int32), ("jv_mode", ctypes.c_int32), ("solver", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("gamma", ctypes.c_double), ("cfl", ctypes.c_double), ("tau_eps", ctypes.c_double),
                 ("tau_C", ctypes.c_double), ("gamma_lin", ctypes.c_double), ("weno_eps", ctypes.c_double),
                 ("mu", ctypes.c_double), ("prandtl", ctypes.c_double), ("fd_sigma", ctypes.c_double),
                 ("cfl_flux", ctypes.c_double), ("cfl_start", ctypes.c_double), ("cfl_growth", ctypes.c_double),
