@@ -84,6 +84,17 @@ def algorithmic_bytes(kernel, N, F, Nb, scheme):
         # cell; per face normal, 2 x 9 Gauss-point offsets and the two cell
         # ids; 60 values written per reconstructed side
         return N * 8 * (105 + 7) + NX * 8 * 5 + F * (8 * 21 + 8) + sides * 8 * 60
+    if kernel == "flux" and scheme == 2:
+        # first-order KFVS: per face the two cell ids, normal, area, the
+        # boundary kind of boundary faces, 5 values written; each cell's state
+        # read once
+        return F * (8 + 24 + 8 + 40) + Nb * 4 + N * 40
+    if kernel == "lusgs_sweep":
+        # one sweep over all colour classes: per cell 4 face ids, colour,
+        # order slot, diagonal, state, right-hand side, its own and (once)
+        # its neighbours' unknowns, 5 values written; per face cell ids,
+        # normal, area and spectral radius
+        return N * (16 + 4 + 4 + 8 + 40 + 40 + 40 + 40) + F * 48
     if kernel == "flux":
         # 60 side values per reconstructed side read; per face the two cell
         # ids, the two cells' time steps, 5 face-flux values written (the
@@ -129,6 +140,9 @@ def main():
     ap.add_argument("--slots", type=int, default=8, help="concurrently admitted requests")
     ap.add_argument("--fp32-inner-serving", action="store_true",
                     help="serve the FP32-inner form (default: plain FP64)")
+    ap.add_argument("--variants-only", action="store_true",
+                    help="only measure the first-order KFVS and LU-SGS variants on the benchmark mesh")
+    ap.add_argument("--lusgs-steps", type=int, default=2000, help="step cap of the LU-SGS convergence run")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (counter calibration) and exit")
     args = ap.parse_args()
@@ -151,6 +165,10 @@ def main():
         serving_bench(hgks, args)
         return
 
+    if args.variants_only:
+        mesh = mesh_for_config("c2")
+        print(json.dumps({"variants": variants_bench(hgks, mesh, len(mesh.bfaces), args.lusgs_steps)}), flush=True)
+        return
     if args.config == "c2":
         mesh = mesh_for_config("c2")
         mach, kinds, opts = 0.5, {1: hgks.SLIP_WALL, 2: hgks.FARFIELD}, dict(scheme=hgks.HWENO)
@@ -227,6 +245,10 @@ def main():
     if not args.no_solve and args.config == "c2":
         solves = time_to_drop(hgks, mesh, kinds, prim, args.solve_steps)
 
+    variants = None
+    if not args.no_solve and args.config == "c2":
+        variants = variants_bench(hgks, mesh, Nb, args.lusgs_steps)
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(mesh, kinds, prim, opts, args.cpu_seconds)
@@ -250,6 +272,7 @@ def main():
         "kernels": kernels,
         "cpu_baseline": cpu,
         "time_to_1e-8": solves,
+        "variants": variants,
         "res_first_last": [infos[0].res, infos[-1].res],
         "setup_s": round(t_setup, 2),
     }
@@ -341,6 +364,68 @@ def time_to_drop(hgks, mesh, kinds, prim, max_steps):
                     "converged": bool(info.converged), "drop": info.drop, "setup_s": round(t_setup, 2)})
         s.close()
         print(f"# time to 1e-8: {out[-1]}", file=sys.stderr, flush=True)
+    return out
+
+
+def _rate(kernel, ms, N, F, Nb, scheme):
+    b = algorithmic_bytes(kernel, N, F, Nb, scheme)
+    return {"avg_ms": round(ms, 4), "bytes": int(b), "GB/s": round(b / (ms * 1e-3) / 1e9, 1),
+            "hbm_frac": round(b / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)}
+
+
+def variants_bench(hgks, mesh, Nb, lusgs_steps):
+    """The first-order KFVS scheme on the supersonic sphere (Mach 3, the
+    retest of Sec. 5) and the LU-SGS comparison solver on the benchmark
+    shell: per-step time, the flux kernel's rate, and convergence."""
+    from inputs import freestream_prim, uniform_state
+    out = {}
+    kinds = {1: hgks.SLIP_WALL, 2: hgks.FARFIELD}
+    # KFVS, GMRES on FD products: kernel rate over 20 steps at CFL 10
+    prim3 = freestream_prim(3.0)
+    s = hgks.Solver(mesh, kinds, prim3, scheme=hgks.KFVS1, cfl=10.0)
+    N, F = s.N, s.F
+    s.set_state(uniform_state(N, prim3))
+    s.implicit_step()
+    s.kernel_times()
+    t0 = time.perf_counter()
+    for _ in range(20):
+        s.implicit_step()
+    ms_step = 1e3 * (time.perf_counter() - t0) / 20
+    kt = s.kernel_times()
+    s.close()
+    ramp = []
+    for cmax in (10.0, 200.0):
+        s = hgks.Solver(mesh, kinds, prim3, scheme=hgks.KFVS1, cfl=cmax, cfl_start=min(5.0, cmax), cfl_growth=1.3)
+        s.set_state(uniform_state(N, prim3))
+        info = s.solve_steady(drop=1e-10, max_steps=400)
+        ramp.append({"cfl": cmax, "cfl_start": min(5.0, cmax), "steps": info.steps, "drop": info.drop,
+                     "converged": bool(info.converged), "seconds": round(info.t_ms * 1e-3, 3)})
+        s.close()
+    out["kfvs_mach3"] = {"ms_per_step": round(ms_step, 3), "flux_kfvs": _rate("flux", kt["flux"], N, F, Nb, 2),
+                         "gather_ms": round(kt["gather"], 4), "time_to_1e-10": ramp}
+    print(f"# KFVS Mach 3: {out['kfvs_mach3']}", file=sys.stderr, flush=True)
+    # LU-SGS, non-compact WENO, Mach 0.5: step time and the drop after lusgs_steps steps
+    prim = freestream_prim(0.5)
+    s = hgks.Solver(mesh, kinds, prim, scheme=hgks.WENO, solver=hgks.SOLVER_LUSGS, cfl=10.0)
+    s.set_state(uniform_state(N, prim))
+    s.implicit_step()
+    s.kernel_times()
+    t0 = time.perf_counter()
+    for _ in range(50):
+        s.implicit_step()
+    ms_step = 1e3 * (time.perf_counter() - t0) / 50
+    kt = s.kernel_times()
+    resid_ms = sum(v for k, v in kt.items() if k != "evaluations")
+    s.close()
+    s = hgks.Solver(mesh, kinds, prim, scheme=hgks.WENO, solver=hgks.SOLVER_LUSGS, cfl=10.0)
+    s.set_state(uniform_state(N, prim))
+    info = s.solve_steady(drop=1e-8, max_steps=lusgs_steps)
+    s.close()
+    out["lusgs_weno"] = {"ms_per_step": round(ms_step, 3), "residual_ms": round(resid_ms, 3),
+                         "sweeps_and_update_ms": round(ms_step - resid_ms, 3), "steps": info.steps,
+                         "drop": info.drop, "seconds": round(info.t_ms * 1e-3, 3),
+                         "sweep_bytes": int(algorithmic_bytes("lusgs_sweep", N, F, Nb, 0))}
+    print(f"# LU-SGS WENO: {out['lusgs_weno']}", file=sys.stderr, flush=True)
     return out
 
 
