@@ -44,6 +44,58 @@ class TetMesh:
                 np.ascontiguousarray(self.btags, dtype=np.int32))
 
 
+@dataclass
+class HexMesh:
+    xyz: np.ndarray            # (n_nodes, 3) float64
+    hexes: np.ndarray          # (n_hex, 8) int32: 0-3 bottom counter-clockwise seen from above, 4-7 above them
+    bfaces: np.ndarray         # (n_bfaces, 4) int32 boundary quadrilaterals
+    btags: np.ndarray          # (n_bfaces,) int32
+    name: str = ""
+    tag_names: dict = field(default_factory=dict)
+
+    @property
+    def n_cells(self) -> int:
+        return int(self.hexes.shape[0])
+
+    @property
+    def tets(self):
+        """cell connectivity under the name the tetrahedral meshes use"""
+        return self.hexes
+
+    def arrays(self):
+        return (np.ascontiguousarray(self.xyz, dtype=np.float64),
+                np.ascontiguousarray(self.hexes, dtype=np.int32),
+                np.ascontiguousarray(self.bfaces, dtype=np.int32),
+                np.ascontiguousarray(self.btags, dtype=np.int32))
+
+
+# hex corner order: lattice (a + 2b + 4c) -> bottom ring, then top ring
+_LAT_TO_RING = [0, 1, 3, 2, 4, 5, 7, 6]
+_QUADS = [(0, 3, 2, 1), (0, 1, 5, 4), (1, 2, 6, 5), (2, 3, 7, 6), (3, 0, 4, 7), (4, 5, 6, 7)]
+
+
+def _finish_hex(xyz, hexes_lat, tag_rules, lat, name, tag_names) -> HexMesh:
+    """Lattice-ordered hexes -> ring order, flipped where the trilinear map is
+    left-handed; boundary quadrilaterals tagged by lattice rules."""
+    h = hexes_lat[:, _LAT_TO_RING].copy()
+    x = xyz[h]
+    jac = np.einsum("ij,ij->i", np.cross(x[:, 1] - x[:, 0], x[:, 3] - x[:, 0]), x[:, 4] - x[:, 0])
+    flip = jac < 0
+    h[flip] = h[flip][:, [4, 5, 6, 7, 0, 1, 2, 3]]
+    quads = np.concatenate([h[:, list(q)] for q in _QUADS])
+    s = np.sort(quads, axis=1).astype(np.int64)
+    n = len(xyz)
+    keys = ((s[:, 0] * n + s[:, 1]) * n + s[:, 2]) * n + s[:, 3]
+    _, first, cnt = np.unique(keys, return_index=True, return_counts=True)
+    if cnt.max() > 2:
+        raise RuntimeError("non-manifold hexahedral mesh")
+    bf = quads[first[cnt == 1]]
+    tags = _tag_by_lattice(bf, lat, tag_rules)
+    return HexMesh(xyz=np.ascontiguousarray(xyz, dtype=np.float64), hexes=np.ascontiguousarray(h, dtype=np.int32),
+                   bfaces=np.ascontiguousarray(bf, dtype=np.int32), btags=np.ascontiguousarray(tags, dtype=np.int32),
+                   name=name, tag_names=tag_names)
+
+
 def _hexes_to_tets(hexes: np.ndarray) -> np.ndarray:
     """hexes: (H, 8) node ids with corner order a + 2b + 4c -> (6H, 4) tets."""
     t = np.stack([hexes[:, list(k)] for k in _KUHN], axis=1)
@@ -112,8 +164,9 @@ def _tag_by_lattice(bf, lat, rules):
     return tags
 
 
-def cube_mesh(n: int, jitter: float = 0.0, seed: int = 0, length: float = 1.0) -> TetMesh:
-    """Unit cube, n^3 hexes x 6 Kuhn tets.  Tags: 1 x-, 2 x+, 3 y-, 4 y+, 5 z-, 6 z+."""
+def cube_mesh(n: int, jitter: float = 0.0, seed: int = 0, length: float = 1.0, hexahedra: bool = False):
+    """Unit cube, n^3 hexes x 6 Kuhn tets (or the n^3 hexahedra themselves).
+    Tags: 1 x-, 2 x+, 3 y-, 4 y+, 5 z-, 6 z+."""
     r = np.arange(n + 1)
     I, J, K = np.meshgrid(r, r, r, indexing="ij")
     lat = np.stack([I.ravel(), J.ravel(), K.ravel()], axis=1)
@@ -129,10 +182,13 @@ def cube_mesh(n: int, jitter: float = 0.0, seed: int = 0, length: float = 1.0) -
         interior = np.all((lat > 0) & (lat < n), axis=1)
         d = rng.uniform(-jitter, jitter, size=xyz.shape) * h[:, None]
         xyz = xyz + d * interior[:, None]
+    rules = [(1, 0, 0), (2, 0, n), (3, 1, 0), (4, 1, n), (5, 2, 0), (6, 2, n)]
+    names = {1: "x-", 2: "x+", 3: "y-", 4: "y+", 5: "z-", 6: "z+"}
+    if hexahedra:
+        return _finish_hex(xyz, hexes, rules, lat, f"hexcube{n}", names)
     bf = _boundary_faces(tets, len(xyz))
-    tags = _tag_by_lattice(bf, lat, [(1, 0, 0), (2, 0, n), (3, 1, 0), (4, 1, n), (5, 2, 0), (6, 2, n)])
-    return _finish(xyz, tets, bf, tags, f"cube{n}",
-                   {1: "x-", 2: "x+", 3: "y-", 4: "y+", 5: "z-", 6: "z+"})
+    tags = _tag_by_lattice(bf, lat, rules)
+    return _finish(xyz, tets, bf, tags, f"cube{n}", names)
 
 
 def _solve_grading(first: float, total: float, nr: int) -> float:
@@ -146,8 +202,9 @@ def _solve_grading(first: float, total: float, nr: int) -> float:
 
 def shell_mesh(n: int, nr: int, r0: float = 0.5, r1: float = 10.0, grading: float | None = 1.1,
                first: float | None = None, jitter: float = 0.0, seed: int = 0,
-               bl_layers: int = 0) -> TetMesh:
-    """Cubed-sphere shell between spheres of radius r0 and r1.
+               bl_layers: int = 0, hexahedra: bool = False):
+    """Cubed-sphere shell between spheres of radius r0 and r1 (tetrahedra, or
+    with hexahedra=True the hexahedra they are cut from).
 
     6 patches of n x n cells per layer, nr geometrically graded radial layers
     (either `grading` is the ratio, or `first` is the first-layer height and the
@@ -205,8 +262,11 @@ def shell_mesh(n: int, nr: int, r0: float = 0.5, r1: float = 10.0, grading: floa
         bl = lev <= bl_layers
         d[bl] -= np.sum(d[bl] * radial[bl], axis=1, keepdims=True) * radial[bl]
         xyz = xyz + d * interior[:, None]
-    bf = _boundary_faces(tets, len(xyz))
     lat = lev[:, None]
+    if hexahedra:
+        return _finish_hex(xyz, hexes, [(1, 0, 0), (2, 0, nr)], lat, f"hexshell{n}x{nr}",
+                           {1: "sphere", 2: "farfield"})
+    bf = _boundary_faces(tets, len(xyz))
     tags = _tag_by_lattice(bf, lat, [(1, 0, 0), (2, 0, nr)])
     return _finish(xyz, tets, bf, tags, f"shell{n}x{nr}", {1: "sphere", 2: "farfield"})
 

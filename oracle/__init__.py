@@ -73,6 +73,12 @@ _vp = ctypes.c_void_p
 def _declare(L):
     L.orc_create.restype = _vp
     L.orc_create.argtypes = [_i64, _vp, _i64, _vp, _i64, _vp, _vp, _i32, _vp, _vp, _P(Options)]
+    L.orc_create_hex.restype = _vp
+    L.orc_create_hex.argtypes = [_i64, _vp, _i64, _vp, _i64, _vp, _vp, _i32, _vp, _vp, _P(Options)]
+    L.orc_face_points.argtypes = [_vp]
+    L.orc_face_points.restype = _i32
+    L.orc_cell_faces.argtypes = [_vp]
+    L.orc_cell_faces.restype = _i32
     L.orc_error.restype = ctypes.c_char_p
     L.orc_destroy.argtypes = [_vp]
     L.orc_set_threads.argtypes = [_i32]
@@ -162,12 +168,16 @@ class Oracle:
             kot[t] = k
         self._keep = (xyz, tets, bf, bt, kot)
         self.prim = _f64(prim)
-        self.h = L.orc_create(len(xyz), _ptr(xyz), len(tets), _ptr(tets), len(bf), _ptr(bf), _ptr(bt),
-                              n_tags, _ptr(kot), _ptr(self.prim), ctypes.byref(self.opts))
+        # a mesh with 8 nodes per cell is hexahedral
+        create = L.orc_create_hex if tets.shape[1] == 8 else L.orc_create
+        self.h = create(len(xyz), _ptr(xyz), len(tets), _ptr(tets), len(bf), _ptr(bf), _ptr(bt),
+                        n_tags, _ptr(kot), _ptr(self.prim), ctypes.byref(self.opts))
         if not self.h:
             raise ValueError("oracle: bad mesh: " + L.orc_error().decode())
         self.N = int(L.orc_n_cells(self.h))
         self.F = int(L.orc_n_faces(self.h))
+        self.ng = int(L.orc_face_points(self.h))
+        self.nf = int(L.orc_cell_faces(self.h))
 
     def __del__(self):
         if getattr(self, "h", None):
@@ -182,7 +192,7 @@ class Oracle:
     def faces(self):
         F = self.F
         L_, R_ = np.zeros(F, np.int32), np.zeros(F, np.int32)
-        S, n, gp = np.zeros(F), np.zeros((3, F)), np.zeros((9, F))
+        S, n, gp = np.zeros(F), np.zeros((3, F)), np.zeros((3 * self.ng, F))
         _load().orc_faces(self.h, _ptr(L_), _ptr(R_), _ptr(S), _ptr(n), _ptr(gp))
         return L_, R_, S, n, gp
 
@@ -209,7 +219,7 @@ class Oracle:
     def side_values(self, Q, f, side, G=None):
         Q = _f64(Q)
         G = None if G is None else _f64(G)
-        out = np.zeros((3, 4, 5))
+        out = np.zeros((self.ng, 4, 5))
         fb = _load().orc_side_values(self.h, _ptr(Q), _ptr(G), int(f), int(side), _ptr(out))
         return out, int(fb)
 

@@ -258,7 +258,9 @@ struct Face {
   int pL = -1, pR = -1;
   V3 n{}, t1{}, t2{}, xc{};
   double S = 0.0;
-  V3 gp[3];
+  int ng = 3;      // Gauss points: 3 on a triangle, 4 on a quadrilateral
+  V3 gp[4];
+  double gw[4] = {0, 0, 0, 0};  // quadrature weights (quadrilaterals; 1/3 each on triangles)
   int kind = -1;  // boundary kind, -1 interior
 };
 
@@ -282,10 +284,11 @@ struct orc_ctx {
   std::vector<V3> cen;
   std::vector<M33> m2;
   std::vector<Face> faces;
-  std::vector<std::array<int, 4>> cf, nb;
+  int nf = 4;  // faces per cell: 4 tetrahedra, 6 hexahedra
+  std::vector<std::array<int, 6>> cf, nb;
   std::vector<Ghost> ghosts;
   std::vector<std::vector<int>> big;
-  std::vector<std::array<std::vector<int>, 4>> sub;
+  std::vector<std::vector<std::vector<int>>> sub;  // non-compact sub-stencils per cell
 
   bool is_ghost(int e) const { return e >= N; }
   const V3& c_of(int e) const { return e < N ? cen[e] : ghosts[e - N].c; }
@@ -480,8 +483,8 @@ void invert5(const double R[5][5], double Ri[5][5]) {
 struct Poly {           // one characteristic component
   double q0;            // cell average
   double a[9];          // P0: linear (3) and quadratic (xx,yy,zz,xy,xz,yz) in xi = (x-c)/h
-  double b[4][3];       // P_m gradients (physical units)
-  bool ok[4];
+  double b[8][3];       // P_m gradients (physical units); up to 8 sub-stencils (hexahedra)
+  bool ok[8];
 };
 
 // mean over cell e of the scaled basis of cell i (xi = (x - c_i)/h_i)
@@ -550,7 +553,7 @@ double beta_lin(const orc_ctx& C, int i, const double b[3]) {
 // Non-compact WENO fits (Sec. 3.2): q[e] are projected averages keyed by
 // position in the big stencil list.
 void fit_weno(const orc_ctx& C, int i, const std::vector<int>& big,
-              const std::array<std::vector<int>, 4>& subs, const std::vector<V5>& qs, Poly P[5]) {
+              const std::vector<std::vector<int>>& subs, const std::vector<V5>& qs, Poly P[5]) {
   int m = (int)big.size() - 1;
   std::vector<double> A(m * 9), B(m * 5), X;
   for (int r = 0; r < m; ++r) {
@@ -574,7 +577,7 @@ void fit_weno(const orc_ctx& C, int i, const std::vector<int>& big,
       for (int k = 0; k < 3; ++k) P[c].a[k] = X[k * 5 + c];
     }
   }
-  for (int s = 0; s < 4; ++s) {
+  for (int s = 0; s < (int)subs.size(); ++s) {
     const std::vector<int>& st = subs[s];
     int ms = (int)st.size() - 1;
     std::vector<double> As(std::max(ms, 0) * 3), Bs(std::max(ms, 0) * 5);
@@ -651,8 +654,8 @@ void fit_hweno(const orc_ctx& C, int i, const std::vector<int>& big,
   }
   // P_m on {i, i_m}: minimise h_i^2|b - g_i|^2 + h_m^2|b - g_m|^2 subject to
   // b . (c_m - c_i) = q_m - q_i
-  for (int s = 0; s < 4; ++s) {
-    bool ok = s < nn;
+  for (int s = 0; s < nn; ++s) {
+    bool ok = true;
     for (int c = 0; c < 5; ++c) P[c].ok[s] = ok;
     if (!ok) continue;
     int e = big[s + 1];
@@ -678,7 +681,7 @@ void fit_hweno(const orc_ctx& C, int i, const std::vector<int>& big,
 // Values and directional derivatives at the 3 Gauss points of face f on side
 // s, local frame.  Returns 1 if the positivity fallback (reading A24) was used.
 static int side_values(const orc_ctx& C, const double* Q, const double* G, int fidx, int side,
-                       double out[3][4][5]) {
+                       double out[4][4][5]) {
   const Face& f = C.faces[fidx];
   int i = side == 0 ? f.L : f.R;
   int j = side == 0 ? (f.R >= 0 ? f.R : C.N + (-f.R - 1)) : f.L;
@@ -700,7 +703,7 @@ static int side_values(const orc_ctx& C, const double* Q, const double* G, int f
   std::vector<int> cbig;
   if (compact) {
     cbig.push_back(i);
-    for (int p = 0; p < 4; ++p) cbig.push_back(C.nb[i][p]);
+    for (int p = 0; p < C.nf; ++p) cbig.push_back(C.nb[i][p]);
   }
   const std::vector<int>& st = compact ? cbig : big;
   std::vector<V5> qs(st.size());
@@ -723,38 +726,40 @@ static int side_values(const orc_ctx& C, const double* Q, const double* G, int f
     fit_weno(C, i, big, C.sub[i], qs, P);
   }
   // weights and point values per characteristic component (Eq. (weno))
-  double qv[3][4][5];
+  const int nsub = compact ? C.nf : (int)C.sub[i].size();
+  const int ng = f.ng;
+  double qv[4][4][5];
   for (int c = 0; c < 5; ++c) {
     int M = 0;
-    for (int s = 0; s < 4; ++s) M += P[c].ok[s] ? 1 : 0;
+    for (int s = 0; s < nsub; ++s) M += P[c].ok[s] ? 1 : 0;
     double gm = C.o.gamma_lin, g0 = 1.0 - gm * M;
-    double w[5];
+    double w[9];
     if (C.o.weights == 1) {
       w[0] = g0;
-      for (int s = 0; s < 4; ++s) w[s + 1] = P[c].ok[s] ? gm : 0.0;
+      for (int s = 0; s < nsub; ++s) w[s + 1] = P[c].ok[s] ? gm : 0.0;
     } else {
-      double b0 = beta_p0(C, i, P[c].a), bm[4];
+      double b0 = beta_p0(C, i, P[c].a), bm[8];
       double tz = 0.0;
-      for (int s = 0; s < 4; ++s)
+      for (int s = 0; s < nsub; ++s)
         if (P[c].ok[s]) {
           bm[s] = beta_lin(C, i, P[c].b[s]);
           tz += std::fabs(b0 - bm[s]) / M;
         }
       double eps = C.o.weno_eps;
-      double wt[5], sum = 0.0;
+      double wt[9], sum = 0.0;
       wt[0] = g0 * (1.0 + tz / (b0 + eps));
       sum += wt[0];
-      for (int s = 0; s < 4; ++s) {
+      for (int s = 0; s < nsub; ++s) {
         wt[s + 1] = P[c].ok[s] ? gm * (1.0 + tz / (bm[s] + eps)) : 0.0;
         sum += wt[s + 1];
       }
-      for (int k = 0; k < 5; ++k) w[k] = wt[k] / sum;
+      for (int k = 0; k <= nsub; ++k) w[k] = wt[k] / sum;
     }
-    for (int g = 0; g < 3; ++g) {
+    for (int g = 0; g < ng; ++g) {
       const V3& x = f.gp[g];
       double val = w[0] / g0 * p0_value(C, i, P[c].q0, P[c].a, x);
       V3 grd = scl(w[0] / g0, p0_grad(C, i, P[c].a, x));
-      for (int s = 0; s < 4; ++s) {
+      for (int s = 0; s < nsub; ++s) {
         if (!P[c].ok[s]) continue;
         double coef = w[s + 1] - w[0] * gm / g0;
         V3 b{P[c].b[s][0], P[c].b[s][1], P[c].b[s][2]};
@@ -768,7 +773,7 @@ static int side_values(const orc_ctx& C, const double* Q, const double* G, int f
     }
   }
   // back to conservative local-frame variables with R*
-  for (int g = 0; g < 3; ++g)
+  for (int g = 0; g < ng; ++g)
     for (int d = 0; d < 4; ++d)
       for (int v = 0; v < 5; ++v) {
         double s = 0.0;
@@ -777,12 +782,12 @@ static int side_values(const orc_ctx& C, const double* Q, const double* G, int f
       }
   // positivity fallback (reading A24)
   bool bad = false;
-  for (int g = 0; g < 3; ++g) {
+  for (int g = 0; g < ng; ++g) {
     V5 w{out[g][0][0], out[g][0][1], out[g][0][2], out[g][0][3], out[g][0][4]};
     if (!physical(w, C.o.gamma)) bad = true;
   }
   if (bad) {
-    for (int g = 0; g < 3; ++g) {
+    for (int g = 0; g < ng; ++g) {
       for (int v = 0; v < 5; ++v) out[g][0][v] = qil[v];
       for (int d = 1; d < 4; ++d)
         for (int v = 0; v < 5; ++v) out[g][d][v] = 0.0;
@@ -967,7 +972,7 @@ static int face_flux(const orc_ctx& C, const double* Q, const double* G, const d
     }
     return 0;
   }
-  double sl[3][4][5], sr[3][4][5];
+  double sl[4][4][5], sr[4][4][5];
   int fb = side_values(C, Q, G, fidx, 0, sl);
   bool bnd = f.R < 0;
   if (!bnd) fb += side_values(C, Q, G, fidx, 1, sr);
@@ -976,7 +981,7 @@ static int face_flux(const orc_ctx& C, const double* Q, const double* G, const d
   // CFL number cfl_flux; the implicit diagonal keeps the step at cfl
   if (C.o.cfl_flux > 0.0) dtf *= C.o.cfl_flux / C.o.cfl;
   V5 Fsum{0, 0, 0, 0, 0}, Qsum{0, 0, 0, 0, 0};
-  for (int g = 0; g < 3; ++g) {
+  for (int g = 0; g < f.ng; ++g) {
     V5 Wl, Wr, dWl[3], dWr[3];
     for (int v = 0; v < 5; ++v) {
       Wl[v] = sl[g][0][v];
@@ -992,9 +997,15 @@ static int face_flux(const orc_ctx& C, const double* Q, const double* G, const d
     }
     V5 Fg, QGg;
     gks_point(C, Wl, dWl, Wr, dWr, dtf, Fg, QGout ? &QGg : nullptr);
-    for (int v = 0; v < 5; ++v) Fsum[v] += Fg[v] / 3.0;  // weights 1/3, reading A1
-    if (QGout)
-      for (int v = 0; v < 5; ++v) Qsum[v] += QGg[v] / 3.0;
+    if (f.ng == 3) {
+      for (int v = 0; v < 5; ++v) Fsum[v] += Fg[v] / 3.0;  // weights 1/3, reading A1
+      if (QGout)
+        for (int v = 0; v < 5; ++v) Qsum[v] += QGg[v] / 3.0;
+    } else {
+      for (int v = 0; v < 5; ++v) Fsum[v] += f.gw[g] * Fg[v];
+      if (QGout)
+        for (int v = 0; v < 5; ++v) Qsum[v] += f.gw[g] * QGg[v];
+    }
   }
   V5 Fg = to_global(Fsum, f);
   for (int v = 0; v < 5; ++v) Fout[v] = f.S * Fg[v];
@@ -1030,7 +1041,7 @@ static int64_t residual(const orc_ctx& C, const double* Q, const double* G, cons
     for (int v = 0; v < 5; ++v) R[(size_t)v * C.N + i] = 0.0;
     if (Gnew)
       for (int k = 0; k < 15; ++k) Gnew[(size_t)k * C.N + i] = 0.0;
-    for (int p = 0; p < 4; ++p) {
+    for (int p = 0; p < C.nf; ++p) {
       int fi = C.cf[i][p];
       const Face& f = C.faces[fi];
       double sg = f.L == i ? 1.0 : -1.0;
@@ -1077,7 +1088,7 @@ static void diag(const orc_ctx& C, const double* Q, const double* dt, double* D)
   for (size_t f = 0; f < C.faces.size(); ++f) lam[f] = face_lambda(C, Q, (int)f);
   for (int i = 0; i < C.N; ++i) {
     double s = C.vol[i] / dt[i];
-    for (int p = 0; p < 4; ++p) s += 0.5 * lam[C.cf[i][p]] * C.faces[C.cf[i][p]].S;
+    for (int p = 0; p < C.nf; ++p) s += 0.5 * lam[C.cf[i][p]] * C.faces[C.cf[i][p]].S;
     D[i] = s;
   }
 }
@@ -1095,7 +1106,7 @@ static void precond(const orc_ctx& C, const double* Q, const double* dt, const d
   for (int k = 0; k < C.o.jacobi_sweeps; ++k) {
     for (int i = 0; i < N; ++i) {
       V5 off{0, 0, 0, 0, 0};
-      for (int p = 0; p < 4; ++p) {
+      for (int p = 0; p < C.nf; ++p) {
         const Face& f = C.faces[C.cf[i][p]];
         if (f.R < 0) continue;  // boundary off-diagonal dropped (A23)
         int j = f.L == i ? f.R : f.L;
@@ -1126,7 +1137,7 @@ static void amatvec(const orc_ctx& C, const double* Q, const double* dt, const d
   for (int i = 0; i < N; ++i) {
     V5 acc;
     for (int v = 0; v < 5; ++v) acc[v] = D[i] * x[(size_t)v * N + i];
-    for (int p = 0; p < 4; ++p) {
+    for (int p = 0; p < C.nf; ++p) {
       const Face& f = C.faces[C.cf[i][p]];
       if (f.R < 0) continue;  // boundary off-diagonal dropped (A23)
       int j = f.L == i ? f.R : f.L;
@@ -1153,7 +1164,7 @@ static int colour_cells(const orc_ctx& C, std::vector<int>& col) {
   int ncol = 0;
   for (int i = 0; i < C.N; ++i) {
     bool used[8] = {false, false, false, false, false, false, false, false};
-    for (int p = 0; p < 4; ++p) {
+    for (int p = 0; p < C.nf; ++p) {
       const Face& f = C.faces[C.cf[i][p]];
       if (f.R < 0) continue;
       int j = f.L == i ? f.R : f.L;
@@ -1188,7 +1199,7 @@ static void lusgs(const orc_ctx& C, const double* Q, const double* dt, const dou
   // sum over the neighbours j with lower (sgn < 0) or higher (sgn > 0) colour
   auto offdiag = [&](int i, const std::vector<double>& x, int sgn) {
     V5 off{0, 0, 0, 0, 0};
-    for (int p = 0; p < 4; ++p) {
+    for (int p = 0; p < C.nf; ++p) {
       const Face& f = C.faces[C.cf[i][p]];
       if (f.R < 0) continue;  // boundary off-diagonal dropped, as in A
       int j = f.L == i ? f.R : f.L;
@@ -1255,92 +1266,16 @@ static double res_norm(const orc_ctx& C, const double* R) {
   return s / v;
 }
 
-static bool build(orc_ctx& C, int64_t n_nodes, const double* xyz, int64_t n_tets,
-                  const int32_t* tets, int64_t n_bf, const int32_t* bf, const int32_t* btag,
-                  int32_t n_tags, const int32_t* kind_of_tag) {
-  int N = (int)n_tets;
-  C.N = N;
-  auto X = [&](int node) { return V3{xyz[3 * node], xyz[3 * node + 1], xyz[3 * node + 2]}; };
-  C.vol.resize(N);
-  C.cen.resize(N);
-  C.m2.resize(N);
-  for (int i = 0; i < N; ++i) {
-    V3 v[4];
-    for (int k = 0; k < 4; ++k) {
-      int nd = tets[4 * i + k];
-      if (nd < 0 || nd >= n_nodes) {
-        g_err = "tet node index out of range";
-        return false;
-      }
-      v[k] = X(nd);
-    }
-    double vol6 = dot(cross(sub(v[1], v[0]), sub(v[2], v[0])), sub(v[3], v[0]));
-    if (!(vol6 > 0.0)) {
-      g_err = "inverted or degenerate tetrahedron " + std::to_string(i);
-      return false;
-    }
-    C.vol[i] = vol6 / 6.0;
-    V3 c{0, 0, 0};
-    for (int k = 0; k < 4; ++k) c = add(c, scl(0.25, v[k]));
-    C.cen[i] = c;
-    // second central moment per unit volume of a simplex: (1/20) sum (v-c)(v-c)^T
-    M33 m{};
-    for (int k = 0; k < 4; ++k) {
-      V3 d = sub(v[k], c);
-      for (int a = 0; a < 3; ++a)
-        for (int b = 0; b < 3; ++b) m[a][b] += d[a] * d[b] / 20.0;
-    }
-    C.m2[i] = m;
-  }
-  // faces: local face p is opposite local vertex p (reading A13)
-  std::map<std::array<int, 3>, int> open;
-  C.cf.assign(N, {-1, -1, -1, -1});
-  C.nb.assign(N, {-1, -1, -1, -1});
-  for (int i = 0; i < N; ++i)
-    for (int p = 0; p < 4; ++p) {
-      std::array<int, 3> nodes;
-      int q = 0;
-      for (int k = 0; k < 4; ++k)
-        if (k != p) nodes[q++] = tets[4 * i + k];
-      std::array<int, 3> key = nodes;
-      std::sort(key.begin(), key.end());
-      auto it = open.find(key);
-      if (it == open.end()) {
-        Face f;
-        f.L = i;
-        f.pL = p;
-        V3 a = X(nodes[0]), b = X(nodes[1]), c = X(nodes[2]);
-        V3 nn = cross(sub(b, a), sub(c, a));
-        f.S = 0.5 * norm(nn);
-        f.n = scl(1.0 / norm(nn), nn);
-        f.xc = scl(1.0 / 3.0, add(add(a, b), c));
-        if (dot(f.n, sub(f.xc, C.cen[i])) < 0) f.n = scl(-1.0, f.n);
-        tangents(f.n, f.t1, f.t2);
-        // 3-point degree-2 rule, barycentric (2/3, 1/6, 1/6), reading A1
-        V3 P[3] = {a, b, c};
-        for (int g = 0; g < 3; ++g)
-          f.gp[g] = add(scl(2.0 / 3.0, P[g]), scl(1.0 / 6.0, add(P[(g + 1) % 3], P[(g + 2) % 3])));
-        open[key] = (int)C.faces.size();
-        C.cf[i][p] = (int)C.faces.size();
-        C.faces.push_back(f);
-      } else {
-        Face& f = C.faces[it->second];
-        if (f.R >= 0) {
-          g_err = "non-manifold face";
-          return false;
-        }
-        f.R = i;
-        f.pR = p;
-        C.cf[i][p] = it->second;
-        C.nb[i][p] = f.L;
-        C.nb[f.L][f.pL] = i;
-        open.erase(it);
-      }
-    }
-  // boundary faces: the remaining open ones must be listed with a tag
-  std::map<std::array<int, 3>, int> btags;
+// Boundary matching, ghost cells, length scales and stencils, common to both
+// cell shapes.  open: faces seen once, keyed by their sorted node ids.
+template <typename Key>
+static bool finish_mesh(orc_ctx& C, std::map<Key, int>& open, int64_t n_bf, const int32_t* bf,
+                        const int32_t* btag, int32_t n_tags, const int32_t* kind_of_tag) {
+  const int N = C.N, nv = (int)std::tuple_size<Key>::value;
+  std::map<Key, int> btags;
   for (int64_t k = 0; k < n_bf; ++k) {
-    std::array<int, 3> key{bf[3 * k], bf[3 * k + 1], bf[3 * k + 2]};
+    Key key;
+    for (int q = 0; q < nv; ++q) key[q] = bf[nv * k + q];
     std::sort(key.begin(), key.end());
     btags[key] = btag[k];
   }
@@ -1377,14 +1312,16 @@ static bool build(orc_ctx& C, int64_t n_nodes, const double* xyz, int64_t n_tets
     C.ghosts.push_back(g);
     C.nb[f.L][f.pL] = N + gid;
   }
-  // length scales: h = |Omega|^(1/3); time-step length 3|Omega|/max S (A18)
+  // length scales: h = |Omega|^(1/3); time-step length 3|Omega|/max S for a
+  // tetrahedron (its height), |Omega|/max S for a hexahedron (its width),
+  // readings A18 and A31
   C.hcell.resize(N);
   C.hdt.resize(N);
   for (int i = 0; i < N; ++i) {
     C.hcell[i] = std::cbrt(C.vol[i]);
     double smax = 0.0;
-    for (int p = 0; p < 4; ++p) smax = std::max(smax, C.faces[C.cf[i][p]].S);
-    C.hdt[i] = 3.0 * C.vol[i] / smax;
+    for (int p = 0; p < C.nf; ++p) smax = std::max(smax, C.faces[C.cf[i][p]].S);
+    C.hdt[i] = (C.nf == 4 ? 3.0 : 1.0) * C.vol[i] / smax;
   }
   // stencils (Sec. 3.1, reading A13)
   C.big.resize(N);
@@ -1395,27 +1332,280 @@ static bool build(orc_ctx& C, int64_t n_nodes, const double* xyz, int64_t n_tets
   for (int i = 0; i < N; ++i) {
     std::vector<int>& b = C.big[i];
     b.push_back(i);
-    for (int p = 0; p < 4; ++p) push_unique(b, C.nb[i][p]);
-    for (int p = 0; p < 4; ++p) {
+    for (int p = 0; p < C.nf; ++p) push_unique(b, C.nb[i][p]);
+    for (int p = 0; p < C.nf; ++p) {
       int j = C.nb[i][p];
       if (j >= N) continue;  // ghosts have no neighbours
-      for (int q = 0; q < 4; ++q)
+      for (int q = 0; q < C.nf; ++q)
         if (C.nb[j][q] != i) push_unique(b, C.nb[j][q]);
     }
-    // S_i1 = {i, i1, i2, i3, nbrs of i1}, S_i2 = {i, i1, i2, i4, nbrs of i2},
-    // S_i3 = {i, i2, i3, i4, nbrs of i3}, S_i4 = {i, i3, i1, i4, nbrs of i4}
-    const int first[4][3] = {{0, 1, 2}, {0, 1, 3}, {1, 2, 3}, {2, 0, 3}};
-    for (int m = 0; m < 4; ++m) {
-      std::vector<int>& s = C.sub[i][m];
-      s.push_back(i);
-      for (int k = 0; k < 3; ++k) push_unique(s, C.nb[i][first[m][k]]);
-      int j = C.nb[i][m];
-      if (j < N)
-        for (int q = 0; q < 4; ++q)
-          if (C.nb[j][q] != i) push_unique(s, C.nb[j][q]);
+    if (C.nf == 4) {
+      // S_i1 = {i, i1, i2, i3, nbrs of i1}, S_i2 = {i, i1, i2, i4, nbrs of i2},
+      // S_i3 = {i, i2, i3, i4, nbrs of i3}, S_i4 = {i, i3, i1, i4, nbrs of i4}
+      const int first[4][3] = {{0, 1, 2}, {0, 1, 3}, {1, 2, 3}, {2, 0, 3}};
+      C.sub[i].assign(4, {});
+      for (int m = 0; m < 4; ++m) {
+        std::vector<int>& st = C.sub[i][m];
+        st.push_back(i);
+        for (int k = 0; k < 3; ++k) push_unique(st, C.nb[i][first[m][k]]);
+        int j = C.nb[i][m];
+        if (j < N)
+          for (int q = 0; q < 4; ++q)
+            if (C.nb[j][q] != i) push_unique(st, C.nb[j][q]);
+      }
+    } else {
+      // hexahedron, faces F1..F6 = local faces 0..5 (F1, F6 opposite, F2..F5
+      // around in order): S_m = {i, i1 or i6, two consecutive lateral
+      // neighbours}, m = 1..8 (Sec. 3.1)
+      const int lat[5] = {1, 2, 3, 4, 1};
+      C.sub[i].assign(8, {});
+      for (int m = 0; m < 8; ++m) {
+        std::vector<int>& st = C.sub[i][m];
+        st.push_back(i);
+        push_unique(st, C.nb[i][m < 4 ? 0 : 5]);
+        push_unique(st, C.nb[i][lat[m % 4]]);
+        push_unique(st, C.nb[i][lat[m % 4 + 1]]);
+      }
     }
   }
   return true;
+}
+
+static bool build(orc_ctx& C, int64_t n_nodes, const double* xyz, int64_t n_tets,
+                  const int32_t* tets, int64_t n_bf, const int32_t* bf, const int32_t* btag,
+                  int32_t n_tags, const int32_t* kind_of_tag) {
+  int N = (int)n_tets;
+  C.N = N;
+  C.nf = 4;
+  auto X = [&](int node) { return V3{xyz[3 * node], xyz[3 * node + 1], xyz[3 * node + 2]}; };
+  C.vol.resize(N);
+  C.cen.resize(N);
+  C.m2.resize(N);
+  for (int i = 0; i < N; ++i) {
+    V3 v[4];
+    for (int k = 0; k < 4; ++k) {
+      int nd = tets[4 * i + k];
+      if (nd < 0 || nd >= n_nodes) {
+        g_err = "tet node index out of range";
+        return false;
+      }
+      v[k] = X(nd);
+    }
+    double vol6 = dot(cross(sub(v[1], v[0]), sub(v[2], v[0])), sub(v[3], v[0]));
+    if (!(vol6 > 0.0)) {
+      g_err = "inverted or degenerate tetrahedron " + std::to_string(i);
+      return false;
+    }
+    C.vol[i] = vol6 / 6.0;
+    V3 c{0, 0, 0};
+    for (int k = 0; k < 4; ++k) c = add(c, scl(0.25, v[k]));
+    C.cen[i] = c;
+    // second central moment per unit volume of a simplex: (1/20) sum (v-c)(v-c)^T
+    M33 m{};
+    for (int k = 0; k < 4; ++k) {
+      V3 d = sub(v[k], c);
+      for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) m[a][b] += d[a] * d[b] / 20.0;
+    }
+    C.m2[i] = m;
+  }
+  // faces: local face p is opposite local vertex p (reading A13)
+  std::map<std::array<int, 3>, int> open;
+  C.cf.assign(N, {-1, -1, -1, -1, -1, -1});
+  C.nb.assign(N, {-1, -1, -1, -1, -1, -1});
+  for (int i = 0; i < N; ++i)
+    for (int p = 0; p < 4; ++p) {
+      std::array<int, 3> nodes;
+      int q = 0;
+      for (int k = 0; k < 4; ++k)
+        if (k != p) nodes[q++] = tets[4 * i + k];
+      std::array<int, 3> key = nodes;
+      std::sort(key.begin(), key.end());
+      auto it = open.find(key);
+      if (it == open.end()) {
+        Face f;
+        f.L = i;
+        f.pL = p;
+        V3 a = X(nodes[0]), b = X(nodes[1]), c = X(nodes[2]);
+        V3 nn = cross(sub(b, a), sub(c, a));
+        f.S = 0.5 * norm(nn);
+        f.n = scl(1.0 / norm(nn), nn);
+        f.xc = scl(1.0 / 3.0, add(add(a, b), c));
+        if (dot(f.n, sub(f.xc, C.cen[i])) < 0) f.n = scl(-1.0, f.n);
+        tangents(f.n, f.t1, f.t2);
+        // 3-point degree-2 rule, barycentric (2/3, 1/6, 1/6), reading A1
+        V3 P[3] = {a, b, c};
+        f.ng = 3;
+        for (int g = 0; g < 3; ++g) {
+          f.gp[g] = add(scl(2.0 / 3.0, P[g]), scl(1.0 / 6.0, add(P[(g + 1) % 3], P[(g + 2) % 3])));
+          f.gw[g] = 1.0 / 3.0;
+        }
+        open[key] = (int)C.faces.size();
+        C.cf[i][p] = (int)C.faces.size();
+        C.faces.push_back(f);
+      } else {
+        Face& f = C.faces[it->second];
+        if (f.R >= 0) {
+          g_err = "non-manifold face";
+          return false;
+        }
+        f.R = i;
+        f.pR = p;
+        C.cf[i][p] = it->second;
+        C.nb[i][p] = f.L;
+        C.nb[f.L][f.pL] = i;
+        open.erase(it);
+      }
+    }
+  return finish_mesh(C, open, n_bf, bf, btag, n_tags, kind_of_tag);
+}
+
+// Hexahedral cells (nodes in the usual order: 0-3 the bottom quadrilateral
+// counter-clockwise seen from above, 4-7 the top one above them), mapped
+// trilinearly from the unit cube.  Cell integrals use the 3-point
+// Gauss-Legendre rule per direction, which is exact for the volume, the
+// centroid and the second moments of a trilinear cell (integrands of degree
+// <= 4 per reference direction).  Faces are the bilinear quadrilaterals; the
+// face vector area is exact, (x_c - x_a) x (x_d - x_b) / 2, and its 2x2
+// Gauss points carry weights proportional to the normal component of the
+// area element (they sum to one exactly) -- reading A30.
+static bool build_hex(orc_ctx& C, int64_t n_nodes, const double* xyz, int64_t n_hex,
+                      const int32_t* hexes, int64_t n_bf, const int32_t* bf, const int32_t* btag,
+                      int32_t n_tags, const int32_t* kind_of_tag) {
+  const int N = (int)n_hex;
+  C.N = N;
+  C.nf = 6;
+  auto X = [&](int node) { return V3{xyz[3 * node], xyz[3 * node + 1], xyz[3 * node + 2]}; };
+  // reference corners (r, s, t) of the node order
+  const int rc[8][3] = {{0, 0, 0}, {1, 0, 0}, {1, 1, 0}, {0, 1, 0}, {0, 0, 1}, {1, 0, 1}, {1, 1, 1}, {0, 1, 1}};
+  const double gx[3] = {0.5 - 0.5 * std::sqrt(0.6), 0.5, 0.5 + 0.5 * std::sqrt(0.6)};
+  const double gw3[3] = {5.0 / 18.0, 8.0 / 18.0, 5.0 / 18.0};
+  C.vol.resize(N);
+  C.cen.resize(N);
+  C.m2.resize(N);
+  for (int i = 0; i < N; ++i) {
+    V3 v[8];
+    for (int k = 0; k < 8; ++k) {
+      int nd = hexes[8 * i + k];
+      if (nd < 0 || nd >= n_nodes) {
+        g_err = "hex node index out of range";
+        return false;
+      }
+      v[k] = X(nd);
+    }
+    // position and Jacobian of the trilinear map at (r, s, t)
+    auto map = [&](double r, double s, double t, V3& x, double& J) {
+      V3 dr{0, 0, 0}, ds{0, 0, 0}, dt{0, 0, 0};
+      x = {0, 0, 0};
+      for (int k = 0; k < 8; ++k) {
+        double fr = rc[k][0] ? r : 1.0 - r, fs = rc[k][1] ? s : 1.0 - s, ft = rc[k][2] ? t : 1.0 - t;
+        double sr = rc[k][0] ? 1.0 : -1.0, ss = rc[k][1] ? 1.0 : -1.0, st = rc[k][2] ? 1.0 : -1.0;
+        x = add(x, scl(fr * fs * ft, v[k]));
+        dr = add(dr, scl(sr * fs * ft, v[k]));
+        ds = add(ds, scl(fr * ss * ft, v[k]));
+        dt = add(dt, scl(fr * fs * st, v[k]));
+      }
+      J = dot(cross(dr, ds), dt);
+    };
+    // a valid cell has a positive Jacobian at its corners and Gauss points
+    bool ok = true;
+    for (int k = 0; k < 8 && ok; ++k) {
+      V3 x;
+      double J;
+      map(rc[k][0], rc[k][1], rc[k][2], x, J);
+      ok = J > 0.0 && std::isfinite(J);
+    }
+    double vol = 0.0;
+    V3 c{0, 0, 0};
+    std::vector<std::pair<V3, double>> pts;
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b)
+        for (int d = 0; d < 3; ++d) {
+          V3 x;
+          double J;
+          map(gx[a], gx[b], gx[d], x, J);
+          if (!(J > 0.0)) ok = false;
+          double w = gw3[a] * gw3[b] * gw3[d] * J;
+          pts.push_back({x, w});
+          vol += w;
+          c = add(c, scl(w, x));
+        }
+    if (!ok) {
+      g_err = "inverted or degenerate hexahedron " + std::to_string(i);
+      return false;
+    }
+    c = scl(1.0 / vol, c);
+    M33 m{};
+    for (auto& pw : pts) {
+      V3 d = sub(pw.first, c);
+      for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) m[a][b] += pw.second * d[a] * d[b] / vol;
+    }
+    C.vol[i] = vol;
+    C.cen[i] = c;
+    C.m2[i] = m;
+  }
+  // local faces F1..F6 = 0..5: bottom, the four sides in order around, top;
+  // node lists counter-clockwise seen from outside
+  const int fn[6][4] = {{0, 3, 2, 1}, {0, 1, 5, 4}, {1, 2, 6, 5}, {2, 3, 7, 6}, {3, 0, 4, 7}, {4, 5, 6, 7}};
+  const double q0 = 0.5 - 0.5 / std::sqrt(3.0), q1 = 0.5 + 0.5 / std::sqrt(3.0);
+  const double quv[4][2] = {{q0, q0}, {q1, q0}, {q1, q1}, {q0, q1}};
+  std::map<std::array<int, 4>, int> open;
+  C.cf.assign(N, {-1, -1, -1, -1, -1, -1});
+  C.nb.assign(N, {-1, -1, -1, -1, -1, -1});
+  for (int i = 0; i < N; ++i)
+    for (int p = 0; p < 6; ++p) {
+      std::array<int, 4> nodes;
+      for (int k = 0; k < 4; ++k) nodes[k] = hexes[8 * i + fn[p][k]];
+      std::array<int, 4> key = nodes;
+      std::sort(key.begin(), key.end());
+      auto it = open.find(key);
+      if (it == open.end()) {
+        Face f;
+        f.L = i;
+        f.pL = p;
+        V3 a = X(nodes[0]), b = X(nodes[1]), c = X(nodes[2]), d = X(nodes[3]);
+        V3 sv = scl(0.5, cross(sub(c, a), sub(d, b)));
+        f.S = norm(sv);
+        if (!(f.S > 0.0)) {
+          g_err = "degenerate quadrilateral face of hexahedron " + std::to_string(i);
+          return false;
+        }
+        f.n = scl(1.0 / f.S, sv);
+        f.ng = 4;
+        V3 xc{0, 0, 0};
+        for (int g = 0; g < 4; ++g) {
+          double u = quv[g][0], w = quv[g][1];
+          f.gp[g] = add(add(scl((1 - u) * (1 - w), a), scl(u * (1 - w), b)), add(scl(u * w, c), scl((1 - u) * w, d)));
+          V3 xu = add(scl(1 - w, sub(b, a)), scl(w, sub(c, d)));
+          V3 xw = add(scl(1 - u, sub(d, a)), scl(u, sub(c, b)));
+          f.gw[g] = 0.25 * dot(cross(xu, xw), f.n) / f.S;
+          xc = add(xc, scl(f.gw[g], f.gp[g]));
+        }
+        f.xc = xc;
+        if (dot(f.n, sub(f.xc, C.cen[i])) < 0) {
+          g_err = "face normal does not point out of hexahedron " + std::to_string(i);
+          return false;
+        }
+        tangents(f.n, f.t1, f.t2);
+        open[key] = (int)C.faces.size();
+        C.cf[i][p] = (int)C.faces.size();
+        C.faces.push_back(f);
+      } else {
+        Face& f = C.faces[it->second];
+        if (f.R >= 0) {
+          g_err = "non-manifold face";
+          return false;
+        }
+        f.R = i;
+        f.pR = p;
+        C.cf[i][p] = it->second;
+        C.nb[i][p] = f.L;
+        C.nb[f.L][f.pL] = i;
+        open.erase(it);
+      }
+    }
+  return finish_mesh(C, open, n_bf, bf, btag, n_tags, kind_of_tag);
 }
 
 // ---------------------------------------------------------------------------
@@ -1553,6 +1743,24 @@ orc_ctx* orc_create(int64_t n_nodes, const double* xyz, int64_t n_tets, const in
   }
   return C;
 }
+orc_ctx* orc_create_hex(int64_t n_nodes, const double* xyz, int64_t n_hex, const int32_t* hexes,
+                        int64_t n_bf, const int32_t* bf, const int32_t* btag, int32_t n_tags,
+                        const int32_t* kind_of_tag, const double* prim, const orc_options* opts) {
+  orc_ctx* C = new orc_ctx;
+  C->o = *opts;
+  C->K = (5.0 - 3.0 * opts->gamma) / (opts->gamma - 1.0);
+  C->rhoinf = prim[0];
+  C->uinf = {prim[1], prim[2], prim[3]};
+  C->pinf = prim[4];
+  C->qinf = to_cons(prim[0], C->uinf, prim[4], opts->gamma);
+  if (!build_hex(*C, n_nodes, xyz, n_hex, hexes, n_bf, bf, btag, n_tags, kind_of_tag)) {
+    delete C;
+    return nullptr;
+  }
+  return C;
+}
+int32_t orc_face_points(const orc_ctx* C) { return C->faces.empty() ? 0 : C->faces[0].ng; }
+int32_t orc_cell_faces(const orc_ctx* C) { return C->nf; }
 const char* orc_error(void) { return g_err.c_str(); }
 void orc_destroy(orc_ctx* C) { delete C; }
 void orc_set_threads(int32_t n) { nthreads_req = n > 0 ? n : 1; }
@@ -1577,11 +1785,12 @@ void orc_faces(const orc_ctx* C, int32_t* L, int32_t* R, double* area, double* n
     R[f] = x.R;
     area[f] = x.S;
     for (int d = 0; d < 3; ++d) nrm[d * F + f] = x.n[d];
-    for (int g = 0; g < 3; ++g)
+    for (int g = 0; g < x.ng; ++g)
       for (int d = 0; d < 3; ++d) gp[(g * 3 + d) * F + f] = x.gp[g][d];
   }
 }
 int32_t orc_stencil(const orc_ctx* C, int64_t cell, int32_t which, int32_t* members, int32_t cap) {
+  if (which < 0 || which > (int)C->sub[cell].size()) return -1;
   const std::vector<int>& s = which == 0 ? C->big[cell] : C->sub[cell][which - 1];
   int n = (int)s.size();
   for (int k = 0; k < n && k < cap; ++k) members[k] = s[k];
@@ -1610,9 +1819,9 @@ int32_t orc_side_values(const orc_ctx* C, const double* Q, const double* G, int6
     zero.assign((size_t)15 * C->N, 0.0);
     G = zero.data();
   }
-  double o[3][4][5];
+  double o[4][4][5];
   int r = side_values(*C, Q, G, (int)f, side, o);
-  std::memcpy(out, o, sizeof(o));
+  std::memcpy(out, o, sizeof(double) * 20 * C->faces[f].ng);
   return r;
 }
 void orc_face_frame(const orc_ctx* C, int64_t f, double* out) {

@@ -58,6 +58,15 @@ orc_ctx* orc_create(int64_t n_nodes, const double* xyz, int64_t n_tets, const in
                     int64_t n_bf, const int32_t* bf, const int32_t* btag, int32_t n_tags,
                     const int32_t* kind_of_tag, const double* freestream_prim,
                     const orc_options* opts);
+/* Hexahedral mesh (reading A30): hexes [n_hex][8] with nodes 0-3 the bottom
+ * quadrilateral counter-clockwise seen from above and 4-7 the top one above
+ * them (positive trilinear Jacobian); boundary quadrilaterals bf [n_bf][4]. */
+orc_ctx* orc_create_hex(int64_t n_nodes, const double* xyz, int64_t n_hex, const int32_t* hexes,
+                        int64_t n_bf, const int32_t* bf, const int32_t* btag, int32_t n_tags,
+                        const int32_t* kind_of_tag, const double* prim, const orc_options* opts);
+/* Gauss points per face (3 triangles, 4 quadrilaterals) and faces per cell */
+int32_t orc_face_points(const orc_ctx*);
+int32_t orc_cell_faces(const orc_ctx*);
 const char* orc_error(void);
 void orc_destroy(orc_ctx*);
 void orc_set_threads(int32_t n);

@@ -106,9 +106,44 @@ def tet_quadrature(verts, order=6):
     return pts, w * vol
 
 
+# trilinear map of a hexahedron from the unit cube; corners in ring order
+# (0-3 bottom counter-clockwise, 4-7 above them)
+_HEX_REF = np.array([[0, 0, 0], [1, 0, 0], [1, 1, 0], [0, 1, 0], [0, 0, 1], [1, 0, 1], [1, 1, 1], [0, 1, 1]], float)
+
+
+def hex_quadrature(verts, order=5):
+    """Tensor Gauss rule on the trilinear image of the unit cube: points
+    (P, 3), weights (P,) summing to the volume (exact for the volume, centroid
+    and second moments from order 3 on)."""
+    g, wg = np.polynomial.legendre.leggauss(order)
+    g = 0.5 * (g + 1)
+    wg = 0.5 * wg
+    r, s, t = [x.ravel() for x in np.meshgrid(g, g, g, indexing="ij")]
+    w = np.einsum("i,j,k->ijk", wg, wg, wg).ravel()
+    v = np.asarray(verts, float)
+    c = _HEX_REF
+    fr = np.where(c[:, 0][None] == 1, r[:, None], 1 - r[:, None])
+    fs = np.where(c[:, 1][None] == 1, s[:, None], 1 - s[:, None])
+    ft = np.where(c[:, 2][None] == 1, t[:, None], 1 - t[:, None])
+    sr, ss, st = 2 * c[:, 0] - 1, 2 * c[:, 1] - 1, 2 * c[:, 2] - 1
+    pts = (fr * fs * ft) @ v
+    dr = (sr[None] * fs * ft) @ v
+    ds = (fr * ss[None] * ft) @ v
+    dt = (fr * fs * st[None]) @ v
+    J = np.einsum("pi,pi->p", np.cross(dr, ds), dt)
+    return pts, w * J
+
+
 def cell_averages(mesh, func, order=6):
     """Quadrature cell averages of func(points (P,3)) -> (5, P) for every tet
-    (vectorised Duffy rule, exact for polynomials of degree <= 2*order-3)."""
+    (vectorised Duffy rule, exact for polynomials of degree <= 2*order-3), or
+    every hexahedron (tensor Gauss rule on its trilinear map)."""
+    if mesh.tets.shape[1] == 8:
+        out = np.zeros((5, len(mesh.tets)))
+        for i, h in enumerate(mesh.tets):
+            pts, w = hex_quadrature(mesh.xyz[h], order=max(order, 3))
+            out[:, i] = func(pts) @ w / w.sum()
+        return out
     g, wg = np.polynomial.legendre.leggauss(order)
     g = 0.5 * (g + 1)
     wg = 0.5 * wg
