@@ -132,6 +132,21 @@ hgks_status hgks_load_mesh(hgks_ctx* ctx, int64_t n_nodes, const double* xyz, in
                            const int32_t* tet2node, int64_t n_bfaces, const int32_t* bface2node,
                            const int32_t* bface_tag);
 
+/* Load a hexahedral mesh (Sec. 3.1; the paper's sphere cases use hexahedra):
+ * hex2node [n_hex][8], nodes 0-3 the bottom quadrilateral counter-clockwise
+ * seen from above and 4-7 the top one above them (a positive Jacobian of the
+ * trilinear map at every corner); boundary quadrilaterals bface2node
+ * [n_bfaces][4] with tags as for hgks_load_mesh.  Cells are trilinear, faces
+ * bilinear with 2x2 Gauss points weighted by the normal component of their
+ * area element; the non-compact scheme uses the eight sub-stencils {i, i_1 or
+ * i_6, two consecutive lateral neighbours} (local faces 1-6: bottom, the four
+ * sides in order around, top), the compact one the six {i, i_f}.  Everything
+ * else (schemes, solvers, precision) works as on tetrahedra; the server takes
+ * tetrahedral meshes only.  HGKS_EMESH on a bad mesh. */
+hgks_status hgks_load_hex_mesh(hgks_ctx* ctx, int64_t n_nodes, const double* xyz, int64_t n_hex,
+                               const int32_t* hex2node, int64_t n_bfaces, const int32_t* bface2node,
+                               const int32_t* bface_tag);
+
 /* Free stream (rho, U, V, W, p) used by far-field and supersonic-inflow
  * boundaries (Sec. 5). */
 hgks_status hgks_set_freestream(hgks_ctx* ctx, const double prim[5]);

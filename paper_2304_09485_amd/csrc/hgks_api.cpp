@@ -195,6 +195,7 @@ hgks_status upload_mesh_fp(hgks_ctx* ctx, DevMesh<T>& M) {
   TRY(upload_conv(ctx, H.fS, M.fS));
   TRY(upload_conv(ctx, H.fxiL, M.fxiL));
   TRY(upload_conv(ctx, H.fxiR, M.fxiR));
+  if (H.ng == 4) TRY(upload_conv(ctx, H.fw, M.fw));
   if (ctx->o.scheme == HGKS_HWENO) {
     TRY(upload_conv(ctx, H.opH, M.opH));
     TRY(upload_conv(ctx, H.hsub, M.hsub));
@@ -212,8 +213,11 @@ hgks_status alloc_work(hgks_ctx* ctx, Work<T>& w) {
   w.Qx = ctx->A.get<T>(5 * NX);
   // the first-order scheme has no reconstruction coefficients or side values
   const bool ho = ctx->o.scheme != HGKS_KFVS1;
-  w.coef = ho ? ctx->A.get<T>(105 * N) : nullptr;
-  w.sv = ho ? ctx->A.get<T>(60 * 2 * F) : nullptr;
+  // 9 + 3 M coefficient vectors per cell (M sub-stencils: 4 on a tetrahedron,
+  // 8 non-compact or 6 compact on a hexahedron); 20 values per Gauss point
+  const size_t nsub = H.nf == 4 ? 4 : (ctx->o.scheme == HGKS_HWENO ? 6 : 8);
+  w.coef = ho ? ctx->A.get<T>(5 * (9 + 3 * nsub) * N) : nullptr;
+  w.sv = ho ? ctx->A.get<T>((size_t)20 * H.ng * 2 * F) : nullptr;
   w.ff = ctx->A.get<T>(5 * F);
   w.fq = ctx->A.get<T>(5 * F);
   w.dt = ctx->A.get<T>(N);
@@ -276,8 +280,9 @@ hgks_status ensure_f32(hgks_ctx* ctx) {
   DevMesh<float>& Mf = ctx->Mf;
   const DevMesh<double>& M = ctx->M;
   Mf.N = M.N; Mf.F = M.F; Mf.Nb = M.Nb; Mf.NX = M.NX;
+  Mf.nf = M.nf; Mf.ng = M.ng; Mf.nbig = M.nbig;
   Mf.fL = M.fL; Mf.fR = M.fR; Mf.fkind = M.fkind; Mf.cface = M.cface; Mf.gowner = M.gowner; Mf.gface = M.gface;
-  Mf.stn = M.stn; Mf.sstn = M.sstn; Mf.smask = M.smask; Mf.nb4 = M.nb4;
+  Mf.stn = M.stn; Mf.sstn = M.sstn; Mf.smask = M.smask; Mf.nbf = M.nbf;
   Mf.ccol = M.ccol; Mf.cord = M.cord;
   TRY(upload_mesh_fp<float>(ctx, Mf));
   TRY(alloc_work<float>(ctx, ctx->W32));
@@ -472,6 +477,9 @@ hgks_status hgks_create(const hgks_options* opts, hgks_ctx** out) {
   return HGKS_OK;
 }
 
+// device upload and work allocation of a built host mesh
+static hgks_status finish_load(hgks_ctx* ctx);
+
 hgks_status hgks_load_mesh(hgks_ctx* ctx, int64_t n_nodes, const double* xyz, int64_t n_tets,
                            const int32_t* tet2node, int64_t n_bfaces, const int32_t* bface2node,
                            const int32_t* bface_tag) {
@@ -486,19 +494,43 @@ hgks_status hgks_load_mesh(hgks_ctx* ctx, int64_t n_nodes, const double* xyz, in
   }
   int rc = build_host_mesh(ctx->H, n_nodes, xyz, n_tets, tet2node, n_bfaces, bface2node, bface_tag, ctx->err);
   if (rc != 0) return rc == -3 ? HGKS_EMESH : HGKS_EINVAL;
+  return finish_load(ctx);
+}
+
+hgks_status hgks_load_hex_mesh(hgks_ctx* ctx, int64_t n_nodes, const double* xyz, int64_t n_hex,
+                               const int32_t* hex2node, int64_t n_bfaces, const int32_t* bface2node,
+                               const int32_t* bface_tag) {
+  if (!ctx) return HGKS_EINVAL;
+  if (ctx->mesh) {
+    ctx->err = "mesh already loaded";
+    return HGKS_EINVAL;
+  }
+  if ((n_bfaces > 0 && (!bface2node || !bface_tag)) || n_bfaces < 0) {
+    ctx->err = "invalid boundary arrays";
+    return HGKS_EINVAL;
+  }
+  int rc = build_host_hex_mesh(ctx->H, n_nodes, xyz, n_hex, hex2node, n_bfaces, bface2node, bface_tag, ctx->err);
+  if (rc != 0) return rc == -3 ? HGKS_EMESH : HGKS_EINVAL;
+  return finish_load(ctx);
+}
+
+static hgks_status finish_load(hgks_ctx* ctx) {
   const HostMesh& H = ctx->H;
   DevMesh<double>& M = ctx->M;
   M.N = H.N;
   M.F = H.F;
   M.Nb = H.Nb;
   M.NX = H.N + H.Nb;
+  M.nf = H.nf;
+  M.ng = H.ng;
+  M.nbig = H.nbig;
   TRY(upload(ctx, H.fL, M.fL));
   TRY(upload(ctx, H.fR, M.fR));
   TRY(upload(ctx, H.cface, M.cface));
   TRY(upload(ctx, H.gowner, M.gowner));
   TRY(upload(ctx, H.gface, M.gface));
   if (ctx->o.scheme == HGKS_HWENO) {
-    TRY(upload(ctx, H.nb4, M.nb4));
+    TRY(upload(ctx, H.nbf, M.nbf));
   } else if (ctx->o.scheme == HGKS_WENO) {
     TRY(upload(ctx, H.stn, M.stn));
     TRY(upload(ctx, H.sstn, M.sstn));

@@ -14,6 +14,9 @@ struct DevMesh {
   int F;    // faces; fR >= N marks a boundary face
   int Nb;   // boundary faces = ghost cells
   int NX;   // N + Nb, leading dimension of extended state arrays
+  int nf;   // faces per cell: 4 tetrahedra, 6 hexahedra
+  int ng;   // Gauss points per face: 3 triangles, 4 quadrilaterals
+  int nbig; // slots of the non-compact stencil (16 tetrahedra; the mesh's largest for hexahedra)
   const T* vol;        // [N]
   const T* h;          // [N]   |Omega|^(1/3)
   const T* hdt;        // [N]   3|Omega| / max face area
@@ -23,21 +26,23 @@ struct DevMesh {
   const int* fkind;    // [F]   boundary kind, -1 interior
   const T* fn;         // [3][F] unit normal L -> R
   const T* fS;         // [F]
-  const T* fxiL;       // [9][F] (gp*3+dir) scaled offsets (x_g - c_L)/h_L
-  const T* fxiR;       // [9][F]
-  const int* cface;    // [4][N] signed face ids: f+1 if the cell is L, -(f+1) if R
+  const T* fxiL;       // [3 ng][F] (gp*3+dir) scaled offsets (x_g - c_L)/h_L
+  const T* fxiR;       // [3 ng][F]
+  const T* fw;         // [ng][F] Gauss weights of quadrilateral faces (null for tetrahedra)
+  const int* cface;    // [nf][N] signed face ids: f+1 if the cell is L, -(f+1) if R
   const int* gowner;   // [Nb]
   const int* gface;    // [Nb]
   // non-compact WENO
-  const int* stn;      // [16][N] big stencil (extended ids), padded with the cell itself
-  const T* opA;        // [144][N] P0 operator, row k*16+j
-  const int* sstn;     // [24][N] sub-stencil members (extended ids), padded with the cell
-  const T* opB;        // [72][N] P_m operators, row (s*3+t)*6+r
+  const int* stn;      // [nbig][N] big stencil (extended ids), padded with the cell itself
+  const T* opA;        // [9 nbig][N] P0 operator, row k*nbig+j
+  const int* sstn;     // [24][N] sub-stencil members (extended ids), padded with the cell:
+                       // 4 x 6 (tetrahedra) or 8 x 3 (hexahedra)
+  const T* opB;        // [72][N] P_m operators, row (s*3+t)*6+r (tetrahedra), (s*3+t)*3+r (hexahedra)
   const uint8_t* smask;// [N]  bit s set = sub-stencil s usable
   // compact HWENO
-  const int* nb4;      // [4][N] face neighbours (extended ids)
-  const T* opH;        // [171][N] P0 operator: rows k*19+j, j<4 averages, j>=4 gradients
-  const T* hsub;       // [24][N] per sub s: wi, wm, dx, dy, dz, 1/|d|^2
+  const int* nbf;      // [nf][N] face neighbours (extended ids)
+  const T* opH;        // [9 (4 nf + 3)][N] P0 operator: rows k*(4nf+3)+j, j<nf averages, then gradients
+  const T* hsub;       // [6 nf][N] per sub s: wi, wm, dx, dy, dz, 1/|d|^2
   // LU-SGS
   const int* ccol;     // [N]  colour of the cell
   const int* cord;     // [N]  cell ids sorted by colour

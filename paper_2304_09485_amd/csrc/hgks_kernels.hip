@@ -205,7 +205,7 @@ __global__ void __launch_bounds__(256) k_recon_hweno(DevMesh<T> M, const T* __re
   const int N = M.N, NX = M.NX;
   int nb[4];
 #pragma unroll
-  for (int k = 0; k < 4; ++k) nb[k] = M.nb4[k * N + i];
+  for (int k = 0; k < 4; ++k) nb[k] = M.nbf[k * N + i];
   const T h = M.h[i];
   // the 19 data of the compact stencil for all 5 variables: 4 neighbour
   // differences, own gradient, the 4 neighbours' gradients
@@ -250,6 +250,125 @@ __global__ void __launch_bounds__(256) k_recon_hweno(DevMesh<T> M, const T* __re
       coef[(size_t)((9 + s * 3 + 0) * 5 + v) * N + i] = h * (g0 + lam * d0);
       coef[(size_t)((9 + s * 3 + 1) * 5 + v) * N + i] = h * (g1 + lam * d1);
       coef[(size_t)((9 + s * 3 + 2) * 5 + v) * N + i] = h * (g2 + lam * d2);
+    }
+  }
+}
+
+// Hexahedral reconstruction: the non-compact stencil has up to 36 cells and
+// the compact one 27 data per variable, too many to hold per lane for all 5
+// variables, so the data are streamed member by member and each operator
+// entry is applied to the 5 variables as it is read (45 accumulators).
+template <typename T>
+__global__ void __launch_bounds__(256) k_recon_weno_hex(DevMesh<T> M, const T* __restrict__ Qx,
+                                                        T* __restrict__ coef) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= M.N) return;
+  const int N = M.N, NX = M.NX, nb = M.nbig;
+  T q0[5];
+#pragma unroll
+  for (int v = 0; v < 5; ++v) q0[v] = Qx[(size_t)v * NX + i];
+  T acc[9][5];
+#pragma unroll
+  for (int k = 0; k < 9; ++k)
+#pragma unroll
+    for (int v = 0; v < 5; ++v) acc[k][v] = T(0);
+  for (int j = 0; j < nb; ++j) {
+    const int c = M.stn[(size_t)j * N + i];
+    T d[5];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) d[v] = Qx[(size_t)v * NX + c] - q0[v];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+      const T o = M.opA[(size_t)(k * nb + j) * N + i];
+#pragma unroll
+      for (int v = 0; v < 5; ++v) acc[k][v] += o * d[v];
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < 9; ++k)
+#pragma unroll
+    for (int v = 0; v < 5; ++v) coef[(size_t)(k * 5 + v) * N + i] = acc[k][v];
+  // the eight sub-stencils {i, i_1 or i_6, two consecutive lateral neighbours}
+  for (int sb = 0; sb < 8; ++sb) {
+    T ds[3][5];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+      const int c = M.sstn[(size_t)(sb * 3 + r) * N + i];
+#pragma unroll
+      for (int v = 0; v < 5; ++v) ds[r][v] = Qx[(size_t)v * NX + c] - q0[v];
+    }
+#pragma unroll
+    for (int t = 0; t < 3; ++t) {
+      T a5[5] = {T(0), T(0), T(0), T(0), T(0)};
+#pragma unroll
+      for (int r = 0; r < 3; ++r) {
+        const T o = M.opB[(size_t)((sb * 3 + t) * 3 + r) * N + i];
+#pragma unroll
+        for (int v = 0; v < 5; ++v) a5[v] += o * ds[r][v];
+      }
+#pragma unroll
+      for (int v = 0; v < 5; ++v) coef[(size_t)((9 + sb * 3 + t) * 5 + v) * N + i] = a5[v];
+    }
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_recon_hweno_hex(DevMesh<T> M, const T* __restrict__ Qx,
+                                                         const T* __restrict__ Gx, T* __restrict__ coef) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= M.N) return;
+  const int N = M.N, NX = M.NX;
+  constexpr int NR = 27;  // 6 neighbour differences, own gradient, 6 neighbour gradients
+  int nb[6];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) nb[k] = M.nbf[k * N + i];
+  const T h = M.h[i];
+  T q0[5];
+#pragma unroll
+  for (int v = 0; v < 5; ++v) q0[v] = Qx[(size_t)v * NX + i];
+  T acc[9][5];
+#pragma unroll
+  for (int k = 0; k < 9; ++k)
+#pragma unroll
+    for (int v = 0; v < 5; ++v) acc[k][v] = T(0);
+  for (int j = 0; j < NR; ++j) {
+    T x[5];
+    if (j < 6) {
+#pragma unroll
+      for (int v = 0; v < 5; ++v) x[v] = Qx[(size_t)v * NX + nb[j]] - q0[v];
+    } else {
+      const int m = (j - 6) / 3, d = (j - 6) % 3;  // m = 0: the cell itself, else neighbour m - 1
+      const int c = m == 0 ? i : nb[m - 1];
+#pragma unroll
+      for (int v = 0; v < 5; ++v) x[v] = Gx[(size_t)(v * 3 + d) * NX + c];
+    }
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+      const T o = M.opH[(size_t)(k * NR + j) * N + i];
+#pragma unroll
+      for (int v = 0; v < 5; ++v) acc[k][v] += o * x[v];
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < 9; ++k)
+#pragma unroll
+    for (int v = 0; v < 5; ++v) coef[(size_t)(k * 5 + v) * N + i] = acc[k][v];
+  // P_m on {i, i_m}: the constrained minimiser has a closed form
+  for (int sb = 0; sb < 6; ++sb) {
+    const T wi = M.hsub[(size_t)(sb * 6 + 0) * N + i], wm = M.hsub[(size_t)(sb * 6 + 1) * N + i];
+    const T d0 = M.hsub[(size_t)(sb * 6 + 2) * N + i], d1 = M.hsub[(size_t)(sb * 6 + 3) * N + i];
+    const T d2 = M.hsub[(size_t)(sb * 6 + 4) * N + i], id2 = M.hsub[(size_t)(sb * 6 + 5) * N + i];
+    const int c = nb[sb];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+      const T g0 = wi * Gx[(size_t)(v * 3 + 0) * NX + i] + wm * Gx[(size_t)(v * 3 + 0) * NX + c];
+      const T g1 = wi * Gx[(size_t)(v * 3 + 1) * NX + i] + wm * Gx[(size_t)(v * 3 + 1) * NX + c];
+      const T g2 = wi * Gx[(size_t)(v * 3 + 2) * NX + i] + wm * Gx[(size_t)(v * 3 + 2) * NX + c];
+      const T dq = Qx[(size_t)v * NX + c] - q0[v];
+      const T lam = (dq - (d0 * g0 + d1 * g1 + d2 * g2)) * id2;
+      coef[(size_t)((9 + sb * 3 + 0) * 5 + v) * N + i] = h * (g0 + lam * d0);
+      coef[(size_t)((9 + sb * 3 + 1) * 5 + v) * N + i] = h * (g1 + lam * d1);
+      coef[(size_t)((9 + sb * 3 + 2) * 5 + v) * N + i] = h * (g2 + lam * d2);
     }
   }
 }
@@ -303,20 +422,23 @@ __device__ void boundary_right(int kind, const T Wl[5], const T dWl[3][5], const
     for (int k = 0; k < 5; ++k) dWr[d][k] = T(0);
 }
 
-// one lane per Gauss point: 21 faces per 64-lane block, the three Gauss-point
-// fluxes of a face are summed through LDS by the face's first lane
-constexpr int FLUX_FPB = 21;
+// one lane per Gauss point: 64 / NG faces per 64-lane block (21 triangles or
+// 16 quadrilaterals), the Gauss-point fluxes of a face are summed through LDS
+// by the face's first lane
+template <int NG>
+constexpr int flux_fpb() { return 64 / NG; }
 
-template <typename T, bool QG>
+template <typename T, bool QG, int NG>
 __global__ void __launch_bounds__(64) k_flux(DevMesh<T> M, Params P, const T* __restrict__ sv,
                                              const T* __restrict__ dt, T* __restrict__ ff,
                                              T* __restrict__ fq) {
+  constexpr int FPB = flux_fpb<NG>();
   __shared__ T red[QG ? 10 : 5][64];
   const int F = M.F, N = M.N;
   const int lane = threadIdx.x;
-  const int f = xcd_block() * FLUX_FPB + lane / 3;  // contiguous face ranges per XCD
-  const int gp = lane % 3;
-  const bool active = lane < 3 * FLUX_FPB && f < F;
+  const int f = xcd_block() * FPB + lane / NG;  // contiguous face ranges per XCD
+  const int gp = lane % NG;
+  const bool active = lane < NG * FPB && f < F;
   T Fg[5] = {0, 0, 0, 0, 0}, Qg[5] = {0, 0, 0, 0, 0};
   if (active) {
     int L = M.fL[f], R = M.fR[f];
@@ -364,12 +486,28 @@ __global__ void __launch_bounds__(64) k_flux(DevMesh<T> M, Params P, const T* __
     for (int v = 0; v < 5; ++v) red[5 + v][lane] = Qg[v];
   __syncthreads();
   if (!active || gp != 0) return;
-  // quadrature with weights 1/3
+  // quadrature: weights 1/3 on a triangle, the stored weights on a quadrilateral
   T Fs[5], Qs[5];
+  if (NG == 3) {
 #pragma unroll
-  for (int v = 0; v < 5; ++v) {
-    Fs[v] = (red[v][lane] / T(3) + red[v][lane + 1] / T(3)) + red[v][lane + 2] / T(3);
-    if (QG) Qs[v] = (red[5 + v][lane] / T(3) + red[5 + v][lane + 1] / T(3)) + red[5 + v][lane + 2] / T(3);
+    for (int v = 0; v < 5; ++v) {
+      Fs[v] = (red[v][lane] / T(3) + red[v][lane + 1] / T(3)) + red[v][lane + 2] / T(3);
+      if (QG) Qs[v] = (red[5 + v][lane] / T(3) + red[5 + v][lane + 1] / T(3)) + red[5 + v][lane + 2] / T(3);
+    }
+  } else {
+    T w[NG];
+#pragma unroll
+    for (int g2 = 0; g2 < NG; ++g2) w[g2] = M.fw[(size_t)g2 * F + f];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+      Fs[v] = T(0);
+      Qs[v] = T(0);
+#pragma unroll
+      for (int g2 = 0; g2 < NG; ++g2) {
+        Fs[v] += w[g2] * red[v][lane + g2];
+        if (QG) Qs[v] += w[g2] * red[5 + v][lane + g2];
+      }
+    }
   }
   T n[3] = {M.fn[f], M.fn[F + f], M.fn[2 * F + f]}, t1[3], t2[3];
   face_frame(n[0], n[1], n[2], t1, t2);
@@ -441,7 +579,7 @@ __global__ void __launch_bounds__(256) k_flux_kfvs(DevMesh<T> M, Params P, const
 //   MODE 1: Av = (|Omega|/dt) v - (L(Q + sigma v) - b) / sigma     (Eq. (frechet))
 //   MODE 2: R = L(Q) and the gradient update of Eq. (derivative)
 // ---------------------------------------------------------------------------
-template <typename T, typename TO, int MODE>
+template <typename T, typename TO, int MODE, int NF>
 __global__ void __launch_bounds__(256) k_gather(DevMesh<T> M, const T* __restrict__ ff,
                                                 const T* __restrict__ fq, TO* __restrict__ out,
                                                 const TO* __restrict__ vin, const TO* __restrict__ bin,
@@ -455,7 +593,7 @@ __global__ void __launch_bounds__(256) k_gather(DevMesh<T> M, const T* __restric
   if (MODE == 2)
     for (int k = 0; k < 15; ++k) gq[k] = T(0);
 #pragma unroll
-  for (int p = 0; p < 4; ++p) {
+  for (int p = 0; p < NF; ++p) {
     int cf = M.cface[p * N + i];
     int f = (cf > 0 ? cf : -cf) - 1;
     T s = cf > 0 ? T(1) : T(-1);
@@ -532,14 +670,14 @@ __global__ void __launch_bounds__(256) k_lambda(DevMesh<T> M, Params P, const T*
   lam[f] = fabs(un) + sqrt(g * p / rho);
 }
 
-template <typename T>
+template <typename T, int NF>
 __global__ void __launch_bounds__(256) k_diag(DevMesh<T> M, const T* __restrict__ lam, const T* __restrict__ dt,
                                               T* __restrict__ D) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= M.N) return;
   T s = M.vol[i] / dt[i];
 #pragma unroll
-  for (int p = 0; p < 4; ++p) {
+  for (int p = 0; p < NF; ++p) {
     int cf = M.cface[p * M.N + i];
     int f = (cf > 0 ? cf : -cf) - 1;
     s += T(0.5) * lam[f] * M.fS[f];
@@ -567,7 +705,7 @@ __device__ __forceinline__ void euler_jn(T g, const T q[5], const T n[3], const 
 // A x with the approximate matrix of Eq. (deri-matrix): D_i x_i plus the
 // off-diagonal blocks 1/2 S_f (J_n(Q_j) - |lambda_f|) x_j of the cell's
 // interior faces (boundary off-diagonal blocks dropped)
-template <typename T>
+template <typename T, int NF>
 __global__ void __launch_bounds__(256) k_amatvec(DevMesh<T> M, Params P, const T* __restrict__ Qx,
                                                  const T* __restrict__ lam, const T* __restrict__ D,
                                                  const double* __restrict__ x, double* __restrict__ out) {
@@ -578,7 +716,7 @@ __global__ void __launch_bounds__(256) k_amatvec(DevMesh<T> M, Params P, const T
   T acc[5];
   for (int v = 0; v < 5; ++v) acc[v] = D[i] * T(x[(size_t)v * N + i]);
 #pragma unroll
-  for (int p = 0; p < 4; ++p) {
+  for (int p = 0; p < NF; ++p) {
     int cf = M.cface[p * N + i];
     int f = (cf > 0 ? cf : -cf) - 1;
     int L = M.fL[f], R = M.fR[f];
@@ -605,7 +743,7 @@ __global__ void __launch_bounds__(256) k_amatvec(DevMesh<T> M, Params P, const T
 //   forward  x_i = (b_i - sum) / D_i        ((D + L) y = R, b = R)
 //   backward x_i = b_i - sum / D_i          ((D + U) dQ = D y, b = y)
 // Cells of one colour share no face, so the class updates in parallel.
-template <typename T, bool FWD>
+template <typename T, bool FWD, int NF>
 __global__ void __launch_bounds__(256) k_lusgs(DevMesh<T> M, Params P, const T* __restrict__ Qx,
                                                const T* __restrict__ lam, const T* __restrict__ D, int c0, int nc,
                                                int col, const double* __restrict__ b, double* x) {
@@ -616,7 +754,7 @@ __global__ void __launch_bounds__(256) k_lusgs(DevMesh<T> M, Params P, const T* 
   const T g = T(P.gamma);
   T off[5] = {0, 0, 0, 0, 0};
 #pragma unroll
-  for (int p = 0; p < 4; ++p) {
+  for (int p = 0; p < NF; ++p) {
     int cf = M.cface[p * N + i];
     int f = (cf > 0 ? cf : -cf) - 1;
     int L = M.fL[f], R = M.fR[f];
@@ -642,7 +780,7 @@ __global__ void __launch_bounds__(256) k_lusgs(DevMesh<T> M, Params P, const T* 
   }
 }
 
-template <typename T>
+template <typename T, int NF>
 __global__ void __launch_bounds__(256) k_jacobi(DevMesh<T> M, Params P, const T* __restrict__ Qx,
                                                 const T* __restrict__ lam, const T* __restrict__ D,
                                                 const double* __restrict__ r, const double* __restrict__ xo,
@@ -655,7 +793,7 @@ __global__ void __launch_bounds__(256) k_jacobi(DevMesh<T> M, Params P, const T*
   if (xo) {
     T g = T(P.gamma);
 #pragma unroll
-    for (int p = 0; p < 4; ++p) {
+    for (int p = 0; p < NF; ++p) {
       int cf = M.cface[p * N + i];
       int f = (cf > 0 ? cf : -cf) - 1;
       int L = M.fL[f], R = M.fR[f];
@@ -819,24 +957,45 @@ void launch_ghost(const DevMesh<T>& M, const Params& P, T* Qx, T* Gx, hipStream_
 }
 template <typename T>
 void launch_recon(const DevMesh<T>& M, const Params& P, const T* Qx, const T* Gx, T* coef, hipStream_t s) {
-  if (P.scheme == 1)
-    hipLaunchKernelGGL(k_recon_hweno<T>, dim3(nblk(M.N, 256)), dim3(256), 0, s, M, Qx, Gx, coef);
-  else
-    hipLaunchKernelGGL(k_recon_weno<T>, dim3(nblk(M.N, 256)), dim3(256), 0, s, M, Qx, coef);
+  const dim3 g(nblk(M.N, 256)), b(256);
+  if (M.nf == 6) {
+    if (P.scheme == 1)
+      hipLaunchKernelGGL(k_recon_hweno_hex<T>, g, b, 0, s, M, Qx, Gx, coef);
+    else
+      hipLaunchKernelGGL(k_recon_weno_hex<T>, g, b, 0, s, M, Qx, coef);
+  } else if (P.scheme == 1) {
+    hipLaunchKernelGGL(k_recon_hweno<T>, g, b, 0, s, M, Qx, Gx, coef);
+  } else {
+    hipLaunchKernelGGL(k_recon_weno<T>, g, b, 0, s, M, Qx, coef);
+  }
 }
 template <typename T>
 void launch_side(const DevMesh<T>& M, const Params& P, const T* Qx, const T* coef, T* sv, int* nfall,
                  hipStream_t s) {
-  hipLaunchKernelGGL(k_side<T>, dim3(nblk(2 * (size_t)M.F, SIDE_SPB)), dim3(SIDE_THREADS), 0, s, M, P, Qx, coef, sv, nfall);
+  const dim3 g(nblk(2 * (size_t)M.F, SIDE_SPB)), b(SIDE_THREADS);
+  if (M.nf == 4)
+    hipLaunchKernelGGL((k_side<T, 4, 3>), g, b, 0, s, M, P, Qx, coef, sv, nfall);
+  else if (P.scheme == 1)
+    hipLaunchKernelGGL((k_side<T, 6, 4>), g, b, 0, s, M, P, Qx, coef, sv, nfall);
+  else
+    hipLaunchKernelGGL((k_side<T, 8, 4>), g, b, 0, s, M, P, Qx, coef, sv, nfall);
 }
 template <typename T>
 void launch_flux(const DevMesh<T>& M, const Params& P, const T* sv, const T* dt, T* ff, T* fq, bool qg,
                  hipStream_t s) {
-  dim3 grid(nblk(M.F, FLUX_FPB));
-  if (qg)
-    hipLaunchKernelGGL((k_flux<T, true>), grid, dim3(64), 0, s, M, P, sv, dt, ff, fq);
-  else
-    hipLaunchKernelGGL((k_flux<T, false>), grid, dim3(64), 0, s, M, P, sv, dt, ff, fq);
+  if (M.ng == 3) {
+    dim3 grid(nblk(M.F, flux_fpb<3>()));
+    if (qg)
+      hipLaunchKernelGGL((k_flux<T, true, 3>), grid, dim3(64), 0, s, M, P, sv, dt, ff, fq);
+    else
+      hipLaunchKernelGGL((k_flux<T, false, 3>), grid, dim3(64), 0, s, M, P, sv, dt, ff, fq);
+  } else {
+    dim3 grid(nblk(M.F, flux_fpb<4>()));
+    if (qg)
+      hipLaunchKernelGGL((k_flux<T, true, 4>), grid, dim3(64), 0, s, M, P, sv, dt, ff, fq);
+    else
+      hipLaunchKernelGGL((k_flux<T, false, 4>), grid, dim3(64), 0, s, M, P, sv, dt, ff, fq);
+  }
 }
 template <typename T>
 void launch_flux_kfvs(const DevMesh<T>& M, const Params& P, const T* Qx, T* ff, hipStream_t s) {
@@ -846,12 +1005,21 @@ template <typename T, typename TO>
 void launch_gather(const DevMesh<T>& M, int mode, const T* ff, const T* fq, TO* out, const TO* v, const TO* b,
                    const T* dt, const double* sigma, TO* gout, hipStream_t s) {
   dim3 g(nblk(M.N, 256)), bl(256);
-  if (mode == 0)
-    hipLaunchKernelGGL((k_gather<T, TO, 0>), g, bl, 0, s, M, ff, fq, out, v, b, dt, sigma, gout);
-  else if (mode == 1)
-    hipLaunchKernelGGL((k_gather<T, TO, 1>), g, bl, 0, s, M, ff, fq, out, v, b, dt, sigma, gout);
-  else
-    hipLaunchKernelGGL((k_gather<T, TO, 2>), g, bl, 0, s, M, ff, fq, out, v, b, dt, sigma, gout);
+  if (M.nf == 4) {
+    if (mode == 0)
+      hipLaunchKernelGGL((k_gather<T, TO, 0, 4>), g, bl, 0, s, M, ff, fq, out, v, b, dt, sigma, gout);
+    else if (mode == 1)
+      hipLaunchKernelGGL((k_gather<T, TO, 1, 4>), g, bl, 0, s, M, ff, fq, out, v, b, dt, sigma, gout);
+    else
+      hipLaunchKernelGGL((k_gather<T, TO, 2, 4>), g, bl, 0, s, M, ff, fq, out, v, b, dt, sigma, gout);
+  } else {
+    if (mode == 0)
+      hipLaunchKernelGGL((k_gather<T, TO, 0, 6>), g, bl, 0, s, M, ff, fq, out, v, b, dt, sigma, gout);
+    else if (mode == 1)
+      hipLaunchKernelGGL((k_gather<T, TO, 1, 6>), g, bl, 0, s, M, ff, fq, out, v, b, dt, sigma, gout);
+    else
+      hipLaunchKernelGGL((k_gather<T, TO, 2, 6>), g, bl, 0, s, M, ff, fq, out, v, b, dt, sigma, gout);
+  }
 }
 template <typename T>
 void launch_dt(const DevMesh<T>& M, const Params& P, double cfl, const T* Qx, T* dt, hipStream_t s) {
@@ -861,17 +1029,26 @@ template <typename T>
 void launch_lambda_diag(const DevMesh<T>& M, const Params& P, const T* Qx, const T* dt, T* lam, T* D,
                         hipStream_t s) {
   hipLaunchKernelGGL(k_lambda<T>, dim3(nblk(M.F, 256)), dim3(256), 0, s, M, P, Qx, lam);
-  hipLaunchKernelGGL(k_diag<T>, dim3(nblk(M.N, 256)), dim3(256), 0, s, M, lam, dt, D);
+  if (M.nf == 4)
+    hipLaunchKernelGGL((k_diag<T, 4>), dim3(nblk(M.N, 256)), dim3(256), 0, s, M, lam, dt, D);
+  else
+    hipLaunchKernelGGL((k_diag<T, 6>), dim3(nblk(M.N, 256)), dim3(256), 0, s, M, lam, dt, D);
 }
 template <typename T>
 void launch_jacobi(const DevMesh<T>& M, const Params& P, const T* Qx, const T* lam, const T* D, const double* r,
                    const double* xo, double* xn, hipStream_t s) {
-  hipLaunchKernelGGL(k_jacobi<T>, dim3(nblk(M.N, 256)), dim3(256), 0, s, M, P, Qx, lam, D, r, xo, xn);
+  if (M.nf == 4)
+    hipLaunchKernelGGL((k_jacobi<T, 4>), dim3(nblk(M.N, 256)), dim3(256), 0, s, M, P, Qx, lam, D, r, xo, xn);
+  else
+    hipLaunchKernelGGL((k_jacobi<T, 6>), dim3(nblk(M.N, 256)), dim3(256), 0, s, M, P, Qx, lam, D, r, xo, xn);
 }
 template <typename T>
 void launch_amatvec(const DevMesh<T>& M, const Params& P, const T* Qx, const T* lam, const T* D, const double* x,
                     double* out, hipStream_t s) {
-  hipLaunchKernelGGL(k_amatvec<T>, dim3(nblk(M.N, 256)), dim3(256), 0, s, M, P, Qx, lam, D, x, out);
+  if (M.nf == 4)
+    hipLaunchKernelGGL((k_amatvec<T, 4>), dim3(nblk(M.N, 256)), dim3(256), 0, s, M, P, Qx, lam, D, x, out);
+  else
+    hipLaunchKernelGGL((k_amatvec<T, 6>), dim3(nblk(M.N, 256)), dim3(256), 0, s, M, P, Qx, lam, D, x, out);
 }
 template <typename T>
 void launch_lusgs(const DevMesh<T>& M, const Params& P, const T* Qx, const T* lam, const T* D,
@@ -879,14 +1056,20 @@ void launch_lusgs(const DevMesh<T>& M, const Params& P, const T* Qx, const T* la
   const int nc = (int)start.size() - 1;
   for (int c = 0; c < nc; ++c) {
     int cnt = start[c + 1] - start[c];
-    if (cnt)
-      hipLaunchKernelGGL((k_lusgs<T, true>), dim3(nblk(cnt, 256)), dim3(256), 0, s, M, P, Qx, lam, D, start[c], cnt,
-                         c, r, y);
+    if (cnt && M.nf == 4)
+      hipLaunchKernelGGL((k_lusgs<T, true, 4>), dim3(nblk(cnt, 256)), dim3(256), 0, s, M, P, Qx, lam, D, start[c],
+                         cnt, c, r, y);
+    else if (cnt)
+      hipLaunchKernelGGL((k_lusgs<T, true, 6>), dim3(nblk(cnt, 256)), dim3(256), 0, s, M, P, Qx, lam, D, start[c],
+                         cnt, c, r, y);
   }
   for (int c = nc - 1; c >= 0; --c) {
     int cnt = start[c + 1] - start[c];
-    if (cnt)
-      hipLaunchKernelGGL((k_lusgs<T, false>), dim3(nblk(cnt, 256)), dim3(256), 0, s, M, P, Qx, lam, D, start[c],
+    if (cnt && M.nf == 4)
+      hipLaunchKernelGGL((k_lusgs<T, false, 4>), dim3(nblk(cnt, 256)), dim3(256), 0, s, M, P, Qx, lam, D, start[c],
+                         cnt, c, (const double*)y, x);
+    else if (cnt)
+      hipLaunchKernelGGL((k_lusgs<T, false, 6>), dim3(nblk(cnt, 256)), dim3(256), 0, s, M, P, Qx, lam, D, start[c],
                          cnt, c, (const double*)y, x);
   }
 }

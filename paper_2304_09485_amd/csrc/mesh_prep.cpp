@@ -129,83 +129,48 @@ bool invert(std::vector<double> A, int n, std::vector<double>& Ainv) {
   return true;
 }
 
-struct FaceRec {
-  std::array<int, 3> key;
-  int tet, p;
+struct FaceTmp {
+  int L, pL, R, pR, tag;
 };
 
-}  // namespace
+// geometry of one face as seen from its left cell
+struct FaceGeo {
+  Vec3 n{0, 0, 0}, xc{0, 0, 0};
+  double S = 0.0;
+  Vec3 gp[4];
+  double gw[4] = {0, 0, 0, 0};
+};
 
-int build_host_mesh(HostMesh& H, int64_t n_nodes, const double* xyz, int64_t n_tets, const int32_t* tet2node,
-                    int64_t n_bf, const int32_t* bf, const int32_t* btag, std::string& err) {
-  if (n_nodes <= 0 || n_tets <= 0 || !xyz || !tet2node || n_tets > (int64_t)1 << 30) {
-    err = "invalid mesh arguments";
-    return -1;
-  }
-  const int N = (int)n_tets;
-  H = HostMesh();
-  H.N = N;
-  auto P = [&](int node) { return Vec3{xyz[3 * (size_t)node], xyz[3 * (size_t)node + 1], xyz[3 * (size_t)node + 2]}; };
-  std::vector<Vec3> cen(N);
-  std::vector<Sym3> m2(N);
-  H.vol.resize(N);
-  for (int i = 0; i < N; ++i) {
-    Vec3 v[4];
-    for (int k = 0; k < 4; ++k) {
-      int nd = tet2node[4 * (size_t)i + k];
-      if (nd < 0 || nd >= n_nodes) {
-        err = "tet node id out of range at tet " + std::to_string(i);
-        return -3;
-      }
-      v[k] = P(nd);
-    }
-    double d6 = dotp(crossp(v[1] - v[0], v[2] - v[0]), v[3] - v[0]);
-    if (!(d6 > 0.0) || !std::isfinite(d6)) {
-      err = "inverted or degenerate tet " + std::to_string(i);
-      return -3;
-    }
-    H.vol[i] = d6 / 6.0;
-    Vec3 c = 0.25 * (((v[0] + v[1]) + v[2]) + v[3]);
-    cen[i] = c;
-    Sym3 s;
-    std::memset(&s, 0, sizeof(s));
-    for (int k = 0; k < 4; ++k) {
-      Vec3 d = v[k] - c;
-      for (int a = 0; a < 3; ++a)
-        for (int b = 0; b < 3; ++b) s.a[a][b] += comp(d, a) * comp(d, b) / 20.0;
-    }
-    m2[i] = s;
-  }
-  // ---- faces: sort the 4N tet faces by their node triple and pair them ----
-  std::vector<FaceRec> recs((size_t)4 * N);
+// Pair the nf faces of every cell by their sorted node keys (NV nodes per
+// face); unpaired faces must appear in the tagged boundary list.
+template <int NV, typename NodesOf>
+int pair_faces(int N, int nf, NodesOf nodes_of, int64_t n_bf, const int32_t* bf, const int32_t* btag,
+               std::vector<FaceTmp>& ft, int& nb_found, std::string& err) {
+  struct Rec {
+    std::array<int, NV> key;
+    int cell, p;
+  };
+  std::vector<Rec> recs((size_t)nf * N);
   for (int i = 0; i < N; ++i)
-    for (int p = 0; p < 4; ++p) {
-      std::array<int, 3> k;
-      int q = 0;
-      for (int c = 0; c < 4; ++c)
-        if (c != p) k[q++] = tet2node[4 * (size_t)i + c];
+    for (int p = 0; p < nf; ++p) {
+      std::array<int, NV> k = nodes_of(i, p);
       std::sort(k.begin(), k.end());
-      recs[(size_t)4 * i + p] = {k, i, p};
+      recs[(size_t)nf * i + p] = {k, i, p};
     }
-  std::sort(recs.begin(), recs.end(), [](const FaceRec& a, const FaceRec& b) {
-    return a.key != b.key ? a.key < b.key : (a.tet != b.tet ? a.tet < b.tet : a.p < b.p);
+  std::sort(recs.begin(), recs.end(), [](const Rec& a, const Rec& b) {
+    return a.key != b.key ? a.key < b.key : (a.cell != b.cell ? a.cell < b.cell : a.p < b.p);
   });
-  std::vector<std::array<int, 3>> bkeys((size_t)n_bf);
-  std::vector<std::pair<std::array<int, 3>, int>> bsorted((size_t)n_bf);
+  std::vector<std::pair<std::array<int, NV>, int>> bsorted((size_t)n_bf);
   for (int64_t k = 0; k < n_bf; ++k) {
-    std::array<int, 3> key{bf[3 * k], bf[3 * k + 1], bf[3 * k + 2]};
+    std::array<int, NV> key;
+    for (int q = 0; q < NV; ++q) key[q] = bf[NV * k + q];
     std::sort(key.begin(), key.end());
     bsorted[k] = {key, btag[k]};
   }
   std::sort(bsorted.begin(), bsorted.end());
-  H.cface.assign((size_t)4 * N, 0);
-  std::vector<std::array<int, 4>> nbr(N, std::array<int, 4>{-1, -1, -1, -1});
-  struct FaceTmp {
-    int L, pL, R, pR, tag;
-  };
-  std::vector<FaceTmp> ft;
-  ft.reserve((size_t)2 * N + n_bf);
-  size_t nb_found = 0;
+  ft.clear();
+  ft.reserve((size_t)nf * N / 2 + n_bf);
+  nb_found = 0;
   for (size_t k = 0; k < recs.size();) {
     size_t e = k + 1;
     while (e < recs.size() && recs[e].key == recs[k].key) ++e;
@@ -213,9 +178,9 @@ int build_host_mesh(HostMesh& H, int64_t n_nodes, const double* xyz, int64_t n_t
       err = "non-manifold face";
       return -3;
     }
-    FaceTmp f{recs[k].tet, recs[k].p, -1, -1, -1};
+    FaceTmp f{recs[k].cell, recs[k].p, -1, -1, -1};
     if (e - k == 2) {
-      f.R = recs[k + 1].tet;
+      f.R = recs[k + 1].cell;
       f.pR = recs[k + 1].p;
     } else {
       auto it = std::lower_bound(bsorted.begin(), bsorted.end(), std::make_pair(recs[k].key, INT32_MIN));
@@ -237,6 +202,15 @@ int build_host_mesh(HostMesh& H, int64_t n_nodes, const double* xyz, int64_t n_t
     err = "boundary face list does not match the mesh boundary";
     return -3;
   }
+  return 0;
+}
+
+// Faces, ghosts, length scales, stencils and reconstruction operators, common
+// to both cell shapes (H.nf, H.ng, H.nbig, H.nsw, H.msw set by the caller).
+template <typename Geo>
+int finish_mesh(HostMesh& H, const std::vector<Vec3>& cen, const std::vector<Sym3>& m2, std::vector<FaceTmp>& ft,
+                int nb_found, Geo face_geo, std::string& err) {
+  const int N = H.N, nf = H.nf, ng = H.ng;
   // face order: by left cell, then its local face.  Consecutive faces then
   // share or neighbour their left cell, so a wavefront's loads of left-cell
   // data touch few cache lines (the cell order is the caller's).
@@ -244,17 +218,20 @@ int build_host_mesh(HostMesh& H, int64_t n_nodes, const double* xyz, int64_t n_t
             [](const FaceTmp& a, const FaceTmp& b) { return a.L != b.L ? a.L < b.L : a.pL < b.pL; });
   const int F = (int)ft.size();
   H.F = F;
-  H.Nb = (int)nb_found;
+  H.Nb = nb_found;
   const int NX = N + H.Nb;
   H.fL.resize(F);
   H.fR.resize(F);
   H.ftag.resize(F);
   H.fn.resize((size_t)3 * F);
   H.fS.resize(F);
-  H.fxiL.resize((size_t)9 * F);
-  H.fxiR.resize((size_t)9 * F);
+  H.fxiL.resize((size_t)3 * ng * F);
+  H.fxiR.resize((size_t)3 * ng * F);
+  if (ng == 4) H.fw.resize((size_t)4 * F);
   H.gowner.resize(H.Nb);
   H.gface.resize(H.Nb);
+  H.cface.assign((size_t)nf * N, 0);
+  std::vector<std::array<int, 6>> nbr(N, std::array<int, 6>{-1, -1, -1, -1, -1, -1});
   std::vector<Vec3> cx(NX);  // centroids incl. ghosts
   std::vector<Sym3> mx(NX);
   std::vector<double> hx(NX);
@@ -264,25 +241,27 @@ int build_host_mesh(HostMesh& H, int64_t n_nodes, const double* xyz, int64_t n_t
     hx[i] = std::cbrt(H.vol[i]);
   }
   std::vector<double> smax(N, 0.0);
-  std::vector<std::array<Vec3, 3>> gps(F);
+  std::vector<std::array<Vec3, 4>> gps(F);
   int g = 0;
   for (int f = 0; f < F; ++f) {
     const FaceTmp& t = ft[f];
-    Vec3 v[3];
-    int q = 0;
-    for (int c = 0; c < 4; ++c)
-      if (c != t.pL) v[q++] = P(tet2node[4 * (size_t)t.L + c]);
-    Vec3 nn = crossp(v[1] - v[0], v[2] - v[0]);
-    double len = std::sqrt(dotp(nn, nn));
-    if (!(len > 0.0)) {
+    FaceGeo G;
+    if (!face_geo(t, G)) {
       err = "degenerate face";
       return -3;
     }
-    double S = 0.5 * len;
-    Vec3 n = (1.0 / len) * nn;
-    Vec3 xc = (1.0 / 3.0) * ((v[0] + v[1]) + v[2]);
-    if (dotp(n, xc - cen[t.L]) < 0.0) n = -1.0 * n;
-    for (int k = 0; k < 3; ++k) gps[f][k] = (2.0 / 3.0) * v[k] + (1.0 / 6.0) * (v[(k + 1) % 3] + v[(k + 2) % 3]);
+    Vec3 n = G.n, xc = G.xc;
+    if (dotp(n, xc - cen[t.L]) < 0.0) {
+      if (ng == 4) {
+        err = "face normal does not point out of hexahedron " + std::to_string(t.L);
+        return -3;
+      }
+      n = -1.0 * n;
+    }
+    for (int k = 0; k < ng; ++k) gps[f][k] = G.gp[k];
+    if (ng == 4)
+      for (int k = 0; k < 4; ++k) H.fw[(size_t)k * F + f] = G.gw[k];
+    const double S = G.S;
     H.fL[f] = t.L;
     H.fn[f] = n.x;
     H.fn[F + f] = n.y;
@@ -330,7 +309,8 @@ int build_host_mesh(HostMesh& H, int64_t n_nodes, const double* xyz, int64_t n_t
   H.total_volume = 0.0;
   for (int i = 0; i < N; ++i) {
     H.h[i] = hx[i];
-    H.hdt[i] = 3.0 * H.vol[i] / smax[i];
+    // time-step length: the height of a tetrahedron, the width of a hexahedron
+    H.hdt[i] = (nf == 4 ? 3.0 : 1.0) * H.vol[i] / smax[i];
     double hh = hx[i] * hx[i];
     const double* s = &m2[i].a[0][0];
     double vals[6] = {s[0], s[4], s[8], s[1], s[2], s[5]};
@@ -342,22 +322,47 @@ int build_host_mesh(HostMesh& H, int64_t n_nodes, const double* xyz, int64_t n_t
   }
   for (int f = 0; f < F; ++f) {
     int L = H.fL[f], R = H.fR[f];
-    for (int k = 0; k < 3; ++k) {
+    for (int k = 0; k < ng; ++k) {
       Vec3 dl = (1.0 / hx[L]) * (gps[f][k] - cen[L]);
       for (int d = 0; d < 3; ++d) H.fxiL[(size_t)(k * 3 + d) * F + f] = comp(dl, d);
       Vec3 dr = R < N ? (1.0 / hx[R]) * (gps[f][k] - cen[R]) : Vec3{0, 0, 0};
       for (int d = 0; d < 3; ++d) H.fxiR[(size_t)(k * 3 + d) * F + f] = comp(dr, d);
     }
   }
-  // ---- stencils ----
-  H.stn.assign((size_t)16 * N, 0);
-  H.sstn.assign((size_t)24 * N, 0);
-  H.opA.assign((size_t)144 * N, 0.0);
-  H.opB.assign((size_t)72 * N, 0.0);
+  // ---- stencils: the largest non-compact stencil sets the hexahedral slot count ----
+  auto add = [](std::vector<int>& v, int e) {
+    for (int x : v)
+      if (x == e) return;
+    v.push_back(e);
+  };
+  auto big_of = [&](int i, std::vector<int>& big) {
+    big.clear();
+    for (int p = 0; p < nf; ++p) add(big, nbr[i][p]);
+    for (int p = 0; p < nf; ++p) {
+      int j = nbr[i][p];
+      if (j >= N) continue;
+      for (int q = 0; q < nf; ++q)
+        if (nbr[j][q] != i) add(big, nbr[j][q]);
+    }
+  };
+  if (nf == 6) {
+    int mx_big = 0;
+    std::vector<int> big;
+    for (int i = 0; i < N; ++i) {
+      big_of(i, big);
+      mx_big = std::max(mx_big, (int)big.size());
+    }
+    H.nbig = std::max(9, mx_big);
+  }
+  const int nbig = H.nbig, nsw = H.nsw, msw = H.msw, nhrow = nf + 3 * (nf + 1);
+  H.stn.assign((size_t)nbig * N, 0);
+  H.sstn.assign((size_t)nsw * msw * N, 0);
+  H.opA.assign((size_t)9 * nbig * N, 0.0);
+  H.opB.assign((size_t)nsw * 3 * msw * N, 0.0);
   H.smask.assign(N, 0);
-  H.nb4.assign((size_t)4 * N, 0);
-  H.opH.assign((size_t)171 * N, 0.0);
-  H.hsub.assign((size_t)24 * N, 0.0);
+  H.nbf.assign((size_t)nf * N, 0);
+  H.opH.assign((size_t)9 * nhrow * N, 0.0);
+  H.hsub.assign((size_t)6 * nf * N, 0.0);
   // basis means of cell e in the frame of cell i (9 values)
   auto row9 = [&](int i, int e, double* r) {
     double hi = hx[i];
@@ -372,29 +377,18 @@ int build_host_mesh(HostMesh& H, int64_t n_nodes, const double* xyz, int64_t n_t
   int64_t nfb = 0, nsd = 0;
 #pragma omp parallel for schedule(dynamic, 256) reduction(+ : nfb, nsd)
   for (int i = 0; i < N; ++i) {
-    auto add = [](std::vector<int>& v, int e) {
-      for (int x : v)
-        if (x == e) return;
-      v.push_back(e);
-    };
     std::vector<int> big;
-    big.reserve(17);
-    for (int p = 0; p < 4; ++p) add(big, nbr[i][p]);
-    for (int p = 0; p < 4; ++p) {
-      int j = nbr[i][p];
-      if (j >= N) continue;
-      for (int q = 0; q < 4; ++q)
-        if (nbr[j][q] != i) add(big, nbr[j][q]);
-    }
+    big.reserve(40);
+    big_of(i, big);
     int m = (int)big.size();
-    for (int r = 0; r < 16; ++r) H.stn[(size_t)r * N + i] = r < m ? big[r] : i;
+    for (int r = 0; r < nbig; ++r) H.stn[(size_t)r * N + i] = r < m ? big[r] : i;
     // P0 operator
     std::vector<double> A((size_t)m * 9), X((size_t)9 * m);
     for (int r = 0; r < m; ++r) row9(i, big[r], &A[(size_t)r * 9]);
     if (m >= 9 && gram_cond_ratio(A.data(), m, 9) > 1e-20) {
       pinv_mgs(A.data(), m, 9, X.data());
       for (int k = 0; k < 9; ++k)
-        for (int r = 0; r < m; ++r) H.opA[(size_t)(k * 16 + r) * N + i] = X[(size_t)k * m + r];
+        for (int r = 0; r < m; ++r) H.opA[(size_t)(k * nbig + r) * N + i] = X[(size_t)k * m + r];
     } else {
       // rank-deficient big stencil: linear least squares on it
       ++nfb;
@@ -403,21 +397,29 @@ int build_host_mesh(HostMesh& H, int64_t n_nodes, const double* xyz, int64_t n_t
         for (int k = 0; k < 3; ++k) A3[r * 3 + k] = A[r * 9 + k];
       pinv_mgs(A3.data(), m, 3, X3.data());
       for (int k = 0; k < 3; ++k)
-        for (int r = 0; r < m; ++r) H.opA[(size_t)(k * 16 + r) * N + i] = X3[(size_t)k * m + r];
+        for (int r = 0; r < m; ++r) H.opA[(size_t)(k * nbig + r) * N + i] = X3[(size_t)k * m + r];
     }
-    // sub-stencils S_i1..S_i4: faces {1,2,3},{1,2,4},{2,3,4},{3,1,4} plus the
-    // neighbours of i_1..i_4 respectively (1-based as in the paper)
-    const int first[4][3] = {{0, 1, 2}, {0, 1, 3}, {1, 2, 3}, {2, 0, 3}};
     uint8_t mask = 0;
-    for (int s = 0; s < 4; ++s) {
+    for (int s = 0; s < nsw; ++s) {
       std::vector<int> sub;
-      for (int k = 0; k < 3; ++k) add(sub, nbr[i][first[s][k]]);
-      int j = nbr[i][s];
-      if (j < N)
-        for (int q = 0; q < 4; ++q)
-          if (nbr[j][q] != i) add(sub, nbr[j][q]);
+      if (nf == 4) {
+        // sub-stencils S_i1..S_i4: faces {1,2,3},{1,2,4},{2,3,4},{3,1,4} plus
+        // the neighbours of i_1..i_4 respectively (1-based as in the paper)
+        const int first[4][3] = {{0, 1, 2}, {0, 1, 3}, {1, 2, 3}, {2, 0, 3}};
+        for (int k = 0; k < 3; ++k) add(sub, nbr[i][first[s][k]]);
+        int j = nbr[i][s];
+        if (j < N)
+          for (int q = 0; q < 4; ++q)
+            if (nbr[j][q] != i) add(sub, nbr[j][q]);
+      } else {
+        // hexahedron: F1 or F6 with two consecutive lateral faces F2..F5
+        const int lat[5] = {1, 2, 3, 4, 1};
+        add(sub, nbr[i][s < 4 ? 0 : 5]);
+        add(sub, nbr[i][lat[s % 4]]);
+        add(sub, nbr[i][lat[s % 4 + 1]]);
+      }
       int ms = (int)sub.size();
-      for (int r = 0; r < 6; ++r) H.sstn[(size_t)(s * 6 + r) * N + i] = r < ms ? sub[r] : i;
+      for (int r = 0; r < msw; ++r) H.sstn[(size_t)(s * msw + r) * N + i] = r < ms ? sub[r] : i;
       std::vector<double> As((size_t)ms * 3), Xs((size_t)3 * ms);
       for (int r = 0; r < ms; ++r) {
         double rr[9];
@@ -427,7 +429,8 @@ int build_host_mesh(HostMesh& H, int64_t n_nodes, const double* xyz, int64_t n_t
       if (ms >= 3 && gram_cond_ratio(As.data(), ms, 3) > 1e-20) {
         pinv_mgs(As.data(), ms, 3, Xs.data());
         for (int t = 0; t < 3; ++t)
-          for (int r = 0; r < ms; ++r) H.opB[(size_t)((s * 3 + t) * 6 + r) * N + i] = Xs[(size_t)t * ms + r];
+          for (int r = 0; r < ms; ++r)
+            H.opB[(size_t)((s * 3 + t) * msw + r) * N + i] = Xs[(size_t)t * ms + r];
         mask |= (uint8_t)(1u << s);
       } else {
         ++nsd;
@@ -435,14 +438,16 @@ int build_host_mesh(HostMesh& H, int64_t n_nodes, const double* xyz, int64_t n_t
     }
     H.smask[i] = mask;
     // ---- compact HWENO: constrained least squares (Sec. 3.3) ----
-    for (int k = 0; k < 4; ++k) H.nb4[(size_t)k * N + i] = nbr[i][k];
+    for (int k = 0; k < nf; ++k) H.nbf[(size_t)k * N + i] = nbr[i][k];
     {
-      const int nu = 9, ne = 4, nl = 15, nk = nu + ne;
-      double Ce[4][9], Al[15][9];
-      for (int r = 0; r < 4; ++r) row9(i, nbr[i][r], Ce[r]);
-      int mem[5] = {i, nbr[i][0], nbr[i][1], nbr[i][2], nbr[i][3]};
-      double hk[5];
-      for (int k = 0; k < 5; ++k) {
+      const int nu = 9, ne = nf, nl = 3 * (nf + 1), nk = nu + ne;
+      std::vector<double> Ce((size_t)ne * 9), Al((size_t)nl * 9);
+      for (int r = 0; r < ne; ++r) row9(i, nbr[i][r], &Ce[(size_t)r * 9]);
+      int mem[7];
+      mem[0] = i;
+      for (int k = 0; k < nf; ++k) mem[1 + k] = nbr[i][k];
+      double hk[7];
+      for (int k = 0; k <= nf; ++k) {
         int e = mem[k];
         hk[k] = hx[e];
         Vec3 d = (1.0 / hx[i]) * (cx[e] - cx[i]);
@@ -450,35 +455,36 @@ int build_host_mesh(HostMesh& H, int64_t n_nodes, const double* xyz, int64_t n_t
                              {0, 1, 0, 0, 2 * d.y, 0, d.x, 0, d.z},
                              {0, 0, 1, 0, 0, 2 * d.z, 0, d.x, d.y}};
         for (int a = 0; a < 3; ++a)
-          for (int q = 0; q < 9; ++q) Al[3 * k + a][q] = hk[k] * rows[a][q] / hx[i];
+          for (int q = 0; q < 9; ++q) Al[(size_t)(3 * k + a) * 9 + q] = hk[k] * rows[a][q] / hx[i];
       }
       std::vector<double> K((size_t)nk * nk, 0.0), Ki;
       for (int p = 0; p < nu; ++p) {
         for (int q = 0; q < nu; ++q) {
           double s = 0.0;
-          for (int r = 0; r < nl; ++r) s += Al[r][p] * Al[r][q];
+          for (int r = 0; r < nl; ++r) s += Al[(size_t)r * 9 + p] * Al[(size_t)r * 9 + q];
           K[p * nk + q] = 2.0 * s;
         }
         for (int r = 0; r < ne; ++r) {
-          K[p * nk + nu + r] = Ce[r][p];
-          K[(nu + r) * nk + p] = Ce[r][p];
+          K[p * nk + nu + r] = Ce[(size_t)r * 9 + p];
+          K[(nu + r) * nk + p] = Ce[(size_t)r * 9 + p];
         }
       }
       invert(K, nk, Ki);
-      // a = Ki[0:9, 0:9] 2 Al^T (h G) + Ki[0:9, 9:13] dQ
+      // a = Ki[0:9, 0:9] 2 Al^T (h G) + Ki[0:9, 9:9+nf] dQ; rows j < nf the
+      // neighbour differences, then the own and the neighbours' gradients
       for (int k = 0; k < 9; ++k) {
-        for (int j = 0; j < 4; ++j) H.opH[(size_t)(k * 19 + j) * N + i] = Ki[k * nk + nu + j];
-        for (int mk = 0; mk < 5; ++mk)
+        for (int j = 0; j < nf; ++j) H.opH[(size_t)(k * nhrow + j) * N + i] = Ki[k * nk + nu + j];
+        for (int mk = 0; mk <= nf; ++mk)
           for (int a = 0; a < 3; ++a) {
             int row = 3 * mk + a;
             double s = 0.0;
-            for (int q = 0; q < nu; ++q) s += Ki[k * nk + q] * 2.0 * Al[row][q];
+            for (int q = 0; q < nu; ++q) s += Ki[k * nk + q] * 2.0 * Al[(size_t)row * 9 + q];
             s *= hk[mk];
-            int j = mk == 0 ? 4 + a : 7 + 3 * (mk - 1) + a;
-            H.opH[(size_t)(k * 19 + j) * N + i] = s;
+            int j = nf + 3 * mk + a;
+            H.opH[(size_t)(k * nhrow + j) * N + i] = s;
           }
       }
-      for (int s = 0; s < 4; ++s) {
+      for (int s = 0; s < nf; ++s) {
         int e = nbr[i][s];
         double h2i = hx[i] * hx[i], h2m = hx[e] * hx[e];
         Vec3 d = cx[e] - cx[i];
@@ -492,14 +498,205 @@ int build_host_mesh(HostMesh& H, int64_t n_nodes, const double* xyz, int64_t n_t
   return 0;
 }
 
+}  // namespace
+
+int build_host_mesh(HostMesh& H, int64_t n_nodes, const double* xyz, int64_t n_tets, const int32_t* tet2node,
+                    int64_t n_bf, const int32_t* bf, const int32_t* btag, std::string& err) {
+  if (n_nodes <= 0 || n_tets <= 0 || !xyz || !tet2node || n_tets > (int64_t)1 << 30) {
+    err = "invalid mesh arguments";
+    return -1;
+  }
+  const int N = (int)n_tets;
+  H = HostMesh();
+  H.N = N;
+  auto P = [&](int node) { return Vec3{xyz[3 * (size_t)node], xyz[3 * (size_t)node + 1], xyz[3 * (size_t)node + 2]}; };
+  std::vector<Vec3> cen(N);
+  std::vector<Sym3> m2(N);
+  H.vol.resize(N);
+  for (int i = 0; i < N; ++i) {
+    Vec3 v[4];
+    for (int k = 0; k < 4; ++k) {
+      int nd = tet2node[4 * (size_t)i + k];
+      if (nd < 0 || nd >= n_nodes) {
+        err = "tet node id out of range at tet " + std::to_string(i);
+        return -3;
+      }
+      v[k] = P(nd);
+    }
+    double d6 = dotp(crossp(v[1] - v[0], v[2] - v[0]), v[3] - v[0]);
+    if (!(d6 > 0.0) || !std::isfinite(d6)) {
+      err = "inverted or degenerate tet " + std::to_string(i);
+      return -3;
+    }
+    H.vol[i] = d6 / 6.0;
+    Vec3 c = 0.25 * (((v[0] + v[1]) + v[2]) + v[3]);
+    cen[i] = c;
+    Sym3 s;
+    std::memset(&s, 0, sizeof(s));
+    for (int k = 0; k < 4; ++k) {
+      Vec3 d = v[k] - c;
+      for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) s.a[a][b] += comp(d, a) * comp(d, b) / 20.0;
+    }
+    m2[i] = s;
+  }
+  // local face p is the one opposite local vertex p
+  auto nodes_of = [&](int i, int p) {
+    std::array<int, 3> k;
+    int q = 0;
+    for (int c = 0; c < 4; ++c)
+      if (c != p) k[q++] = tet2node[4 * (size_t)i + c];
+    return k;
+  };
+  std::vector<FaceTmp> ft;
+  int nb_found = 0;
+  int rc = pair_faces<3>(N, 4, nodes_of, n_bf, bf, btag, ft, nb_found, err);
+  if (rc) return rc;
+  auto geo = [&](const FaceTmp& t, FaceGeo& G) {
+    std::array<int, 3> k = nodes_of(t.L, t.pL);
+    Vec3 v[3] = {P(k[0]), P(k[1]), P(k[2])};
+    Vec3 nn = crossp(v[1] - v[0], v[2] - v[0]);
+    double len = std::sqrt(dotp(nn, nn));
+    if (!(len > 0.0)) return false;
+    G.S = 0.5 * len;
+    G.n = (1.0 / len) * nn;
+    G.xc = (1.0 / 3.0) * ((v[0] + v[1]) + v[2]);
+    for (int q = 0; q < 3; ++q) G.gp[q] = (2.0 / 3.0) * v[q] + (1.0 / 6.0) * (v[(q + 1) % 3] + v[(q + 2) % 3]);
+    return true;
+  };
+  return finish_mesh(H, cen, m2, ft, nb_found, geo, err);
+}
+
+int build_host_hex_mesh(HostMesh& H, int64_t n_nodes, const double* xyz, int64_t n_hex, const int32_t* hex2node,
+                        int64_t n_bf, const int32_t* bf, const int32_t* btag, std::string& err) {
+  if (n_nodes <= 0 || n_hex <= 0 || !xyz || !hex2node || n_hex > (int64_t)1 << 29) {
+    err = "invalid mesh arguments";
+    return -1;
+  }
+  const int N = (int)n_hex;
+  H = HostMesh();
+  H.N = N;
+  H.nf = 6;
+  H.ng = 4;
+  H.nsw = 8;
+  H.msw = 3;
+  auto P = [&](int node) { return Vec3{xyz[3 * (size_t)node], xyz[3 * (size_t)node + 1], xyz[3 * (size_t)node + 2]}; };
+  // reference corners (r, s, t) of the node order; 3-point Gauss-Legendre
+  // per direction integrates volume, centroid and second moments of the
+  // trilinear cell exactly
+  static const int rc3[8][3] = {{0, 0, 0}, {1, 0, 0}, {1, 1, 0}, {0, 1, 0}, {0, 0, 1}, {1, 0, 1}, {1, 1, 1}, {0, 1, 1}};
+  const double gx[3] = {0.5 - 0.5 * std::sqrt(0.6), 0.5, 0.5 + 0.5 * std::sqrt(0.6)};
+  const double gw[3] = {5.0 / 18.0, 8.0 / 18.0, 5.0 / 18.0};
+  std::vector<Vec3> cen(N);
+  std::vector<Sym3> m2(N);
+  H.vol.resize(N);
+  for (int i = 0; i < N; ++i) {
+    Vec3 v[8];
+    for (int k = 0; k < 8; ++k) {
+      int nd = hex2node[8 * (size_t)i + k];
+      if (nd < 0 || nd >= n_nodes) {
+        err = "hex node id out of range at hex " + std::to_string(i);
+        return -3;
+      }
+      v[k] = P(nd);
+    }
+    auto map = [&](double r, double s, double t, Vec3& x) {
+      Vec3 dr{0, 0, 0}, ds{0, 0, 0}, dt{0, 0, 0};
+      x = Vec3{0, 0, 0};
+      for (int k = 0; k < 8; ++k) {
+        double fr = rc3[k][0] ? r : 1.0 - r, fs = rc3[k][1] ? s : 1.0 - s, ftt = rc3[k][2] ? t : 1.0 - t;
+        double sr = rc3[k][0] ? 1.0 : -1.0, ss = rc3[k][1] ? 1.0 : -1.0, st = rc3[k][2] ? 1.0 : -1.0;
+        x = x + (fr * fs * ftt) * v[k];
+        dr = dr + (sr * fs * ftt) * v[k];
+        ds = ds + (fr * ss * ftt) * v[k];
+        dt = dt + (fr * fs * st) * v[k];
+      }
+      return dotp(crossp(dr, ds), dt);
+    };
+    bool ok = true;
+    Vec3 x;
+    for (int k = 0; k < 8; ++k) {
+      double J = map(rc3[k][0], rc3[k][1], rc3[k][2], x);
+      if (!(J > 0.0) || !std::isfinite(J)) ok = false;
+    }
+    double vol = 0.0;
+    Vec3 c{0, 0, 0};
+    Vec3 px[27];
+    double pw[27];
+    int np = 0;
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b)
+        for (int d = 0; d < 3; ++d) {
+          double J = map(gx[a], gx[b], gx[d], x);
+          if (!(J > 0.0)) ok = false;
+          pw[np] = gw[a] * gw[b] * gw[d] * J;
+          px[np] = x;
+          vol += pw[np];
+          c = c + pw[np] * x;
+          ++np;
+        }
+    if (!ok) {
+      err = "inverted or degenerate hexahedron " + std::to_string(i);
+      return -3;
+    }
+    c = (1.0 / vol) * c;
+    Sym3 s;
+    std::memset(&s, 0, sizeof(s));
+    for (int q = 0; q < 27; ++q) {
+      Vec3 d = px[q] - c;
+      for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) s.a[a][b] += pw[q] * comp(d, a) * comp(d, b) / vol;
+    }
+    H.vol[i] = vol;
+    cen[i] = c;
+    m2[i] = s;
+  }
+  // local faces F1..F6 = 0..5: bottom, the four sides in order around, top;
+  // node lists counter-clockwise seen from outside
+  static const int fq[6][4] = {{0, 3, 2, 1}, {0, 1, 5, 4}, {1, 2, 6, 5}, {2, 3, 7, 6}, {3, 0, 4, 7}, {4, 5, 6, 7}};
+  auto nodes_of = [&](int i, int p) {
+    std::array<int, 4> k;
+    for (int q = 0; q < 4; ++q) k[q] = hex2node[8 * (size_t)i + fq[p][q]];
+    return k;
+  };
+  std::vector<FaceTmp> ft;
+  int nb_found = 0;
+  int rc = pair_faces<4>(N, 6, nodes_of, n_bf, bf, btag, ft, nb_found, err);
+  if (rc) return rc;
+  const double q0 = 0.5 - 0.5 / std::sqrt(3.0), q1 = 0.5 + 0.5 / std::sqrt(3.0);
+  const double quv[4][2] = {{q0, q0}, {q1, q0}, {q1, q1}, {q0, q1}};
+  // bilinear face: exact vector area (x_c - x_a) x (x_d - x_b) / 2; 2x2 Gauss
+  // points weighted by the normal component of the area element
+  auto geo = [&](const FaceTmp& t, FaceGeo& G) {
+    std::array<int, 4> k = nodes_of(t.L, t.pL);
+    Vec3 a = P(k[0]), b = P(k[1]), c = P(k[2]), d = P(k[3]);
+    Vec3 sv = 0.5 * crossp(c - a, d - b);
+    G.S = std::sqrt(dotp(sv, sv));
+    if (!(G.S > 0.0)) return false;
+    G.n = (1.0 / G.S) * sv;
+    Vec3 xc{0, 0, 0};
+    for (int q = 0; q < 4; ++q) {
+      double u = quv[q][0], w = quv[q][1];
+      G.gp[q] = (((1 - u) * (1 - w)) * a + (u * (1 - w)) * b) + ((u * w) * c + ((1 - u) * w) * d);
+      Vec3 xu = (1 - w) * (b - a) + w * (c - d);
+      Vec3 xw = (1 - u) * (d - a) + u * (c - b);
+      G.gw[q] = 0.25 * dotp(crossp(xu, xw), G.n) / G.S;
+      xc = xc + G.gw[q] * G.gp[q];
+    }
+    G.xc = xc;
+    return true;
+  };
+  return finish_mesh(H, cen, m2, ft, nb_found, geo, err);
+}
+
 int colour_cells(const HostMesh& H, std::vector<int>& col, std::vector<int>& order, std::vector<int>& start) {
   const int N = H.N;
   col.assign(N, -1);
   int ncol = 0;
   for (int i = 0; i < N; ++i) {
     unsigned taken = 0;  // bit c: a coloured neighbour has colour c
-    for (int k = 0; k < 4; ++k) {
-      int j = H.nb4[(size_t)k * N + i];
+    for (int k = 0; k < H.nf; ++k) {
+      int j = H.nbf[(size_t)k * N + i];
       if (j < N && col[j] >= 0) taken |= 1u << col[j];
     }
     int c = 0;

@@ -1,18 +1,20 @@
 // Face-side kernel: characteristic WENO of Sec. 3.4 Eq. (weno) with the
 // characteristic projection of Sec. 5, values and (n, t1, t2) derivatives at
-// the 3 Gauss points of the face, back-projected to conservative variables in
-// the face's local frame.  One lane per face side; the 5 characteristic
-// components are taken in turn (projection of the side cell's 21 coefficient
-// vectors, smoothness indicators, nonlinear weights, combined polynomial at
-// the Gauss points) and accumulated into the 60 outputs through R*.
-// sv layout [60][2F], row (g*4+d)*5+v, column side*F+f.
+// the NG Gauss points of the face (3 on a triangle, 4 on a quadrilateral),
+// back-projected to conservative variables in the face's local frame.  One
+// lane per face side; the 5 characteristic components are taken in turn
+// (projection of the side cell's 9 + 3 NSUB coefficient vectors, smoothness
+// indicators, nonlinear weights, combined polynomial at the Gauss points) and
+// accumulated into the 20 NG outputs through R*.  NSUB: 4 sub-stencils on a
+// tetrahedron, 8 (non-compact) or 6 (compact) on a hexahedron.
+// sv layout [20 NG][2F], row (g*4+d)*5+v, column side*F+f.
 // Included inside namespace hgks of hgks_kernels.hip.
 #pragma once
 
 constexpr int SIDE_SPB = 128;      // face sides per block
 constexpr int SIDE_THREADS = 128;  // threads per block
 
-template <typename T>
+template <typename T, int NSUB, int NG>
 __global__ void __launch_bounds__(128) k_side(DevMesh<T> M, Params P, const T* __restrict__ Qx,
                                               const T* __restrict__ coef, T* __restrict__ sv,
                                               int* __restrict__ nfall) {
@@ -56,16 +58,16 @@ __global__ void __launch_bounds__(128) k_side(DevMesh<T> M, Params P, const T* _
 #pragma unroll
   for (int k = 0; k < 6; ++k) m2[k] = M.m2s[k * N + i];
   const T* xis = side ? M.fxiR : M.fxiL;
-  T xi[3][3];
+  T xi[NG][3];
 #pragma unroll
-  for (int k = 0; k < 9; ++k) xi[k / 3][k % 3] = xis[(size_t)k * F + f];
-  unsigned mask = P.scheme == 1 ? 15u : (unsigned)M.smask[i];
+  for (int k = 0; k < 3 * NG; ++k) xi[k / 3][k % 3] = xis[(size_t)k * F + f];
+  unsigned mask = P.scheme == 1 ? (1u << NSUB) - 1u : (unsigned)M.smask[i];
   int nsub = __popc(mask);
   const T gl = T(P.gamma_lin);
   const T g0 = T(1) - gl * T(nsub);
-  T out[3][4][5];
+  T out[NG][4][5];
 #pragma unroll
-  for (int a = 0; a < 3; ++a)
+  for (int a = 0; a < NG; ++a)
 #pragma unroll
     for (int d = 0; d < 4; ++d)
 #pragma unroll
@@ -106,25 +108,25 @@ __global__ void __launch_bounds__(128) k_side(DevMesh<T> M, Params P, const T* _
 #pragma unroll
     for (int d = 0; d < 3; ++d) tc[1 + d] = l[1] * e[0][d] + l[2] * e[1][d] + l[3] * e[2][d];
     T q0 = tc[0] * qi[0] + tc[1] * qi[1] + tc[2] * qi[2] + tc[3] * qi[3] + tc[4] * qi[4];
-    T a[9], b[4][3];
+    T a[9], b[NSUB][3];
 #pragma unroll
     for (int k = 0; k < 9; ++k) {
       const T* cp = coef + (size_t)(k * 5) * N + i;
       a[k] = tc[0] * cp[0] + tc[1] * cp[N] + tc[2] * cp[2 * N] + tc[3] * cp[3 * N] + tc[4] * cp[4 * N];
     }
 #pragma unroll
-    for (int s = 0; s < 4; ++s)
+    for (int s = 0; s < NSUB; ++s)
 #pragma unroll
       for (int t = 0; t < 3; ++t) {
         const T* cp = coef + (size_t)((9 + s * 3 + t) * 5) * N + i;
         b[s][t] = tc[0] * cp[0] + tc[1] * cp[N] + tc[2] * cp[2 * N] + tc[3] * cp[3 * N] + tc[4] * cp[4 * N];
       }
     // weights
-    T w0, ws[4];
+    T w0, ws[NSUB];
     if (P.weights == 1) {
       w0 = g0;
 #pragma unroll
-      for (int s = 0; s < 4; ++s) ws[s] = (mask >> s) & 1u ? gl : T(0);
+      for (int s = 0; s < NSUB; ++s) ws[s] = (mask >> s) & 1u ? gl : T(0);
     } else {
       T s0[3] = {T(2) * a[3], a[6], a[7]}, s1[3] = {a[6], T(2) * a[4], a[8]}, s2[3] = {a[7], a[8], T(2) * a[5]};
       auto quad = [&](const T* sv3) {
@@ -133,9 +135,9 @@ __global__ void __launch_bounds__(128) k_side(DevMesh<T> M, Params P, const T* _
       };
       T beta0 = a[0] * a[0] + quad(s0) + a[1] * a[1] + quad(s1) + a[2] * a[2] + quad(s2) +
                 T(4) * (a[3] * a[3] + a[4] * a[4] + a[5] * a[5]) + a[6] * a[6] + a[7] * a[7] + a[8] * a[8];
-      T bm[4], tz = T(0);
+      T bm[NSUB], tz = T(0);
 #pragma unroll
-      for (int s = 0; s < 4; ++s) {
+      for (int s = 0; s < NSUB; ++s) {
         bm[s] = b[s][0] * b[s][0] + b[s][1] * b[s][1] + b[s][2] * b[s][2];
         if ((mask >> s) & 1u) tz += fabs(beta0 - bm[s]);
       }
@@ -144,14 +146,14 @@ __global__ void __launch_bounds__(128) k_side(DevMesh<T> M, Params P, const T* _
       T wt0 = g0 * (T(1) + tz / (beta0 + eps));
       T sum = wt0;
 #pragma unroll
-      for (int s = 0; s < 4; ++s) {
+      for (int s = 0; s < NSUB; ++s) {
         ws[s] = (mask >> s) & 1u ? gl * (T(1) + tz / (bm[s] + eps)) : T(0);
         sum += ws[s];
       }
       T isum = T(1) / sum;
       w0 = wt0 * isum;
 #pragma unroll
-      for (int s = 0; s < 4; ++s) ws[s] *= isum;
+      for (int s = 0; s < NSUB; ++s) ws[s] *= isum;
     }
     // combined polynomial: q0 + Lc . xi + Qc . (xi xi - m2)
     T r0 = w0 / g0;
@@ -159,7 +161,7 @@ __global__ void __launch_bounds__(128) k_side(DevMesh<T> M, Params P, const T* _
 #pragma unroll
     for (int t = 0; t < 3; ++t) Lc[t] = r0 * a[t];
 #pragma unroll
-    for (int s = 0; s < 4; ++s) {
+    for (int s = 0; s < NSUB; ++s) {
       if (!((mask >> s) & 1u)) continue;
       T cs = ws[s] - w0 * gl / g0;
 #pragma unroll
@@ -168,7 +170,7 @@ __global__ void __launch_bounds__(128) k_side(DevMesh<T> M, Params P, const T* _
 #pragma unroll
     for (int t = 0; t < 6; ++t) Qc[t] = r0 * a[3 + t];
 #pragma unroll
-    for (int gp = 0; gp < 3; ++gp) {
+    for (int gp = 0; gp < NG; ++gp) {
       T x0 = xi[gp][0], x1 = xi[gp][1], x2 = xi[gp][2];
       T val = q0 + Lc[0] * x0 + Lc[1] * x1 + Lc[2] * x2 + Qc[0] * (x0 * x0 - m2[0]) +
               Qc[1] * (x1 * x1 - m2[1]) + Qc[2] * (x2 * x2 - m2[2]) + Qc[3] * (x0 * x1 - m2[3]) +
@@ -186,11 +188,13 @@ __global__ void __launch_bounds__(128) k_side(DevMesh<T> M, Params P, const T* _
         for (int v = 0; v < 5; ++v) out[gp][d][v] += r[v] * dd[d];
     }
   }
-  bool ok = phys_ok(out[0][0], g) && phys_ok(out[1][0], g) && phys_ok(out[2][0], g);
+  bool ok = true;
+#pragma unroll
+  for (int gp = 0; gp < NG; ++gp) ok = ok && phys_ok(out[gp][0], g);
   if (!ok) {
     // positivity fallback: first order on this side
     atomicAdd(nfall, 1);
-    for (int gp = 0; gp < 3; ++gp) {
+    for (int gp = 0; gp < NG; ++gp) {
       for (int v = 0; v < 5; ++v) out[gp][0][v] = qil[v];
       for (int d = 1; d < 4; ++d)
         for (int v = 0; v < 5; ++v) out[gp][d][v] = T(0);
@@ -198,7 +202,7 @@ __global__ void __launch_bounds__(128) k_side(DevMesh<T> M, Params P, const T* _
   }
   const size_t ld = 2 * (size_t)F;
 #pragma unroll
-  for (int gp = 0; gp < 3; ++gp)
+  for (int gp = 0; gp < NG; ++gp)
 #pragma unroll
     for (int d = 0; d < 4; ++d)
 #pragma unroll

@@ -26,7 +26,7 @@ FARFIELD, SLIP_WALL, NOSLIP_ADIABATIC, SUP_IN, SUP_OUT = 0, 1, 2, 3, 4
 STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EMESH", -4: "ESTATE", -5: "ENOCONV", -6: "EDEVICE"}
 
 # exported symbols declared in include/hgks.h
-SYMBOLS = ["hgks_default_options", "hgks_create", "hgks_load_mesh", "hgks_set_freestream", "hgks_set_bc",
+SYMBOLS = ["hgks_default_options", "hgks_create", "hgks_load_mesh", "hgks_load_hex_mesh", "hgks_set_freestream", "hgks_set_bc",
            "hgks_set_state", "hgks_get_state", "hgks_residual", "hgks_time_step", "hgks_jv", "hgks_precond",
            "hgks_implicit_step", "hgks_solve_steady", "hgks_residual_dev", "hgks_jv_dev", "hgks_n_cells",
            "hgks_n_faces", "hgks_kernel_times", "hgks_last_error", "hgks_destroy", "hgks_estimate_bytes",
@@ -107,6 +107,7 @@ def load_library():
         "hgks_default_options": (None, [ctypes.POINTER(Options)]),
         "hgks_create": (i32, [ctypes.POINTER(Options), ctypes.POINTER(vp)]),
         "hgks_load_mesh": (i32, [vp, i64, vp, i64, vp, i64, vp, vp]),
+        "hgks_load_hex_mesh": (i32, [vp, i64, vp, i64, vp, i64, vp, vp]),
         "hgks_set_freestream": (i32, [vp, vp]),
         "hgks_set_bc": (i32, [vp, i32, i32, vp]),
         "hgks_set_state": (i32, [vp, vp, vp]),
@@ -171,9 +172,10 @@ class Solver:
         h = ctypes.c_void_p()
         self._check(self._L.hgks_create(ctypes.byref(self.opts), ctypes.byref(h)), None)
         self.h = h
-        xyz, tets, bf, bt = mesh.arrays()
-        self._check(self._L.hgks_load_mesh(self.h, len(xyz), _ptr(xyz), len(tets), _ptr(tets), len(bf), _ptr(bf),
-                                           _ptr(bt)))
+        xyz, cells, bf, bt = mesh.arrays()
+        # 8 nodes per cell: a hexahedral mesh
+        load = self._L.hgks_load_hex_mesh if cells.shape[1] == 8 else self._L.hgks_load_mesh
+        self._check(load(self.h, len(xyz), _ptr(xyz), len(cells), _ptr(cells), len(bf), _ptr(bf), _ptr(bt)))
         p = _f64(prim)
         self._check(self._L.hgks_set_freestream(self.h, _ptr(p)))
         for tag, kind in kinds.items():
