@@ -375,8 +375,8 @@ def _rate(kernel, ms, N, F, Nb, scheme):
 
 def variants_bench(hgks, mesh, Nb, lusgs_steps):
     """The first-order KFVS scheme on the supersonic sphere (Mach 3, the
-    retest of Sec. 5) and the LU-SGS comparison solver on the benchmark
-    shell: per-step time, the flux kernel's rate, and convergence."""
+    retest of Sec. 5), the LU-SGS comparison solver on the benchmark shell,
+    and the hexahedral shell: per-step time, kernel rates, convergence."""
     from inputs import freestream_prim, uniform_state
     out = {}
     kinds = {1: hgks.SLIP_WALL, 2: hgks.FARFIELD}
@@ -426,6 +426,35 @@ def variants_bench(hgks, mesh, Nb, lusgs_steps):
                          "drop": info.drop, "seconds": round(info.t_ms * 1e-3, 3),
                          "sweep_bytes": int(algorithmic_bytes("lusgs_sweep", N, F, Nb, 0))}
     print(f"# LU-SGS WENO: {out['lusgs_weno']}", file=sys.stderr, flush=True)
+    # hexahedra: the benchmark shell's cubed-sphere layout without the
+    # tetrahedral split (32 x 32 cells per patch, 22 layers, 135,168 hexes)
+    from inputs import shell_mesh
+    hm = shell_mesh(32, 22, grading=1.1, jitter=0.02, seed=2, hexahedra=True)
+    hexres = {"cells": hm.n_cells}
+    for name, sch in (("hweno", hgks.HWENO), ("weno", hgks.WENO)):
+        s = hgks.Solver(hm, kinds, prim, scheme=sch)
+        s.set_state(uniform_state(s.N, prim), np.zeros((15, s.N)) if sch == hgks.HWENO else None)
+        s.implicit_step()
+        s.kernel_times()
+        t0 = time.perf_counter()
+        ev = 0
+        for _ in range(5):
+            ev += s.implicit_step().n_resid_evals
+        el = time.perf_counter() - t0
+        kt = s.kernel_times()
+        s.close()
+        e = {"ms_per_step": round(1e3 * el / 5, 3), "Mcell_resid_per_s": round(hm.n_cells * ev / el / 1e6, 2),
+             "kernel_ms": {k: round(v, 4) for k, v in kt.items() if k != "evaluations"}}
+        if sch == hgks.WENO:
+            s = hgks.Solver(hm, kinds, prim, scheme=sch)
+            s.set_state(uniform_state(s.N, prim))
+            info = s.solve_steady(drop=1e-8, max_steps=400)
+            s.close()
+            e["time_to_1e-8"] = {"steps": info.steps, "drop": info.drop, "converged": bool(info.converged),
+                                 "seconds": round(info.t_ms * 1e-3, 3)}
+        hexres[name] = e
+    out["hex_shell_m05"] = hexres
+    print(f"# hexahedra: {hexres}", file=sys.stderr, flush=True)
     return out
 
 

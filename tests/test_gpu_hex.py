@@ -167,7 +167,12 @@ def test_hex_repeat_and_free_stream(oracle_lib, scheme):
     a steady state on a jittered hexahedral shell: every accumulator of the
     4-point quadrilateral path is cleared per evaluation."""
     from inputs import uniform_state
-    m, prim, o, s = _pair(oracle_lib, "hshell", scheme)
+    from paper_2304_09485_amd import hgks
+    mk, _, mach = HCASES["hshell"]
+    m, prim = mk(), freestream_prim(mach)
+    far = {1: C.FAR, 2: C.FAR}  # a uniform stream is steady only with far field on every boundary
+    o = oracle_lib.Oracle(m, far, prim)
+    s = hgks.Solver(m, far, prim, **SCHEMES[scheme])
     Q = perturbed_state(o.N, prim, amp=0.03, seed=9)
     U = uniform_state(o.N, prim)
     G = np.zeros((15, o.N)) if scheme == "hweno" else None
