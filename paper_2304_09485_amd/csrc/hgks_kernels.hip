@@ -972,13 +972,18 @@ void launch_recon(const DevMesh<T>& M, const Params& P, const T* Qx, const T* Gx
 template <typename T>
 void launch_side(const DevMesh<T>& M, const Params& P, const T* Qx, const T* coef, T* sv, int* nfall,
                  hipStream_t s) {
-  const dim3 g(nblk(2 * (size_t)M.F, SIDE_SPB)), b(SIDE_THREADS);
-  if (M.nf == 4)
-    hipLaunchKernelGGL((k_side<T, 4, 3>), g, b, 0, s, M, P, Qx, coef, sv, nfall);
-  else if (P.scheme == 1)
-    hipLaunchKernelGGL((k_side<T, 6, 4>), g, b, 0, s, M, P, Qx, coef, sv, nfall);
-  else
-    hipLaunchKernelGGL((k_side<T, 8, 4>), g, b, 0, s, M, P, Qx, coef, sv, nfall);
+  const dim3 b(SIDE_THREADS);
+  if (M.nf == 4) {
+    hipLaunchKernelGGL((k_side<T, 4, 3, 1>), dim3(nblk(2 * (size_t)M.F, SIDE_SPB)), b, 0, s, M, P, Qx, coef, sv,
+                       nfall);
+  } else {
+    // quadrilateral faces: one lane per Gauss point
+    const dim3 g(nblk(2 * (size_t)M.F * 4, SIDE_THREADS));
+    if (P.scheme == 1)
+      hipLaunchKernelGGL((k_side<T, 6, 4, 4>), g, b, 0, s, M, P, Qx, coef, sv, nfall);
+    else
+      hipLaunchKernelGGL((k_side<T, 8, 4, 4>), g, b, 0, s, M, P, Qx, coef, sv, nfall);
+  }
 }
 template <typename T>
 void launch_flux(const DevMesh<T>& M, const Params& P, const T* sv, const T* dt, T* ff, T* fq, bool qg,

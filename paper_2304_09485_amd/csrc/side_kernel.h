@@ -14,13 +14,20 @@
 constexpr int SIDE_SPB = 128;      // face sides per block
 constexpr int SIDE_THREADS = 128;  // threads per block
 
-template <typename T, int NSUB, int NG>
+// LPS lanes per side: 1 (each lane evaluates all NG Gauss points), or NG
+// (each lane one Gauss point; the projection and the weights are repeated
+// per lane, the live output shrinks from 20 NG to 20 values, and the
+// positivity decision is shared by the side's lanes through a ballot).
+template <typename T, int NSUB, int NG, int LPS>
 __global__ void __launch_bounds__(128) k_side(DevMesh<T> M, Params P, const T* __restrict__ Qx,
                                               const T* __restrict__ coef, T* __restrict__ sv,
                                               int* __restrict__ nfall) {
-  int sidx = xcd_block() * blockDim.x + threadIdx.x;  // contiguous side ranges per XCD
+  constexpr int NGL = NG / LPS;  // Gauss points of this lane
+  const int tid = xcd_block() * blockDim.x + threadIdx.x;  // contiguous side ranges per XCD
+  int sidx = tid / LPS;
+  const int g_lo = (tid % LPS) * NGL;
   const int F = M.F, N = M.N, NX = M.NX;
-  if (sidx >= 2 * F) return;
+  if (sidx >= 2 * F) return;  // whole lane groups (LPS divides the block)
   int side = sidx >= F;
   int f = side ? sidx - F : sidx;
   int L = M.fL[f], R = M.fR[f];
@@ -58,16 +65,16 @@ __global__ void __launch_bounds__(128) k_side(DevMesh<T> M, Params P, const T* _
 #pragma unroll
   for (int k = 0; k < 6; ++k) m2[k] = M.m2s[k * N + i];
   const T* xis = side ? M.fxiR : M.fxiL;
-  T xi[NG][3];
+  T xi[NGL][3];
 #pragma unroll
-  for (int k = 0; k < 3 * NG; ++k) xi[k / 3][k % 3] = xis[(size_t)k * F + f];
+  for (int k = 0; k < 3 * NGL; ++k) xi[k / 3][k % 3] = xis[(size_t)(3 * g_lo + k) * F + f];
   unsigned mask = P.scheme == 1 ? (1u << NSUB) - 1u : (unsigned)M.smask[i];
   int nsub = __popc(mask);
   const T gl = T(P.gamma_lin);
   const T g0 = T(1) - gl * T(nsub);
-  T out[NG][4][5];
+  T out[NGL][4][5];
 #pragma unroll
-  for (int a = 0; a < NG; ++a)
+  for (int a = 0; a < NGL; ++a)
 #pragma unroll
     for (int d = 0; d < 4; ++d)
 #pragma unroll
@@ -170,7 +177,7 @@ __global__ void __launch_bounds__(128) k_side(DevMesh<T> M, Params P, const T* _
 #pragma unroll
     for (int t = 0; t < 6; ++t) Qc[t] = r0 * a[3 + t];
 #pragma unroll
-    for (int gp = 0; gp < NG; ++gp) {
+    for (int gp = 0; gp < NGL; ++gp) {
       T x0 = xi[gp][0], x1 = xi[gp][1], x2 = xi[gp][2];
       T val = q0 + Lc[0] * x0 + Lc[1] * x1 + Lc[2] * x2 + Qc[0] * (x0 * x0 - m2[0]) +
               Qc[1] * (x1 * x1 - m2[1]) + Qc[2] * (x2 * x2 - m2[2]) + Qc[3] * (x0 * x1 - m2[3]) +
@@ -190,11 +197,17 @@ __global__ void __launch_bounds__(128) k_side(DevMesh<T> M, Params P, const T* _
   }
   bool ok = true;
 #pragma unroll
-  for (int gp = 0; gp < NG; ++gp) ok = ok && phys_ok(out[gp][0], g);
+  for (int gp = 0; gp < NGL; ++gp) ok = ok && phys_ok(out[gp][0], g);
+  if (LPS > 1) {
+    // the side falls back if any of its lanes' Gauss points is non-physical
+    const unsigned long long bad = __ballot(!ok);
+    const int lane0 = (int)(__lane_id() & ~(unsigned)(LPS - 1));
+    ok = ((bad >> lane0) & ((1ull << LPS) - 1ull)) == 0ull;
+  }
   if (!ok) {
     // positivity fallback: first order on this side
-    atomicAdd(nfall, 1);
-    for (int gp = 0; gp < NG; ++gp) {
+    if (g_lo == 0) atomicAdd(nfall, 1);
+    for (int gp = 0; gp < NGL; ++gp) {
       for (int v = 0; v < 5; ++v) out[gp][0][v] = qil[v];
       for (int d = 1; d < 4; ++d)
         for (int v = 0; v < 5; ++v) out[gp][d][v] = T(0);
@@ -202,10 +215,10 @@ __global__ void __launch_bounds__(128) k_side(DevMesh<T> M, Params P, const T* _
   }
   const size_t ld = 2 * (size_t)F;
 #pragma unroll
-  for (int gp = 0; gp < NG; ++gp)
+  for (int gp = 0; gp < NGL; ++gp)
 #pragma unroll
     for (int d = 0; d < 4; ++d)
 #pragma unroll
-      for (int v = 0; v < 5; ++v) sv[(size_t)((gp * 4 + d) * 5 + v) * ld + sidx] = out[gp][d][v];
+      for (int v = 0; v < 5; ++v) sv[(size_t)(((g_lo + gp) * 4 + d) * 5 + v) * ld + sidx] = out[gp][d][v];
 }
 
