@@ -293,6 +293,8 @@ class Server:
 
     def submit(self, mesh, kinds: dict, prim, drop=1e-8, max_steps=1000, **opts):
         xyz, tets, bf, bt = mesh.arrays()
+        if tets.shape[1] != 4:
+            raise ValueError("the server takes tetrahedral meshes")
         tags = np.array(sorted(kinds), dtype=np.int32)
         knd = np.array([kinds[t] for t in sorted(kinds)], dtype=np.int32)
         r = Request()

@@ -26,10 +26,11 @@ def _solver(hgks, scheme, mesh=None):
     return m, s
 
 
-@pytest.mark.parametrize("scheme", [0, 1])
-def test_resume_is_bitwise(tmp_path, scheme):
+@pytest.mark.parametrize("scheme,hexa", [(0, False), (1, False), (1, True)])
+def test_resume_is_bitwise(tmp_path, scheme, hexa):
     from paper_2304_09485_amd import hgks
-    m, a = _solver(hgks, scheme)
+    mesh = shell_mesh(4, 4, grading=1.3, jitter=0.05, seed=2, hexahedra=True) if hexa else None
+    m, a = _solver(hgks, scheme, mesh=mesh)
     for _ in range(2):
         a.implicit_step()
     path = os.fspath(tmp_path / "solve.ckpt")

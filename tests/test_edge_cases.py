@@ -101,3 +101,22 @@ def test_invalid_options(opts):
 def test_invalid_boundary_kind():
     from paper_2304_09485_amd import hgks
     _expect(-1, lambda: hgks.Solver(cube_mesh(1), {1: 7}, freestream_prim(0.3)))
+
+
+def test_hex_mesh_errors():
+    from paper_2304_09485_amd import hgks
+    from inputs import HexMesh
+    prim = freestream_prim(0.3)
+    far = {t: C.FAR for t in range(1, 7)}
+    good = cube_mesh(2, hexahedra=True)
+    # top and bottom rings swapped: a left-handed (inverted) hexahedron
+    inv = good.hexes.copy()
+    inv[0] = inv[0][[4, 5, 6, 7, 0, 1, 2, 3]]
+    _expect(-3, lambda: hgks.Solver(HexMesh(xyz=good.xyz, hexes=inv, bfaces=good.bfaces, btags=good.btags), far, prim))
+    # a boundary quadrilateral missing from the boundary list
+    miss = HexMesh(xyz=good.xyz, hexes=good.hexes, bfaces=good.bfaces[1:], btags=good.btags[1:])
+    _expect(-3, lambda: hgks.Solver(miss, far, prim))
+    # node id out of range
+    bad = good.hexes.copy()
+    bad[1, 3] = len(good.xyz) + 5
+    _expect(-3, lambda: hgks.Solver(HexMesh(xyz=good.xyz, hexes=bad, bfaces=good.bfaces, btags=good.btags), far, prim))

@@ -95,3 +95,32 @@ def test_small_budget_serialises_admission():
     # each request is admitted only after the previous one finished
     for a, b in zip(rs, rs[1:]):
         assert b.t_queue_ms >= a.t_total_ms - 5.0
+
+
+@pytest.mark.gpu
+def test_first_order_and_lusgs_requests_match_standalone_solves():
+    """Requests with the first-order KFVS scheme and with the LU-SGS solver,
+    served together, end in the state a standalone context reaches with the
+    same options from the free stream (the server runs the same library
+    calls; its free-stream state is formed in C++, so the start may differ
+    from numpy's in the last bit: 1e-9 relative)."""
+    hgks = _lib_or_skip()
+    from inputs import shell_mesh, uniform_state
+    m = shell_mesh(4, 4, grading=1.3, jitter=0.05, seed=2)
+    kinds = {1: hgks.SLIP_WALL, 2: hgks.FARFIELD}
+    cases = [(freestream_prim(0.5), dict(scheme=hgks.KFVS1, cfl=1.0)),
+             (freestream_prim(0.5), dict(scheme=hgks.WENO, solver=hgks.SOLVER_LUSGS, cfl=1.0))]
+    srv = hgks.Server(8 << 30, 2)
+    tickets = [srv.submit(m, kinds, prim, drop=1e-6, max_steps=20, **o) for prim, o in cases]
+    res = [srv.wait(t) for t in tickets]
+    states = [srv.state(t) for t in tickets]
+    srv.close()
+    for (prim, o), r, q in zip(cases, res, states):
+        s = hgks.Solver(m, kinds, prim, **o)
+        s.set_state(uniform_state(s.N, prim))
+        info = s.solve_steady(drop=1e-6, max_steps=20)
+        assert r.steps == info.steps
+        np.testing.assert_allclose(q, s.get_state(), rtol=1e-9, atol=1e-12)
+        s.close()
+    with pytest.raises(ValueError):
+        hgks.Server(1 << 30, 1).submit(cube_mesh(1, hexahedra=True), {1: 0}, freestream_prim(0.5))
