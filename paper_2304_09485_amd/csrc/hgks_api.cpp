@@ -329,11 +329,16 @@ hgks_status jv_device(hgks_ctx* ctx, const double* v, double sigma_fixed, double
 // Jacobi preconditioner: out = P^{-1} r (uses ctx->lam, ctx->D, W64.Qx = Q^n)
 void precond_device(hgks_ctx* ctx, const double* r, double* out, hipStream_t s) {
   int K = std::max(0, ctx->o.jacobi_sweeps);
-  // ping-pong between t1/t2 so that the last sweep lands in out
+  if (K == 0) {
+    launch_jacobi<double>(ctx->M, ctx->P, ctx->W64.Qx, ctx->lam, ctx->D, r, nullptr, out, s);
+    return;
+  }
+  // x0 = D^{-1} r is formed inside the first sweep; ping-pong between t1/t2
+  // so that the last sweep lands in out
   double* bufs[2] = {ctx->t1, ctx->t2};
-  double* cur = K == 0 ? out : bufs[0];
-  launch_jacobi<double>(ctx->M, ctx->P, ctx->W64.Qx, ctx->lam, ctx->D, r, nullptr, cur, s);
-  for (int k = 1; k <= K; ++k) {
+  double* cur = K == 1 ? out : bufs[1];
+  launch_jacobi<double>(ctx->M, ctx->P, ctx->W64.Qx, ctx->lam, ctx->D, r, r, cur, s);
+  for (int k = 2; k <= K; ++k) {
     double* nxt = k == K ? out : bufs[k % 2];
     launch_jacobi<double>(ctx->M, ctx->P, ctx->W64.Qx, ctx->lam, ctx->D, r, cur, nxt, s);
     cur = nxt;

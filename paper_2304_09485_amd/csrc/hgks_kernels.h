@@ -23,6 +23,8 @@ void launch_gather(const DevMesh<T>&, int mode, const T* ff, const T* fq, TO* ou
 template <typename T> void launch_dt(const DevMesh<T>&, const Params&, double cfl, const T* Qx, T* dt, hipStream_t);
 template <typename T>
 void launch_lambda_diag(const DevMesh<T>&, const Params&, const T* Qx, const T* dt, T* lam, T* D, hipStream_t);
+// xo == nullptr: xn = D^{-1} r; xo == r: one sweep from x0 = D^{-1} r (the first
+// two sweeps fused); otherwise one sweep from xo
 template <typename T>
 void launch_jacobi(const DevMesh<T>&, const Params&, const T* Qx, const T* lam, const T* D, const double* r,
                    const double* xo, double* xn, hipStream_t);

@@ -780,7 +780,9 @@ __global__ void __launch_bounds__(256) k_lusgs(DevMesh<T> M, Params P, const T* 
   }
 }
 
-template <typename T, int NF>
+// X0R: the sweep's input is x0 = D^{-1} r, formed on the fly from r and D
+// (the first two sweeps in one pass, with the same arithmetic as a stored x0)
+template <typename T, int NF, bool X0R>
 __global__ void __launch_bounds__(256) k_jacobi(DevMesh<T> M, Params P, const T* __restrict__ Qx,
                                                 const T* __restrict__ lam, const T* __restrict__ D,
                                                 const double* __restrict__ r, const double* __restrict__ xo,
@@ -790,7 +792,7 @@ __global__ void __launch_bounds__(256) k_jacobi(DevMesh<T> M, Params P, const T*
   if (i >= N) return;
   T acc[5];
   for (int v = 0; v < 5; ++v) acc[v] = T(r[(size_t)v * N + i]);
-  if (xo) {
+  if (xo || X0R) {
     T g = T(P.gamma);
 #pragma unroll
     for (int p = 0; p < NF; ++p) {
@@ -802,9 +804,10 @@ __global__ void __launch_bounds__(256) k_jacobi(DevMesh<T> M, Params P, const T*
       T s = cf > 0 ? T(1) : T(-1);
       T n[3] = {s * M.fn[f], s * M.fn[F + f], s * M.fn[2 * F + f]};
       T qj[5], xj[5], jx[5];
+      const T idj = X0R ? T(1) / D[jn] : T(0);
       for (int v = 0; v < 5; ++v) {
         qj[v] = Qx[(size_t)v * NX + jn];
-        xj[v] = T(xo[(size_t)v * N + jn]);
+        xj[v] = X0R ? T(double(T(r[(size_t)v * N + jn]) * idj)) : T(xo[(size_t)v * N + jn]);
       }
       euler_jn(g, qj, n, xj, jx);
       T hs = T(0.5) * M.fS[f], l = lam[f];
@@ -1042,10 +1045,18 @@ void launch_lambda_diag(const DevMesh<T>& M, const Params& P, const T* Qx, const
 template <typename T>
 void launch_jacobi(const DevMesh<T>& M, const Params& P, const T* Qx, const T* lam, const T* D, const double* r,
                    const double* xo, double* xn, hipStream_t s) {
-  if (M.nf == 4)
-    hipLaunchKernelGGL((k_jacobi<T, 4>), dim3(nblk(M.N, 256)), dim3(256), 0, s, M, P, Qx, lam, D, r, xo, xn);
-  else
-    hipLaunchKernelGGL((k_jacobi<T, 6>), dim3(nblk(M.N, 256)), dim3(256), 0, s, M, P, Qx, lam, D, r, xo, xn);
+  // xo == r: the input of the sweep is D^{-1} r (fused first sweep)
+  const dim3 g(nblk(M.N, 256)), b(256);
+  if (xo == r) {
+    if (M.nf == 4)
+      hipLaunchKernelGGL((k_jacobi<T, 4, true>), g, b, 0, s, M, P, Qx, lam, D, r, nullptr, xn);
+    else
+      hipLaunchKernelGGL((k_jacobi<T, 6, true>), g, b, 0, s, M, P, Qx, lam, D, r, nullptr, xn);
+  } else if (M.nf == 4) {
+    hipLaunchKernelGGL((k_jacobi<T, 4, false>), g, b, 0, s, M, P, Qx, lam, D, r, xo, xn);
+  } else {
+    hipLaunchKernelGGL((k_jacobi<T, 6, false>), g, b, 0, s, M, P, Qx, lam, D, r, xo, xn);
+  }
 }
 template <typename T>
 void launch_amatvec(const DevMesh<T>& M, const Params& P, const T* Qx, const T* lam, const T* D, const double* x,
