@@ -93,6 +93,8 @@ struct hgks_ctx {
   double* b32 = nullptr;    // [5][N] inner-precision base residual
   double* part = nullptr;   // reduction partials
   double* sc = nullptr;     // device scalars [64]
+  double* gm = nullptr;     // GMRES cycle: H, Givens rotations, g (device)
+  int* gst = nullptr;       // GMRES cycle state (device)
   int* flags = nullptr;     // [0] positivity fallbacks, [1] bad state
   std::vector<int> cstart;  // LU-SGS colour classes: offsets into M.cord
   double res0 = -1.0;
@@ -573,7 +575,9 @@ static hgks_status finish_load(hgks_ctx* ctx) {
   ctx->part = ctx->A.get<double>(REDUCE_PARTS);
   ctx->sc = ctx->A.get<double>(64 + MAXM + 1);
   ctx->flags = ctx->A.get<int>(4);
-  if (!ctx->Qc || !ctx->dtc || !ctx->b || !ctx->V || !ctx->flags || !ctx->sc || !ctx->part) {
+  ctx->gm = ctx->A.get<double>((size_t)(m + 1) * m + 3 * m + 1);
+  ctx->gst = ctx->A.get<int>(4);
+  if (!ctx->Qc || !ctx->dtc || !ctx->b || !ctx->V || !ctx->flags || !ctx->sc || !ctx->part || !ctx->gm || !ctx->gst) {
     ctx->err = "device allocation failed";
     return HGKS_ENOMEM;
   }
@@ -730,6 +734,13 @@ hgks_status hgks_implicit_step(hgks_ctx* ctx, hgks_step_info* info) {
   double beta0 = -1.0, last = 0.0;
   bool nonfinite = false;  // a NaN/Inf in the residual or the preconditioned residual
   double* hc = ctx->sc + 8;  // device column of H (m+1 entries)
+  double* yd = ctx->sc + 48;  // device solution of the cycle's least-squares problem (m entries)
+  double* last_d = ctx->sc + 6;
+  // The Arnoldi steps of a restart are queued without host round trips: the
+  // Givens rotations run on the device (k_gmres_column), and a finished cycle
+  // (happy breakdown, non-finite data) turns the remaining steps into no-ops
+  // for the update.  One synchronisation per restart reads beta, the final
+  // residual estimate and the cycle state.
   for (int rs = 0; rs < (lusgs ? 0 : ctx->o.restarts); ++rs) {
     if (rs == 0) {
       HIPCHK(hipMemcpyAsync(ctx->rv, ctx->b, n * sizeof(double), hipMemcpyDeviceToDevice, s));
@@ -743,20 +754,9 @@ hgks_status hgks_implicit_step(hgks_ctx* ctx, hgks_step_info* info) {
       launch_axpy_dev(ctx->yv, ctx->rv, n, ctx->sc + 4, -1.0, s);
     }
     precond_device(ctx, ctx->rv, ctx->wv, s);
-    launch_dot(ctx->wv, ctx->wv, n, ctx->part, ctx->sc + 5, true, s);
-    double beta = 0.0;
-    HIPCHK(hipMemcpyAsync(&beta, ctx->sc + 5, sizeof(double), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
-    if (beta0 < 0) beta0 = beta;
-    if (!std::isfinite(beta)) {
-      nonfinite = true;
-      break;
-    }
-    if (!(beta > 0.0)) break;
-    launch_scale_inv(ctx->wv, ctx->V, n, ctx->sc + 5, s);
-    std::vector<double> H((size_t)(m + 1) * m, 0.0), cs(m), sn(m), gv(m + 1, 0.0);
-    gv[0] = beta;
-    int jdone = 0;
+    launch_dot(ctx->wv, ctx->wv, n, ctx->part, ctx->sc + 5, true, s);  // beta
+    launch_gmres_start(ctx->sc + 5, ctx->gm, ctx->gst, m, s);
+    launch_scale_inv(ctx->wv, ctx->V, n, ctx->sc + 5, s, ctx->gst);
     for (int j = 0; j < m; ++j) {
       double* vj = ctx->V + (size_t)j * n;
       TRY(jv_device(ctx, vj, ctx->o.fd_sigma, ctx->yv, s));
@@ -770,44 +770,24 @@ hgks_status hgks_implicit_step(hgks_ctx* ctx, hgks_step_info* info) {
         const double* next = i < j ? ctx->V + (size_t)(i + 1) * n : nullptr;
         launch_axpy_dot(vi, ctx->wv, n, hc + i, next, ctx->part, hc + i + 1, s);
       }
-      std::vector<double> col(j + 2);
-      HIPCHK(hipMemcpyAsync(col.data(), hc, (j + 2) * sizeof(double), hipMemcpyDeviceToHost, s));
-      HIPCHK(hipStreamSynchronize(s));
-      for (int i = 0; i <= j + 1; ++i) {
-        if (!std::isfinite(col[i])) nonfinite = true;
-        H[(size_t)i * m + j] = col[i];
-      }
-      if (nonfinite) break;  // an FD product produced NaN/Inf: no update from this cycle
-      double hn = col[j + 1];
-      // Givens rotations (host, FP64)
-      for (int i = 0; i < j; ++i) {
-        double a = H[(size_t)i * m + j], c = H[(size_t)(i + 1) * m + j];
-        H[(size_t)i * m + j] = cs[i] * a + sn[i] * c;
-        H[(size_t)(i + 1) * m + j] = -sn[i] * a + cs[i] * c;
-      }
-      double a = H[(size_t)j * m + j], c = H[(size_t)(j + 1) * m + j];
-      double rr = std::hypot(a, c);
-      cs[j] = a / rr;
-      sn[j] = c / rr;
-      H[(size_t)j * m + j] = rr;
-      H[(size_t)(j + 1) * m + j] = 0.0;
-      gv[j + 1] = -sn[j] * gv[j];
-      gv[j] = cs[j] * gv[j];
-      jdone = j + 1;
-      if (hn <= 1e-14 * beta) break;  // happy breakdown
-      launch_scale_inv(ctx->wv, ctx->V + (size_t)(j + 1) * n, n, hc + j + 1, s);
+      launch_gmres_column(j, m, hc, ctx->sc + 5, ctx->gm, ctx->gst, s);
+      if (j + 1 < m) launch_scale_inv(ctx->wv, ctx->V + (size_t)(j + 1) * n, n, hc + j + 1, s, ctx->gst);
     }
-    if (nonfinite) break;
-    std::vector<double> y(jdone, 0.0);
-    for (int i = jdone - 1; i >= 0; --i) {
-      double sacc = gv[i];
-      for (int k = i + 1; k < jdone; ++k) sacc -= H[(size_t)i * m + k] * y[k];
-      y[i] = sacc / H[(size_t)i * m + i];
+    launch_gmres_solve(m, ctx->gm, ctx->gst, yd, last_d, s);
+    launch_combine(ctx->V, yd, m, n, ctx->dQ, ctx->dQ, s);
+    double sc_h[2];
+    int st_h[3];
+    HIPCHK(hipMemcpyAsync(sc_h, ctx->sc + 5, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(st_h, ctx->gst, sizeof(st_h), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    const double beta = sc_h[0];
+    if (beta0 < 0) beta0 = beta;
+    if (st_h[1]) {
+      nonfinite = true;  // an FD product or the residual produced NaN/Inf: no update from this cycle
+      break;
     }
-    HIPCHK(hipMemcpyAsync(ctx->sc + 48, y.data(), jdone * sizeof(double), hipMemcpyHostToDevice, s));
-    launch_combine(ctx->V, ctx->sc + 48, jdone, n, ctx->dQ, ctx->dQ, s);
-    last = std::fabs(gv[jdone]);
-    HIPCHK(hipStreamSynchronize(s));  // y is a host array
+    if (!(beta > 0.0)) break;
+    last = sc_h[1];
   }
   // res_abs was read back before the first restart's synchronisation
   if (nonfinite || !std::isfinite(res_abs)) {

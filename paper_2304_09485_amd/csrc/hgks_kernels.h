@@ -47,7 +47,12 @@ void launch_abssum(const double* x, size_t n, double* part, double* out, hipStre
 void launch_axpy_dot(const double* v, double* w, size_t n, const double* a, const double* z, double* part,
                      double* out, hipStream_t);
 void launch_axpy_dev(const double* x, double* y, size_t n, const double* a, double sgn, hipStream_t);
-void launch_scale_inv(const double* x, double* y, size_t n, const double* a, hipStream_t);
+void launch_scale_inv(const double* x, double* y, size_t n, const double* a, hipStream_t, const int* skip = nullptr);
+// GMRES cycle bookkeeping on the device: G [(m+1) m + 2 m + m + 1] holds H,
+// the Givens rotations and g; st [3]: finished, non-finite, columns done
+void launch_gmres_start(const double* beta, double* G, int* st, int m, hipStream_t);
+void launch_gmres_column(int j, int m, const double* hc, const double* beta, double* G, int* st, hipStream_t);
+void launch_gmres_solve(int m, const double* G, const int* st, double* y, double* out, hipStream_t);
 void launch_combine(const double* V, const double* c, int nv, size_t n, const double* x, double* y, hipStream_t);
 void launch_convert(const double* src, float* dst, size_t n, hipStream_t);
 void launch_sigma(const double* vv, const double* qq, double n, double eps, double fixed, double* sigma,

@@ -884,12 +884,84 @@ __global__ void __launch_bounds__(256) k_axpy_dev(const double* __restrict__ x, 
   y[k] += sgn * a[0] * x[k];
 }
 
-// y = x / a[0]
+// y = x / a[0]; nothing if skip[0] is set (a finished GMRES cycle)
 __global__ void __launch_bounds__(256) k_scale_inv(const double* __restrict__ x, double* __restrict__ y, size_t n,
-                                                   const double* __restrict__ a) {
+                                                   const double* __restrict__ a, const int* __restrict__ skip) {
   size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= n) return;
+  if (k >= n || (skip && skip[0])) return;
   y[k] = x[k] / a[0];
+}
+
+// ---------------------------------------------------------------------------
+// GMRES cycle bookkeeping on the device (one thread), so that the Arnoldi
+// steps of a restart are queued without a host round trip.  G holds the
+// Hessenberg matrix H [(m+1) x m], the Givens cosines and sines [m], the
+// rotated right-hand side g [m+1]; st: [0] cycle finished (happy breakdown,
+// zero or non-finite data), [1] non-finite data seen, [2] columns done.
+// ---------------------------------------------------------------------------
+__global__ void k_gmres_start(const double* __restrict__ beta, double* __restrict__ G, int* __restrict__ st,
+                              int m) {
+  double* g = G + (size_t)(m + 1) * m + 2 * m;
+  for (int k = 0; k <= m; ++k) g[k] = 0.0;
+  const double b = beta[0];
+  g[0] = b;
+  const bool fin = isfinite(b);
+  st[0] = (!fin || !(b > 0.0)) ? 1 : 0;
+  st[1] = fin ? 0 : 1;
+  st[2] = 0;
+}
+
+// column j of H from the modified Gram-Schmidt coefficients hc[0..j+1]:
+// apply the previous rotations, form rotation j, update g
+__global__ void k_gmres_column(int j, int m, const double* __restrict__ hc, const double* __restrict__ beta,
+                               double* __restrict__ G, int* __restrict__ st) {
+  if (st[0]) return;
+  double* H = G;
+  double* cs = G + (size_t)(m + 1) * m;
+  double* sn = cs + m;
+  double* g = sn + m;
+  for (int i = 0; i <= j + 1; ++i)
+    if (!isfinite(hc[i])) {
+      st[1] = 1;
+      st[0] = 1;
+      return;
+    }
+  for (int i = 0; i <= j + 1; ++i) H[(size_t)i * m + j] = hc[i];
+  const double hn = hc[j + 1];
+  for (int i = 0; i < j; ++i) {
+    double a = H[(size_t)i * m + j], c = H[(size_t)(i + 1) * m + j];
+    H[(size_t)i * m + j] = cs[i] * a + sn[i] * c;
+    H[(size_t)(i + 1) * m + j] = -sn[i] * a + cs[i] * c;
+  }
+  double a = H[(size_t)j * m + j], c = H[(size_t)(j + 1) * m + j];
+  double rr = hypot(a, c);
+  cs[j] = a / rr;
+  sn[j] = c / rr;
+  H[(size_t)j * m + j] = rr;
+  H[(size_t)(j + 1) * m + j] = 0.0;
+  g[j + 1] = -sn[j] * g[j];
+  g[j] = cs[j] * g[j];
+  st[2] = j + 1;
+  if (hn <= 1e-14 * beta[0]) st[0] = 1;  // happy breakdown
+}
+
+// back substitution of the triangular system (y = 0 beyond the columns done,
+// and for a cycle with non-finite data); out[0] = |g[columns done]|
+__global__ void k_gmres_solve(int m, const double* __restrict__ G, const int* __restrict__ st,
+                              double* __restrict__ y, double* __restrict__ out) {
+  const double* H = G;
+  const double* g = G + (size_t)(m + 1) * m + 2 * m;
+  const int jd = st[1] ? 0 : st[2];
+  for (int i = m - 1; i >= 0; --i) {
+    if (i >= jd) {
+      y[i] = 0.0;
+      continue;
+    }
+    double sacc = g[i];
+    for (int k = i + 1; k < jd; ++k) sacc -= H[(size_t)i * m + k] * y[k];
+    y[i] = sacc / H[(size_t)i * m + i];
+  }
+  out[0] = fabs(g[st[2]]);
 }
 
 // y = x + sum_j c[j] V[j]  (V: nv vectors of length n, c on the device)
@@ -1120,8 +1192,17 @@ void launch_axpy_dot(const double* v, double* w, size_t n, const double* a, cons
 void launch_axpy_dev(const double* x, double* y, size_t n, const double* a, double sgn, hipStream_t s) {
   hipLaunchKernelGGL(k_axpy_dev, dim3(nblk(n, 256)), dim3(256), 0, s, x, y, n, a, sgn);
 }
-void launch_scale_inv(const double* x, double* y, size_t n, const double* a, hipStream_t s) {
-  hipLaunchKernelGGL(k_scale_inv, dim3(nblk(n, 256)), dim3(256), 0, s, x, y, n, a);
+void launch_scale_inv(const double* x, double* y, size_t n, const double* a, hipStream_t s, const int* skip) {
+  hipLaunchKernelGGL(k_scale_inv, dim3(nblk(n, 256)), dim3(256), 0, s, x, y, n, a, skip);
+}
+void launch_gmres_start(const double* beta, double* G, int* st, int m, hipStream_t s) {
+  hipLaunchKernelGGL(k_gmres_start, dim3(1), dim3(1), 0, s, beta, G, st, m);
+}
+void launch_gmres_column(int j, int m, const double* hc, const double* beta, double* G, int* st, hipStream_t s) {
+  hipLaunchKernelGGL(k_gmres_column, dim3(1), dim3(1), 0, s, j, m, hc, beta, G, st);
+}
+void launch_gmres_solve(int m, const double* G, const int* st, double* y, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_gmres_solve, dim3(1), dim3(1), 0, s, m, G, st, y, out);
 }
 void launch_combine(const double* V, const double* c, int nv, size_t n, const double* x, double* y, hipStream_t s) {
   hipLaunchKernelGGL(k_combine, dim3(nblk(n, 256)), dim3(256), 0, s, V, c, nv, n, x, y);
