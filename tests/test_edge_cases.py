@@ -120,3 +120,26 @@ def test_hex_mesh_errors():
     bad = good.hexes.copy()
     bad[1, 3] = len(good.xyz) + 5
     _expect(-3, lambda: hgks.Solver(HexMesh(xyz=good.xyz, hexes=bad, bfaces=good.bfaces, btags=good.btags), far, prim))
+
+
+@pytest.mark.parametrize("n_tets", [1, 2])
+def test_gmres_breakdown_matches_oracle(oracle_lib, n_tets):
+    """5 or 10 unknowns and a Krylov dimension of 10: the Arnoldi process
+    exhausts the space (happy breakdown) inside the first cycle.  The step
+    with the approximate matrix (a linear solve) equals the oracle's, whose
+    loop stops at the breakdown, at 1e-10."""
+    from paper_2304_09485_amd import hgks
+    m = tiny_mesh(n_tets)
+    prim = freestream_prim(0.3)
+    kinds = {t: C.FAR for t in range(1, 7)}
+    o = oracle_lib.Oracle(m, kinds, prim, jv_mode=1, cfl=1.0)
+    s = hgks.Solver(m, kinds, prim, jv_mode=hgks.JV_APPROX, cfl=1.0)
+    Q = perturbed_state(o.N, prim, amp=0.01, seed=5)
+    s.set_state(Q)
+    Qo = Q.copy()
+    st, io = o.implicit_step(Qo)
+    ig = s.implicit_step()
+    assert st == 0 and np.isfinite(ig.res)
+    assert io.gmres_rel < 1e-20  # the oracle's cycle ended in an exact solve
+    np.testing.assert_allclose(s.get_state(), Qo, rtol=1e-10, atol=1e-12)
+    s.close()
