@@ -306,8 +306,7 @@ hgks_status jv_device(hgks_ctx* ctx, const double* v, double sigma_fixed, double
   if (ctx->o.jv_mode == HGKS_JV_APPROX) {
     // the approximate matrix at the base point (W64.Qx = Q^n, lam, D)
     launch_amatvec<double>(ctx->M, ctx->P, ctx->W64.Qx, ctx->lam, ctx->D, v, out, s);
-    const double zero = 0.0;
-    HIPCHK(hipMemcpyAsync(ctx->sc + 2, &zero, sizeof(double), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemsetAsync(ctx->sc + 2, 0, sizeof(double), s));  // sigma: none
     return HGKS_OK;
   }
   size_t n = n5(ctx);
@@ -577,6 +576,12 @@ static hgks_status finish_load(hgks_ctx* ctx) {
   ctx->flags = ctx->A.get<int>(4);
   ctx->gm = ctx->A.get<double>((size_t)(m + 1) * m + 3 * m + 1);
   ctx->gst = ctx->A.get<int>(4);
+  if (ctx->sc) {
+    // device constant sc[4] = 1 (the unit coefficient of the update axpys),
+    // set once so that no host copy sits between queued kernels
+    const double one = 1.0;
+    HIPCHK(hipMemcpy(ctx->sc + 4, &one, sizeof(double), hipMemcpyHostToDevice));
+  }
   if (!ctx->Qc || !ctx->dtc || !ctx->b || !ctx->V || !ctx->flags || !ctx->sc || !ctx->part || !ctx->gm || !ctx->gst) {
     ctx->err = "device allocation failed";
     return HGKS_ENOMEM;
@@ -749,9 +754,7 @@ hgks_status hgks_implicit_step(hgks_ctx* ctx, hgks_step_info* info) {
       if (fd) ++evals;
       // r = b - A dQ (FP64 in both forms: the outer defect correction)
       HIPCHK(hipMemcpyAsync(ctx->rv, ctx->b, n * sizeof(double), hipMemcpyDeviceToDevice, s));
-      double one = 1.0;
-      HIPCHK(hipMemcpyAsync(ctx->sc + 4, &one, sizeof(double), hipMemcpyHostToDevice, s));
-      launch_axpy_dev(ctx->yv, ctx->rv, n, ctx->sc + 4, -1.0, s);
+      launch_axpy_dev(ctx->yv, ctx->rv, n, ctx->sc + 4, -1.0, s);  // sc[4] = 1
     }
     precond_device(ctx, ctx->rv, ctx->wv, s);
     launch_dot(ctx->wv, ctx->wv, n, ctx->part, ctx->sc + 5, true, s);  // beta
@@ -799,9 +802,7 @@ hgks_status hgks_implicit_step(hgks_ctx* ctx, hgks_step_info* info) {
     return HGKS_ESTATE;
   }
   // Q^{n+1} = Q^n + dQ
-  double one = 1.0;
-  HIPCHK(hipMemcpyAsync(ctx->sc + 4, &one, sizeof(double), hipMemcpyHostToDevice, s));
-  launch_axpy_dev(ctx->dQ, ctx->Qc, n, ctx->sc + 4, 1.0, s);
+  launch_axpy_dev(ctx->dQ, ctx->Qc, n, ctx->sc + 4, 1.0, s);  // sc[4] = 1
   if (hw) {
     const int NX = N + ctx->H.Nb;
     for (int k = 0; k < 15; ++k)
