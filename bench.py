@@ -241,6 +241,8 @@ def main():
                 "frac": d["hbm_frac"], "traffic": traffic_for(dom), "avg_ms": d["avg_ms"], "launches": n_launch,
                 "per_launch": f"{d['bytes']} algorithmic bytes"}
 
+    chain = residual_chain(torch, s, N)
+
     solves = None
     if not args.no_solve and args.config == "c2":
         solves = time_to_drop(hgks, mesh, kinds, prim, args.solve_steps)
@@ -270,6 +272,7 @@ def main():
                    "cfl": 10.0, "krylov_dim": 10, "restarts": 3, "jacobi_sweeps": 2},
         "roofline": roof,
         "kernels": kernels,
+        "residual_chain": chain,
         "cpu_baseline": cpu,
         "time_to_1e-8": solves,
         "variants": variants,
@@ -474,6 +477,40 @@ def copy_calibration(torch):
     print(json.dumps({"copy_bytes_read": n * 8, "copy_bytes_written": n * 8, "copies": 3}), flush=True)
 
 
+def residual_chain(torch, s, N, reps=25, warm=3):
+    """The residual kernel chain on its own (state expansion, ghost cells,
+    time steps, reconstruction, side values, flux, gather), outside any
+    solve: each call is bracketed by HIP events on the stream it is queued
+    on; the median over the timed calls gives the rate."""
+    Q = torch.from_numpy(np.ascontiguousarray(s.get_state())).to("cuda")
+    R = torch.empty_like(Q)
+    st = torch.cuda.Stream()
+    for _ in range(warm):
+        s.residual_dev(Q, R, st.cuda_stream)
+    st.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    for a, b in ev:
+        a.record(st)
+        s.residual_dev(Q, R, st.cuda_stream)
+        b.record(st)
+    st.synchronize()
+    ms = sorted(a.elapsed_time(b) for a, b in ev)
+    med = float(np.median(ms))
+    return {"median_ms": round(med, 4), "min_ms": round(ms[0], 4), "max_ms": round(ms[-1], 4), "calls": reps,
+            "Mcell-residual/s": round(N / (med * 1e-3) / 1e6, 2)}
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def cpu_baseline(mesh, kinds, prim, opts, budget_s):
     """The oracle as it stands, timed on the host cores on a bounded sample:
     full residual evaluations of the same mesh and state, as many as fit the
@@ -498,8 +535,17 @@ def cpu_baseline(mesh, kinds, prim, opts, budget_s):
         if time.perf_counter() - t0 >= budget_s or n >= 50:
             break
     el = time.perf_counter() - t0
+    # the same oracle on one thread: one full evaluation
+    oracle.set_threads(1)
+    t1 = time.perf_counter()
+    o.residual(Q, G=G, want_grad=opts.get("scheme", 0) == 1)
+    el1 = time.perf_counter() - t1
+    oracle.set_threads(cores)
     return {"value": round(N * n / el / 1e6, 5), "unit": "Mcell-residual/s", "cores": cores, "kind": "oracle",
-            "sample": f"{n} full residual evaluation(s) of the same {N}-tet mesh and state, {el:.1f} s"}
+            "sample": f"{n} full residual evaluation(s) of the same {N}-tet mesh and state, {el:.1f} s",
+            "single_thread": {"value": round(N / el1 / 1e6, 5), "cores": 1,
+                              "sample": f"1 full residual evaluation of the same mesh and state, {el1:.1f} s"},
+            "host": {"nproc": os.cpu_count(), "cpu_model": cpu_model()}}
 
 
 if __name__ == "__main__":
