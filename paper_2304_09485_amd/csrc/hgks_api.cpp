@@ -571,7 +571,7 @@ static hgks_status finish_load(hgks_ctx* ctx) {
   ctx->dQ = ctx->A.get<double>(n);
   ctx->t1 = ctx->A.get<double>(n);
   ctx->t2 = ctx->A.get<double>(n);
-  ctx->part = ctx->A.get<double>(REDUCE_PARTS);
+  ctx->part = ctx->A.get<double>(2 * REDUCE_PARTS);  // two halves: the Gram-Schmidt chain alternates
   ctx->sc = ctx->A.get<double>(64 + MAXM + 1);
   ctx->flags = ctx->A.get<int>(4);
   ctx->gm = ctx->A.get<double>((size_t)(m + 1) * m + 3 * m + 1);
@@ -765,14 +765,18 @@ hgks_status hgks_implicit_step(hgks_ctx* ctx, hgks_step_info* info) {
       TRY(jv_device(ctx, vj, ctx->o.fd_sigma, ctx->yv, s));
       if (fd) ++evals;
       precond_device(ctx, ctx->yv, ctx->wv, s);
-      // modified Gram-Schmidt: h_0 = (w, v_0); then per i: w -= h_i v_i and
-      // h_{i+1} = (w, v_{i+1}) in one pass, the last pass giving |w|
-      launch_dot(ctx->wv, ctx->V, n, ctx->part, hc, false, s);
+      // modified Gram-Schmidt: partials of h_0 = (w, v_0); then per i one
+      // pass that sums the partials of h_i (stored in hc[i]), forms
+      // w -= h_i v_i and the partials of h_{i+1} = (w, v_{i+1}), the last
+      // pass those of |w|^2; the two halves of part alternate
+      launch_dot_part(ctx->wv, ctx->V, n, ctx->part, s);
       for (int i = 0; i <= j; ++i) {
         const double* vi = ctx->V + (size_t)i * n;
         const double* next = i < j ? ctx->V + (size_t)(i + 1) * n : nullptr;
-        launch_axpy_dot(vi, ctx->wv, n, hc + i, next, ctx->part, hc + i + 1, s);
+        launch_axpy_dot_chain(ctx->part + (i & 1) * REDUCE_PARTS, hc + i, vi, ctx->wv, n, next,
+                              ctx->part + ((i + 1) & 1) * REDUCE_PARTS, s);
       }
+      launch_reduce_final(ctx->part + ((j + 1) & 1) * REDUCE_PARTS, hc + j + 1, true, s);
       launch_gmres_column(j, m, hc, ctx->sc + 5, ctx->gm, ctx->gst, s);
       if (j + 1 < m) launch_scale_inv(ctx->wv, ctx->V + (size_t)(j + 1) * n, n, hc + j + 1, s, ctx->gst);
     }

@@ -42,10 +42,14 @@ template <typename T> void launch_check(const T* Qx, int N, int NX, double gamma
 
 void launch_dot(const double* x, const double* y, size_t n, double* part, double* out, bool sqrt_out, hipStream_t);
 void launch_abssum(const double* x, size_t n, double* part, double* out, hipStream_t);
-// w -= a[0] v; out = w.z, or |w| if z is null (one modified Gram-Schmidt step
-// and the next inner product in one pass)
-void launch_axpy_dot(const double* v, double* w, size_t n, const double* a, const double* z, double* part,
-                     double* out, hipStream_t);
+// block partials of x.y into part[REDUCE_PARTS]; their fixed-order sum
+// (sqrt of it if sq) into out[0]
+void launch_dot_part(const double* x, const double* y, size_t n, double* part, hipStream_t);
+void launch_reduce_final(const double* part, double* out, bool sq, hipStream_t);
+// h = the fixed-order sum of pin (stored in hout[0]); w -= h v; pout = block
+// partials of w.z, or of w.w if z is null (pin and pout distinct)
+void launch_axpy_dot_chain(const double* pin, double* hout, const double* v, double* w, size_t n, const double* z,
+                           double* pout, hipStream_t);
 void launch_axpy_dev(const double* x, double* y, size_t n, const double* a, double sgn, hipStream_t);
 void launch_scale_inv(const double* x, double* y, size_t n, const double* a, hipStream_t, const int* skip = nullptr);
 // GMRES cycle bookkeeping on the device: G [(m+1) m + 2 m + m + 1] holds H,

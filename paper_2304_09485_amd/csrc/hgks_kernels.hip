@@ -822,7 +822,7 @@ __global__ void __launch_bounds__(256) k_jacobi(DevMesh<T> M, Params P, const T*
 // vector kernels (FP64 Krylov space); deterministic two-level reductions
 // ---------------------------------------------------------------------------
 constexpr int RB = 256;     // reduction block
-constexpr int RGRID = 1024; // fixed grid -> fixed summation order
+constexpr int RGRID = REDUCE_PARTS; // fixed grid -> fixed summation order
 
 __device__ __forceinline__ double block_sum(double x) {
   __shared__ double sh[RB];
@@ -860,12 +860,19 @@ __global__ void __launch_bounds__(RB) k_reduce_final(const double* __restrict__ 
 }
 
 // one modified Gram-Schmidt step fused with the partials of the next inner
-// product: w -= a[0] v, then part = block partials of w.z (z = the next basis
-// vector, or w itself for the norm)
-__global__ void __launch_bounds__(RB) k_axpy_dot_part(const double* __restrict__ v, double* __restrict__ w, size_t n,
-                                                      const double* __restrict__ a, const double* __restrict__ z,
-                                                      double* __restrict__ part) {
-  const double h = a[0];
+// product.  Its coefficient h comes from the block partials of the previous
+// inner product: every block sums pin in the fixed order of k_reduce_final
+// (so h is bitwise the value that kernel would write), and block 0 stores it
+// in hout[0] for the Hessenberg column.  Then w -= h v, and pout = block
+// partials of w.z, or of w.w if z is null (pin and pout are distinct).
+__global__ void __launch_bounds__(RB) k_axpy_dot_chain(const double* __restrict__ pin, double* __restrict__ hout,
+                                                       const double* __restrict__ v, double* __restrict__ w, size_t n,
+                                                       const double* __restrict__ z, double* __restrict__ pout) {
+  double s0 = 0.0;
+  for (int k = threadIdx.x; k < RGRID; k += RB) s0 += pin[k];
+  const double h = block_sum(s0);
+  __syncthreads();  // every lane has read the sum before block_sum's buffer is reused
+  if (blockIdx.x == 0 && threadIdx.x == 0) hout[0] = h;
   double s = 0.0;
   for (size_t k = (size_t)blockIdx.x * RB + threadIdx.x; k < n; k += (size_t)RGRID * RB) {
     double wk = w[k] - h * v[k];
@@ -873,7 +880,7 @@ __global__ void __launch_bounds__(RB) k_axpy_dot_part(const double* __restrict__
     s += wk * (z ? z[k] : wk);
   }
   double t = block_sum(s);
-  if (threadIdx.x == 0) part[blockIdx.x] = t;
+  if (threadIdx.x == 0) pout[blockIdx.x] = t;
 }
 
 // y += alpha * x, alpha = sgn * a[0] (or * 1/a[0] if INV)
@@ -1181,13 +1188,18 @@ void launch_abssum(const double* x, size_t n, double* part, double* out, hipStre
   hipLaunchKernelGGL(k_reduce_part<1>, dim3(RGRID), dim3(RB), 0, s, x, x, n, part);
   hipLaunchKernelGGL(k_reduce_final<false>, dim3(1), dim3(RB), 0, s, part, out);
 }
-void launch_axpy_dot(const double* v, double* w, size_t n, const double* a, const double* z, double* part, double* out,
-                     hipStream_t s) {
-  hipLaunchKernelGGL(k_axpy_dot_part, dim3(RGRID), dim3(RB), 0, s, v, w, n, a, z ? z : w, part);
-  if (z)
-    hipLaunchKernelGGL(k_reduce_final<false>, dim3(1), dim3(RB), 0, s, part, out);
-  else
+void launch_dot_part(const double* x, const double* y, size_t n, double* part, hipStream_t s) {
+  hipLaunchKernelGGL(k_reduce_part<0>, dim3(RGRID), dim3(RB), 0, s, x, y, n, part);
+}
+void launch_reduce_final(const double* part, double* out, bool sq, hipStream_t s) {
+  if (sq)
     hipLaunchKernelGGL(k_reduce_final<true>, dim3(1), dim3(RB), 0, s, part, out);
+  else
+    hipLaunchKernelGGL(k_reduce_final<false>, dim3(1), dim3(RB), 0, s, part, out);
+}
+void launch_axpy_dot_chain(const double* pin, double* hout, const double* v, double* w, size_t n, const double* z,
+                           double* pout, hipStream_t s) {
+  hipLaunchKernelGGL(k_axpy_dot_chain, dim3(RGRID), dim3(RB), 0, s, pin, hout, v, w, n, z, pout);
 }
 void launch_axpy_dev(const double* x, double* y, size_t n, const double* a, double sgn, hipStream_t s) {
   hipLaunchKernelGGL(k_axpy_dev, dim3(nblk(n, 256)), dim3(256), 0, s, x, y, n, a, sgn);
