@@ -90,11 +90,11 @@ def algorithmic_bytes(kernel, N, F, Nb, scheme):
         # read once
         return F * (8 + 24 + 8 + 40) + Nb * 4 + N * 40
     if kernel == "lusgs_sweep":
-        # one sweep over all colour classes: per cell 4 face ids, colour,
-        # order slot, diagonal, state, right-hand side, its own and (once)
-        # its neighbours' unknowns, 5 values written; per face cell ids,
-        # normal, area and spectral radius
-        return N * (16 + 4 + 4 + 8 + 40 + 40 + 40 + 40) + F * 48
+        # one sweep over all colour classes: per cell 4 face ids, 4
+        # neighbour ids, colour, order slot, diagonal, state, right-hand
+        # side, its own and (once) its neighbours' unknowns, 5 values
+        # written; per face normal, area and spectral radius
+        return N * (16 + 16 + 4 + 4 + 8 + 40 + 40 + 40 + 40) + F * 40
     if kernel == "flux":
         # 60 side values per reconstructed side read; per face the two cell
         # ids, the two cells' time steps, 5 face-flux values written (the

@@ -311,10 +311,10 @@ hgks_status jv_device(hgks_ctx* ctx, const double* v, double sigma_fixed, double
   }
   size_t n = n5(ctx);
   const int N = ctx->H.N, NX = ctx->H.N + ctx->H.Nb;
-  launch_dot(v, v, n, ctx->part, ctx->sc + 1, false, s);
+  launch_dot_part(v, v, n, ctx->part, s);  // partials of |v|^2, summed by the sigma kernel
   bool f32 = inner && ctx->o.precision == HGKS_FP32_INNER;
   double eps = f32 ? std::ldexp(1.0, -23) : std::ldexp(1.0, -52);
-  launch_sigma(ctx->sc + 1, ctx->sc + 0, (double)n, eps, sigma_fixed, ctx->sc + 2, s);
+  launch_sigma(ctx->part, ctx->sc + 0, (double)n, eps, sigma_fixed, ctx->sc + 2, s);
   if (!f32) {
     launch_perturb<double>(ctx->Qc, v, ctx->sc + 2, N, NX, ctx->Qp64, s);
     residual_pipeline<double, double>(ctx, ctx->M, ctx->W64, ctx->Qp64, ctx->W64.dt, 1, out, v, ctx->b,
@@ -535,9 +535,10 @@ static hgks_status finish_load(hgks_ctx* ctx) {
   TRY(upload(ctx, H.cface, M.cface));
   TRY(upload(ctx, H.gowner, M.gowner));
   TRY(upload(ctx, H.gface, M.gface));
-  if (ctx->o.scheme == HGKS_HWENO) {
-    TRY(upload(ctx, H.nbf, M.nbf));
-  } else if (ctx->o.scheme == HGKS_WENO) {
+  // face neighbours: the compact stencil, and the neighbour ids of the
+  // Jacobi sweeps for every scheme
+  TRY(upload(ctx, H.nbf, M.nbf));
+  if (ctx->o.scheme == HGKS_WENO) {
     TRY(upload(ctx, H.stn, M.stn));
     TRY(upload(ctx, H.sstn, M.sstn));
     TRY(upload(ctx, H.smask, M.smask));

@@ -59,7 +59,9 @@ void launch_gmres_column(int j, int m, const double* hc, const double* beta, dou
 void launch_gmres_solve(int m, const double* G, const int* st, double* y, double* out, hipStream_t);
 void launch_combine(const double* V, const double* c, int nv, size_t n, const double* x, double* y, hipStream_t);
 void launch_convert(const double* src, float* dst, size_t n, hipStream_t);
-void launch_sigma(const double* vv, const double* qq, double n, double eps, double fixed, double* sigma,
+// FD step of the Jv product from the block partials of |v|^2 (vpart) and the
+// reduced |Q|^2 (qq[0]) into sigma[0]
+void launch_sigma(const double* vpart, const double* qq, double n, double eps, double fixed, double* sigma,
                   hipStream_t);
 
 constexpr int REDUCE_PARTS = 1024;  // partials of a reduction

@@ -717,11 +717,10 @@ __global__ void __launch_bounds__(256) k_amatvec(DevMesh<T> M, Params P, const T
   for (int v = 0; v < 5; ++v) acc[v] = D[i] * T(x[(size_t)v * N + i]);
 #pragma unroll
   for (int p = 0; p < NF; ++p) {
-    int cf = M.cface[p * N + i];
-    int f = (cf > 0 ? cf : -cf) - 1;
-    int L = M.fL[f], R = M.fR[f];
-    if (R >= N) continue;
-    int jn = cf > 0 ? R : L;
+    const int cf = M.cface[p * N + i];
+    const int jn = M.nbf[p * N + i];  // read beside the face id
+    if (jn >= N) continue;
+    const int f = (cf > 0 ? cf : -cf) - 1;
     T s = cf > 0 ? T(1) : T(-1);
     T n[3] = {s * M.fn[f], s * M.fn[F + f], s * M.fn[2 * F + f]};
     T qj[5], xj[5], jx[5];
@@ -755,11 +754,10 @@ __global__ void __launch_bounds__(256) k_lusgs(DevMesh<T> M, Params P, const T* 
   T off[5] = {0, 0, 0, 0, 0};
 #pragma unroll
   for (int p = 0; p < NF; ++p) {
-    int cf = M.cface[p * N + i];
-    int f = (cf > 0 ? cf : -cf) - 1;
-    int L = M.fL[f], R = M.fR[f];
-    if (R >= N) continue;
-    int jn = cf > 0 ? R : L;
+    const int cf = M.cface[p * N + i];
+    const int jn = M.nbf[p * N + i];  // read beside the face id
+    if (jn >= N) continue;
+    const int f = (cf > 0 ? cf : -cf) - 1;
     int cj = M.ccol[jn];
     if (FWD ? cj > col : cj < col) continue;
     T s = cf > 0 ? T(1) : T(-1);
@@ -796,11 +794,12 @@ __global__ void __launch_bounds__(256) k_jacobi(DevMesh<T> M, Params P, const T*
     T g = T(P.gamma);
 #pragma unroll
     for (int p = 0; p < NF; ++p) {
-      int cf = M.cface[p * N + i];
-      int f = (cf > 0 ? cf : -cf) - 1;
-      int L = M.fL[f], R = M.fR[f];
-      if (R >= N) continue;  // boundary off-diagonal blocks are dropped
-      int jn = cf > 0 ? R : L;
+      // the neighbour id is read beside the face id (not through the face),
+      // so the neighbour's data and the face's data are gathered in parallel
+      const int cf = M.cface[p * N + i];
+      const int jn = M.nbf[p * N + i];
+      if (jn >= N) continue;  // boundary off-diagonal blocks are dropped
+      const int f = (cf > 0 ? cf : -cf) - 1;
       T s = cf > 0 ? T(1) : T(-1);
       T n[3] = {s * M.fn[f], s * M.fn[F + f], s * M.fn[2 * F + f]};
       T qj[5], xj[5], jx[5];
@@ -1002,10 +1001,15 @@ __global__ void __launch_bounds__(256) k_convert(const double* __restrict__ src,
 }
 
 // automatic FD step of Eq. (frechet): sqrt(eps) max(1, rms Q) / rms v
-__global__ void k_sigma(const double* __restrict__ vv, const double* __restrict__ qq, double n, double eps,
-                        double fixed, double* __restrict__ sigma) {
+// (|v|^2 is summed here from its block partials, in the fixed order of
+// k_reduce_final, so no separate reduction launch precedes this one)
+__global__ void __launch_bounds__(RB) k_sigma(const double* __restrict__ vpart, const double* __restrict__ qq,
+                                              double n, double eps, double fixed, double* __restrict__ sigma) {
+  double s0 = 0.0;
+  for (int k = threadIdx.x; k < RGRID; k += RB) s0 += vpart[k];
+  const double vv = block_sum(s0);
   if (threadIdx.x != 0) return;
-  double rv = sqrt(vv[0] / n);
+  double rv = sqrt(vv / n);
   if (rv == 0.0) {
     sigma[0] = 0.0;
     return;
@@ -1222,9 +1226,9 @@ void launch_combine(const double* V, const double* c, int nv, size_t n, const do
 void launch_convert(const double* src, float* dst, size_t n, hipStream_t s) {
   if (n) hipLaunchKernelGGL(k_convert, dim3(nblk(n, 256)), dim3(256), 0, s, src, dst, n);
 }
-void launch_sigma(const double* vv, const double* qq, double n, double eps, double fixed, double* sigma,
+void launch_sigma(const double* vpart, const double* qq, double n, double eps, double fixed, double* sigma,
                   hipStream_t s) {
-  hipLaunchKernelGGL(k_sigma, dim3(1), dim3(64), 0, s, vv, qq, n, eps, fixed, sigma);
+  hipLaunchKernelGGL(k_sigma, dim3(1), dim3(RB), 0, s, vpart, qq, n, eps, fixed, sigma);
 }
 
 #define HGKS_INST(T)                                                                                              \

@@ -164,14 +164,15 @@ size_t hgks_estimate_bytes(int64_t n_tets, int64_t n_bfaces, const hgks_options*
   bool hw = o && o->scheme == HGKS_HWENO;
   bool ko = o && o->scheme == HGKS_KFVS1;  // no stencils, operators or side values
   bool f32 = o && o->precision == HGKS_FP32_INNER;
-  double ints = F * 3 + N * 4 + Nb * 2 + (ko ? 0 : (hw ? 4 * N : (16 + 24) * N));
+  // faces (L, R, kind), cell faces, neighbours, ghosts; WENO stencils
+  double ints = F * 3 + N * 4 + N * 4 + Nb * 2 + (ko || hw ? 0 : (16 + 24) * N);
   double bytes = 4.0 * ints + (hw || ko ? 0 : N);
   double fp = N * (1 + 1 + 1 + 6) + F * (3 + 1 + 9 + 9) + (ko ? 0 : (hw ? N * (171 + 24) : N * (144 + 72)));
   double work = 5 * NX + (ko ? 0 : 105 * N + 120 * F) + 5 * F + 5 * F + N + (hw ? 15 * NX : 0);
   bytes += 8.0 * (fp + work);
   // state, base residuals, gradients, diagonal, Krylov basis, work vectors
   bytes += 8.0 * (5 * N + 5 * NX + (hw ? 15 * NX : 0) + N + 10 * N + 15 * N + F + N + (m + 1) * 5 * N + 6 * 5 * N +
-                  1024 + 128);
+                  2 * 1024 + 128);
   if (f32) bytes += 4.0 * (fp + work + 5 * NX);
   if (o && o->solver == HGKS_SOLVER_LUSGS) bytes += 4.0 * 2 * N;  // colours and colour order
   return (size_t)(bytes * 1.05) + ((size_t)16 << 20);
