@@ -4,8 +4,11 @@
 // back-projected to conservative variables in the face's local frame.  One
 // lane per face side; the 5 characteristic components are taken in turn
 // (projection of the side cell's 9 + 3 NSUB coefficient vectors, smoothness
-// indicators, nonlinear weights, combined polynomial at the Gauss points) and
-// accumulated into the 20 NG outputs through R*.  NSUB: 4 sub-stencils on a
+// indicators, nonlinear weights, combined polynomial).  Each component's
+// combined polynomial is kept as 10 numbers in LDS (the lane's own column,
+// no sharing between lanes), and the 20 NG outputs are formed from them
+// through R* after the component loop, so that no output accumulators are
+// live while the 105 coefficients are.  NSUB: 4 sub-stencils on a
 // tetrahedron, 8 (non-compact) or 6 (compact) on a hexahedron.
 // sv layout [20 NG][2F], row (g*4+d)*5+v, column side*F+f.
 // Included inside namespace hgks of hgks_kernels.hip.
@@ -16,8 +19,8 @@ constexpr int SIDE_THREADS = 128;  // threads per block
 
 // LPS lanes per side: 1 (each lane evaluates all NG Gauss points), or NG
 // (each lane one Gauss point; the projection and the weights are repeated
-// per lane, the live output shrinks from 20 NG to 20 values, and the
-// positivity decision is shared by the side's lanes through a ballot).
+// per lane, and the positivity decision is shared by the side's lanes
+// through a ballot).
 template <typename T, int NSUB, int NG, int LPS>
 __global__ void __launch_bounds__(128) k_side(DevMesh<T> M, Params P, const T* __restrict__ Qx,
                                               const T* __restrict__ coef, T* __restrict__ sv,
@@ -72,40 +75,33 @@ __global__ void __launch_bounds__(128) k_side(DevMesh<T> M, Params P, const T* _
   int nsub = __popc(mask);
   const T gl = T(P.gamma_lin);
   const T g0 = T(1) - gl * T(nsub);
-  T out[NGL][4][5];
-#pragma unroll
-  for (int a = 0; a < NGL; ++a)
-#pragma unroll
-    for (int d = 0; d < 4; ++d)
-#pragma unroll
-      for (int v = 0; v < 5; ++v) out[a][d][v] = T(0);
+  // per characteristic component cc, the combined polynomial in the form
+  // q0' + Lc . xi + Qc . (xi xi) with q0' = q0 - Qc . m2 (10 numbers); the
+  // outputs are formed from these after the component loop
+  __shared__ T pqs[50][SIDE_THREADS];  // [cc * 10 + k][lane of the block]
+  const int lt = threadIdx.x;
+#pragma unroll 1
   for (int cc = 0; cc < 5; ++cc) {
-    // row cc of L* = R*^{-1} and column cc of R* (x-split Euler eigenvectors
-    // at Q*, columns u-c, u, u, u, u+c), built from the eigen-system scalars
-    // (no per-lane matrices: indexing those by cc would put them in scratch)
-    T l[5], r[5];
+    // row cc of L* = R*^{-1} (x-split Euler eigenvectors at Q*, columns
+    // u-c, u, u, u, u+c), built from the eigen-system scalars
+    T l[5];
     switch (cc) {
       case 0:
         l[0] = T(0.5) * (b2 + u * ic); l[1] = T(0.5) * (-b1 * u - ic); l[2] = T(-0.5) * b1 * vv;
         l[3] = T(-0.5) * b1 * w; l[4] = T(0.5) * b1;
-        r[0] = T(1); r[1] = u - c; r[2] = vv; r[3] = w; r[4] = H - u * c;
         break;
       case 1:
         l[0] = T(1) - b2; l[1] = b1 * u; l[2] = b1 * vv; l[3] = b1 * w; l[4] = -b1;
-        r[0] = T(1); r[1] = u; r[2] = vv; r[3] = w; r[4] = T(0.5) * q2;
         break;
       case 2:
         l[0] = -vv; l[1] = T(0); l[2] = T(1); l[3] = T(0); l[4] = T(0);
-        r[0] = T(0); r[1] = T(0); r[2] = T(1); r[3] = T(0); r[4] = vv;
         break;
       case 3:
         l[0] = -w; l[1] = T(0); l[2] = T(0); l[3] = T(1); l[4] = T(0);
-        r[0] = T(0); r[1] = T(0); r[2] = T(0); r[3] = T(1); r[4] = w;
         break;
       default:
         l[0] = T(0.5) * (b2 - u * ic); l[1] = T(0.5) * (-b1 * u + ic); l[2] = T(-0.5) * b1 * vv;
         l[3] = T(-0.5) * b1 * w; l[4] = T(0.5) * b1;
-        r[0] = T(1); r[1] = u + c; r[2] = vv; r[3] = w; r[4] = H + u * c;
         break;
     }
     // row cc of T = L* . Rot
@@ -176,49 +172,82 @@ __global__ void __launch_bounds__(128) k_side(DevMesh<T> M, Params P, const T* _
     }
 #pragma unroll
     for (int t = 0; t < 6; ++t) Qc[t] = r0 * a[3 + t];
+    pqs[cc * 10][lt] = q0 - (Qc[0] * m2[0] + Qc[1] * m2[1] + Qc[2] * m2[2] + Qc[3] * m2[3] + Qc[4] * m2[4] + Qc[5] * m2[5]);
 #pragma unroll
-    for (int gp = 0; gp < NGL; ++gp) {
-      T x0 = xi[gp][0], x1 = xi[gp][1], x2 = xi[gp][2];
-      T val = q0 + Lc[0] * x0 + Lc[1] * x1 + Lc[2] * x2 + Qc[0] * (x0 * x0 - m2[0]) +
-              Qc[1] * (x1 * x1 - m2[1]) + Qc[2] * (x2 * x2 - m2[2]) + Qc[3] * (x0 * x1 - m2[3]) +
-              Qc[4] * (x0 * x2 - m2[4]) + Qc[5] * (x1 * x2 - m2[5]);
-      T gx = Lc[0] + T(2) * Qc[0] * x0 + Qc[3] * x1 + Qc[4] * x2;
-      T gy = Lc[1] + T(2) * Qc[1] * x1 + Qc[3] * x0 + Qc[5] * x2;
-      T gz = Lc[2] + T(2) * Qc[2] * x2 + Qc[4] * x0 + Qc[5] * x1;
-      T dd[4];
-      dd[0] = val;
+    for (int t = 0; t < 3; ++t) pqs[cc * 10 + 1 + t][lt] = Lc[t];
 #pragma unroll
-      for (int a2 = 0; a2 < 3; ++a2) dd[1 + a2] = (gx * e[a2][0] + gy * e[a2][1] + gz * e[a2][2]) * ih;
-#pragma unroll
-      for (int d = 0; d < 4; ++d)
-#pragma unroll
-        for (int v = 0; v < 5; ++v) out[gp][d][v] += r[v] * dd[d];
-    }
+    for (int t = 0; t < 6; ++t) pqs[cc * 10 + 4 + t][lt] = Qc[t];
   }
+  // column cc of R* (conservative components of the characteristic mode cc)
+  T rc[5][5];
+  rc[0][0] = T(1); rc[0][1] = u - c; rc[0][2] = vv; rc[0][3] = w; rc[0][4] = H - u * c;
+  rc[1][0] = T(1); rc[1][1] = u; rc[1][2] = vv; rc[1][3] = w; rc[1][4] = T(0.5) * q2;
+  rc[2][0] = T(0); rc[2][1] = T(0); rc[2][2] = T(1); rc[2][3] = T(0); rc[2][4] = vv;
+  rc[3][0] = T(0); rc[3][1] = T(0); rc[3][2] = T(0); rc[3][3] = T(1); rc[3][4] = w;
+  rc[4][0] = T(1); rc[4][1] = u + c; rc[4][2] = vv; rc[4][3] = w; rc[4][4] = H + u * c;
+  // point values first: they decide the side's positivity fallback
   bool ok = true;
 #pragma unroll
-  for (int gp = 0; gp < NGL; ++gp) ok = ok && phys_ok(out[gp][0], g);
+  for (int gp = 0; gp < NGL; ++gp) {
+    const T x0 = xi[gp][0], x1 = xi[gp][1], x2 = xi[gp][2];
+    T val[5] = {T(0), T(0), T(0), T(0), T(0)};
+#pragma unroll
+    for (int cc = 0; cc < 5; ++cc) {
+      T p[10];
+#pragma unroll
+      for (int k = 0; k < 10; ++k) p[k] = pqs[cc * 10 + k][lt];
+      T pv = p[0] + p[1] * x0 + p[2] * x1 + p[3] * x2 + p[4] * (x0 * x0) + p[5] * (x1 * x1) + p[6] * (x2 * x2) +
+             p[7] * (x0 * x1) + p[8] * (x0 * x2) + p[9] * (x1 * x2);
+#pragma unroll
+      for (int v = 0; v < 5; ++v) val[v] += rc[cc][v] * pv;
+    }
+    ok = ok && phys_ok(val, g);
+  }
   if (LPS > 1) {
     // the side falls back if any of its lanes' Gauss points is non-physical
     const unsigned long long bad = __ballot(!ok);
     const int lane0 = (int)(__lane_id() & ~(unsigned)(LPS - 1));
     ok = ((bad >> lane0) & ((1ull << LPS) - 1ull)) == 0ull;
   }
+  const size_t ld = 2 * (size_t)F;
   if (!ok) {
     // positivity fallback: first order on this side
     if (g_lo == 0) atomicAdd(nfall, 1);
-    for (int gp = 0; gp < NGL; ++gp) {
-      for (int v = 0; v < 5; ++v) out[gp][0][v] = qil[v];
-      for (int d = 1; d < 4; ++d)
-        for (int v = 0; v < 5; ++v) out[gp][d][v] = T(0);
-    }
+    for (int gp = 0; gp < NGL; ++gp)
+      for (int d = 0; d < 4; ++d)
+        for (int v = 0; v < 5; ++v)
+          sv[(size_t)(((g_lo + gp) * 4 + d) * 5 + v) * ld + sidx] = d == 0 ? qil[v] : T(0);
+    return;
   }
-  const size_t ld = 2 * (size_t)F;
 #pragma unroll
-  for (int gp = 0; gp < NGL; ++gp)
+  for (int gp = 0; gp < NGL; ++gp) {
+    const T x0 = xi[gp][0], x1 = xi[gp][1], x2 = xi[gp][2];
+    T out[4][5];
 #pragma unroll
     for (int d = 0; d < 4; ++d)
 #pragma unroll
-      for (int v = 0; v < 5; ++v) sv[(size_t)(((g_lo + gp) * 4 + d) * 5 + v) * ld + sidx] = out[gp][d][v];
+      for (int v = 0; v < 5; ++v) out[d][v] = T(0);
+#pragma unroll
+    for (int cc = 0; cc < 5; ++cc) {
+      T p[10];
+#pragma unroll
+      for (int k = 0; k < 10; ++k) p[k] = pqs[cc * 10 + k][lt];
+      T dd[4];
+      dd[0] = p[0] + p[1] * x0 + p[2] * x1 + p[3] * x2 + p[4] * (x0 * x0) + p[5] * (x1 * x1) + p[6] * (x2 * x2) +
+              p[7] * (x0 * x1) + p[8] * (x0 * x2) + p[9] * (x1 * x2);
+      const T gx = p[1] + T(2) * p[4] * x0 + p[7] * x1 + p[8] * x2;
+      const T gy = p[2] + T(2) * p[5] * x1 + p[7] * x0 + p[9] * x2;
+      const T gz = p[3] + T(2) * p[6] * x2 + p[8] * x0 + p[9] * x1;
+#pragma unroll
+      for (int a2 = 0; a2 < 3; ++a2) dd[1 + a2] = (gx * e[a2][0] + gy * e[a2][1] + gz * e[a2][2]) * ih;
+#pragma unroll
+      for (int d = 0; d < 4; ++d)
+#pragma unroll
+        for (int v = 0; v < 5; ++v) out[d][v] += rc[cc][v] * dd[d];
+    }
+#pragma unroll
+    for (int d = 0; d < 4; ++d)
+#pragma unroll
+      for (int v = 0; v < 5; ++v) sv[(size_t)(((g_lo + gp) * 4 + d) * 5 + v) * ld + sidx] = out[d][v];
+  }
 }
-
