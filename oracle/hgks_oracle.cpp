@@ -1680,6 +1680,10 @@ static int implicit_step(const orc_ctx& C, double* Q, double* G, orc_step_info* 
       }
       double hn = std::sqrt(dotv(w, w));
       H[(j + 1) * m + j] = hn;
+      // norm of the preconditioned product before orthogonalisation, from the
+      // raw column (h_0j, ..., h_jj, h_j+1,j), for the breakdown test below
+      double col2 = 0.0;
+      for (int i = 0; i <= j + 1; ++i) col2 += H[i * m + j] * H[i * m + j];
       // Givens rotations on the new column
       for (int i = 0; i < j; ++i) {
         double a = H[i * m + j], c = H[(i + 1) * m + j];
@@ -1695,7 +1699,9 @@ static int implicit_step(const orc_ctx& C, double* Q, double* G, orc_step_info* 
       gvec[j + 1] = -sn[j] * gvec[j];
       gvec[j] = cs[j] * gvec[j];
       jdone = j + 1;
-      if (hn <= 1e-14 * beta) break;  // happy breakdown (reading A21)
+      // happy breakdown (reading A21): the new direction is lost to rounding
+      // relative to the vector it was orthogonalised from
+      if (hn <= 1e-14 * std::sqrt(col2)) break;
       for (size_t k = 0; k < n; ++k) V[j + 1][k] = w[k] / hn;
     }
     // back substitution of the triangular system

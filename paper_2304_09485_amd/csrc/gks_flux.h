@@ -271,10 +271,13 @@ HGKS_HD void apsi_mom(const VWX<T>& M, const T u[8], const T a[5], T s, T out[5]
 
 // Time-averaged flux over [0, dt] (local frame) and, if want_qg, the point
 // value Q(x_G, t = dt) of Eq. (point).  W*: conserved local-frame states,
-// d*[3][5]: their derivatives along (n, t1, t2).
+// d*[3][5]: their derivatives along (n, t1, t2).  sl: storage for the 45
+// slope values (left, right, equilibrium); the device passes a slot of LDS,
+// so that the slopes need not stay in registers between their formation and
+// the terms that use them.
 template <typename T, bool want_qg>
 HGKS_HD void gks_flux(const T Wl[5], const T dWl[3][5], const T Wr[5], const T dWr[3][5], T dt,
-                      const FluxParams<T>& P, T F[5], T QG[5]) {
+                      const FluxParams<T>& P, T F[5], T QG[5], T* sl) {
   const T g = P.gamma, K = P.K;
   const T ik3 = T(1) / (K + T(3));
   // primitive variables of both sides; per Maxwellian the factor 1/(2 lam)
@@ -334,7 +337,9 @@ HGKS_HD void gks_flux(const T Wl[5], const T dWl[3][5], const T Wr[5], const T d
 
   // slopes of the initial distributions in the directions (n, t1, t2) and
   // the kinetic-weighted derivatives of Q0
-  T al[3][5], ar[3][5], ab[3][5];
+  T(*al)[5] = reinterpret_cast<T(*)[5]>(sl);
+  T(*ar)[5] = reinterpret_cast<T(*)[5]>(sl + 15);
+  T(*ab)[5] = reinterpret_cast<T(*)[5]>(sl + 30);
   {
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
@@ -425,6 +430,14 @@ HGKS_HD void gks_flux(const T Wl[5], const T dWl[3][5], const T Wr[5], const T d
   if (want_qg)
 #pragma unroll
     for (int k = 0; k < 5; ++k) QG[k] = Qg[k];
+}
+
+// the same with the slopes in a local array (host builds)
+template <typename T, bool want_qg>
+HGKS_HD void gks_flux(const T Wl[5], const T dWl[3][5], const T Wr[5], const T dWr[3][5], T dt,
+                      const FluxParams<T>& P, T F[5], T QG[5]) {
+  T sl[45];
+  gks_flux<T, want_qg>(Wl, dWl, Wr, dWr, dt, P, F, QG, sl);
 }
 
 // First-order kinetic flux vector splitting (the Mach 3 retest of Sec. 5):

@@ -778,7 +778,7 @@ hgks_status hgks_implicit_step(hgks_ctx* ctx, hgks_step_info* info) {
                               ctx->part + ((i + 1) & 1) * REDUCE_PARTS, s);
       }
       launch_reduce_final(ctx->part + ((j + 1) & 1) * REDUCE_PARTS, hc + j + 1, true, s);
-      launch_gmres_column(j, m, hc, ctx->sc + 5, ctx->gm, ctx->gst, s);
+      launch_gmres_column(j, m, hc, ctx->gm, ctx->gst, s);
       if (j + 1 < m) launch_scale_inv(ctx->wv, ctx->V + (size_t)(j + 1) * n, n, hc + j + 1, s, ctx->gst);
     }
     launch_gmres_solve(m, ctx->gm, ctx->gst, yd, last_d, s);

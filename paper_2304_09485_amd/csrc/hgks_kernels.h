@@ -55,7 +55,7 @@ void launch_scale_inv(const double* x, double* y, size_t n, const double* a, hip
 // GMRES cycle bookkeeping on the device: G [(m+1) m + 2 m + m + 1] holds H,
 // the Givens rotations and g; st [3]: finished, non-finite, columns done
 void launch_gmres_start(const double* beta, double* G, int* st, int m, hipStream_t);
-void launch_gmres_column(int j, int m, const double* hc, const double* beta, double* G, int* st, hipStream_t);
+void launch_gmres_column(int j, int m, const double* hc, double* G, int* st, hipStream_t);
 void launch_gmres_solve(int m, const double* G, const int* st, double* y, double* out, hipStream_t);
 void launch_combine(const double* V, const double* c, int nv, size_t n, const double* x, double* y, hipStream_t);
 void launch_convert(const double* src, float* dst, size_t n, hipStream_t);

@@ -434,6 +434,7 @@ __global__ void __launch_bounds__(64) k_flux(DevMesh<T> M, Params P, const T* __
                                              T* __restrict__ fq) {
   constexpr int FPB = flux_fpb<NG>();
   __shared__ T red[QG ? 10 : 5][64];
+  __shared__ T slopes[64 * 45];  // the 45 slope values of each lane's Gauss point
   const int F = M.F, N = M.N;
   const int lane = threadIdx.x;
   const int f = xcd_block() * FPB + lane / NG;  // contiguous face ranges per XCD
@@ -477,7 +478,7 @@ __global__ void __launch_bounds__(64) k_flux(DevMesh<T> M, Params P, const T* __
         for (int d = 0; d < 3; ++d) dWr[d][v] = sv[(size_t)((gp * 4 + 1 + d) * 5 + v) * ld + rc];
       }
     }
-    gks_flux<T, QG>(Wl, dWl, Wr, dWr, dtf, fp, Fg, Qg);
+    gks_flux<T, QG>(Wl, dWl, Wr, dWr, dtf, fp, Fg, Qg, slopes + lane * 45);
   }
 #pragma unroll
   for (int v = 0; v < 5; ++v) red[v][lane] = Fg[v];
@@ -919,8 +920,8 @@ __global__ void k_gmres_start(const double* __restrict__ beta, double* __restric
 
 // column j of H from the modified Gram-Schmidt coefficients hc[0..j+1]:
 // apply the previous rotations, form rotation j, update g
-__global__ void k_gmres_column(int j, int m, const double* __restrict__ hc, const double* __restrict__ beta,
-                               double* __restrict__ G, int* __restrict__ st) {
+__global__ void k_gmres_column(int j, int m, const double* __restrict__ hc, double* __restrict__ G,
+                               int* __restrict__ st) {
   if (st[0]) return;
   double* H = G;
   double* cs = G + (size_t)(m + 1) * m;
@@ -934,6 +935,10 @@ __global__ void k_gmres_column(int j, int m, const double* __restrict__ hc, cons
     }
   for (int i = 0; i <= j + 1; ++i) H[(size_t)i * m + j] = hc[i];
   const double hn = hc[j + 1];
+  // |P A v_j| before orthogonalisation, from the raw column, for the
+  // breakdown test
+  double col2 = 0.0;
+  for (int i = 0; i <= j + 1; ++i) col2 += hc[i] * hc[i];
   for (int i = 0; i < j; ++i) {
     double a = H[(size_t)i * m + j], c = H[(size_t)(i + 1) * m + j];
     H[(size_t)i * m + j] = cs[i] * a + sn[i] * c;
@@ -948,7 +953,9 @@ __global__ void k_gmres_column(int j, int m, const double* __restrict__ hc, cons
   g[j + 1] = -sn[j] * g[j];
   g[j] = cs[j] * g[j];
   st[2] = j + 1;
-  if (hn <= 1e-14 * beta[0]) st[0] = 1;  // happy breakdown
+  // happy breakdown: the new direction is lost to rounding relative to the
+  // vector it was orthogonalised from
+  if (hn <= 1e-14 * sqrt(col2)) st[0] = 1;
 }
 
 // back substitution of the triangular system (y = 0 beyond the columns done,
@@ -1214,8 +1221,8 @@ void launch_scale_inv(const double* x, double* y, size_t n, const double* a, hip
 void launch_gmres_start(const double* beta, double* G, int* st, int m, hipStream_t s) {
   hipLaunchKernelGGL(k_gmres_start, dim3(1), dim3(1), 0, s, beta, G, st, m);
 }
-void launch_gmres_column(int j, int m, const double* hc, const double* beta, double* G, int* st, hipStream_t s) {
-  hipLaunchKernelGGL(k_gmres_column, dim3(1), dim3(1), 0, s, j, m, hc, beta, G, st);
+void launch_gmres_column(int j, int m, const double* hc, double* G, int* st, hipStream_t s) {
+  hipLaunchKernelGGL(k_gmres_column, dim3(1), dim3(1), 0, s, j, m, hc, G, st);
 }
 void launch_gmres_solve(int m, const double* G, const int* st, double* y, double* out, hipStream_t s) {
   hipLaunchKernelGGL(k_gmres_solve, dim3(1), dim3(1), 0, s, m, G, st, y, out);
