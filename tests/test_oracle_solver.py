@@ -225,3 +225,36 @@ def test_config1_ten_steps_converge(oracle_lib):
     # gains little per step; the density residual still falls several-fold
     assert res[-1] < 0.2 * res[0], res
     assert all(np.isfinite(res))
+
+
+def test_gmres_breakdown_single_tet_is_exact(oracle_lib):
+    """One tetrahedron: all four faces are boundary faces, whose off-diagonal
+    blocks of Eq. (deri-matrix) are dropped, so A = D I with the scalar
+    diagonal D = |Omega|/dt + sum_f lam_f S_f / 2, recomputed here from the
+    face data (supersonic-inflow boundaries: the ghost is the free stream, and
+    lam_f comes from the mean of the owner's and the free stream's primitive
+    variables).  The Jacobi-preconditioned Arnoldi process therefore loses
+    its second direction to rounding right after the first column (happy
+    breakdown), and the step must be Q + L(Q)/D."""
+    from tests.test_edge_cases import tiny_mesh
+    m = tiny_mesh(1)
+    prim = freestream_prim(0.3)
+    kinds = {t: oracle_lib.SUP_IN for t in range(1, 7)}
+    o = oracle_lib.Oracle(m, kinds, prim, jv_mode=1, cfl=1.0)
+    Q = perturbed_state(o.N, prim, amp=0.01, seed=5)
+    dt = o.dt(Q)
+    b = o.residual(Q, dt=dt)
+    vol = o.geometry()[0]
+    L, R, S, n, gp = o.faces()
+    assert o.N == 1 and (R < 0).all()
+    ra, Ua, pa = I.prim(Q[:, 0])
+    rb, Ub, pb = I.prim(prim_to_cons(prim))
+    r, U, p = (ra + rb) / 2, (Ua + Ub) / 2, (pa + pb) / 2
+    lam_f = np.array([abs(U @ n[:, f]) + np.sqrt(1.4 * p / r) for f in range(len(L))])
+    D = vol[0] / dt[0] + 0.5 * (lam_f * S).sum()
+    Q1 = Q.copy()
+    st, info = o.implicit_step(Q1)
+    assert st == 0 and info.n_resid_evals == 1 and info.gmres_rel < 1e-14
+    assert np.abs(b).max() > 1e-4  # the inflow makes a residual of size
+    ref = b / D
+    np.testing.assert_allclose(Q1 - Q, ref, rtol=0, atol=1e-12 * np.abs(ref).max())
