@@ -824,15 +824,21 @@ __global__ void __launch_bounds__(256) k_jacobi(DevMesh<T> M, Params P, const T*
 constexpr int RB = 256;     // reduction block
 constexpr int RGRID = REDUCE_PARTS; // fixed grid -> fixed summation order
 
+// sum over the block in a fixed order: a shuffle tree within each 64-lane
+// wave, then the wave sums in index order; every lane gets the result.  A
+// second call in the same kernel needs a barrier before it (the wave sums
+// are read by all lanes).
 __device__ __forceinline__ double block_sum(double x) {
-  __shared__ double sh[RB];
-  sh[threadIdx.x] = x;
+  static_assert(RB % 64 == 0, "whole waves");
+  __shared__ double sh[RB / 64];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) x += __shfl_down(x, off, 64);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = x;
   __syncthreads();
-  for (int s = RB / 2; s > 0; s >>= 1) {
-    if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
-    __syncthreads();
-  }
-  return sh[0];
+  double t = sh[0];
+#pragma unroll
+  for (int k = 1; k < RB / 64; ++k) t += sh[k];
+  return t;
 }
 
 // part[blockIdx] = sum over a fixed strided slice of op(x, y) (OP 0: x.y,
