@@ -1076,12 +1076,13 @@ void launch_side(const DevMesh<T>& M, const Params& P, const T* Qx, const T* coe
     hipLaunchKernelGGL((k_side<T, 4, 3, 1>), dim3(nblk(2 * (size_t)M.F, SIDE_SPB)), b, 0, s, M, P, Qx, coef, sv,
                        nfall);
   } else {
-    // quadrilateral faces: one lane per Gauss point
-    const dim3 g(nblk(2 * (size_t)M.F * 4, SIDE_THREADS));
+    // quadrilateral faces: one lane per side, its 4 Gauss points evaluated
+    // from the combined polynomials after the component loop
+    const dim3 g(nblk(2 * (size_t)M.F, SIDE_SPB));
     if (P.scheme == 1)
-      hipLaunchKernelGGL((k_side<T, 6, 4, 4>), g, b, 0, s, M, P, Qx, coef, sv, nfall);
+      hipLaunchKernelGGL((k_side<T, 6, 4, 1>), g, b, 0, s, M, P, Qx, coef, sv, nfall);
     else
-      hipLaunchKernelGGL((k_side<T, 8, 4, 4>), g, b, 0, s, M, P, Qx, coef, sv, nfall);
+      hipLaunchKernelGGL((k_side<T, 8, 4, 1>), g, b, 0, s, M, P, Qx, coef, sv, nfall);
   }
 }
 template <typename T>

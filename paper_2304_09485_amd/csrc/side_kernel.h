@@ -17,10 +17,10 @@
 constexpr int SIDE_SPB = 128;      // face sides per block
 constexpr int SIDE_THREADS = 128;  // threads per block
 
-// LPS lanes per side: 1 (each lane evaluates all NG Gauss points), or NG
-// (each lane one Gauss point; the projection and the weights are repeated
-// per lane, and the positivity decision is shared by the side's lanes
-// through a ballot).
+// LPS lanes per side: 1 (each lane evaluates all NG Gauss points; the form
+// launched for triangles and quadrilaterals), or NG (each lane one Gauss
+// point; the projection and the weights are repeated per lane, and the
+// positivity decision is shared by the side's lanes through a ballot).
 template <typename T, int NSUB, int NG, int LPS>
 __global__ void __launch_bounds__(128) k_side(DevMesh<T> M, Params P, const T* __restrict__ Qx,
                                               const T* __restrict__ coef, T* __restrict__ sv,
