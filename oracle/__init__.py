@@ -96,6 +96,14 @@ def _declare(L):
     L.orc_side_values.argtypes = [_vp, _vp, _vp, _i64, _i32, _vp]
     L.orc_side_values.restype = _i32
     L.orc_face_frame.argtypes = [_vp, _i64, _vp]
+    L.orc_side_debug.argtypes = [_vp, _vp, _vp, _i64, _i32, _vp]
+    L.orc_side_debug.restype = _i32
+    L.orc_right_eigenvectors.argtypes = [_d, _vp, _vp]
+    L.orc_ghost.argtypes = [_vp, _vp, _vp, _i64, _vp, _vp, _vp]
+    L.orc_ghost.restype = _i32
+    L.orc_cell_scales.argtypes = [_vp, _vp, _vp]
+    L.orc_boundary_right.argtypes = [_vp, _i64, _vp, _vp, _vp, _vp]
+    L.orc_boundary_right.restype = _i32
     L.orc_gks_point.argtypes = [_vp, _vp, _vp, _vp, _vp, _d, _vp, _vp]
     L.orc_kfvs_point.argtypes = [_vp, _vp, _vp, _vp, _vp]
     L.orc_colours.argtypes = [_vp, _vp]
@@ -146,6 +154,14 @@ def slope_solve(U, V, W, lam, K, rhs) -> np.ndarray:
     out = np.zeros(5)
     _load().orc_slope_solve(U, V, W, lam, K, _ptr(r), _ptr(out))
     return out
+
+
+def right_eigenvectors(gamma, q) -> np.ndarray:
+    """R* of the x-split Euler flux Jacobian at the local-frame state q."""
+    q = _f64(q)
+    R = np.zeros(25)
+    _load().orc_right_eigenvectors(gamma, _ptr(q), _ptr(R))
+    return R.reshape(5, 5)
 
 
 def euler_jn(gamma, Q, n, x) -> np.ndarray:
@@ -222,6 +238,49 @@ class Oracle:
         out = np.zeros((self.ng, 4, 5))
         fb = _load().orc_side_values(self.h, _ptr(Q), _ptr(G), int(f), int(side), _ptr(out))
         return out, int(fb)
+
+    def side_debug(self, Q, f, side, G=None):
+        """Per characteristic component of one face side: the cell average
+        q0, P0's coefficients a (9), the sub-stencil gradients b (8, 3), their
+        usable flags, beta (beta_0, beta_1..beta_8), tau_Z, the weights omega
+        (omega_0..omega_8) and M; plus R* and its inverse."""
+        Q = _f64(Q)
+        G = None if G is None else _f64(G)
+        d = np.zeros(370)
+        fb = _load().orc_side_debug(self.h, _ptr(Q), _ptr(G), int(f), int(side), _ptr(d))
+        comp = d[:320].reshape(5, 64)
+        out = {"q0": comp[:, 0].copy(), "a": comp[:, 1:10].copy(), "b": comp[:, 10:34].reshape(5, 8, 3).copy(),
+               "ok": comp[:, 34:42] > 0.5, "beta": comp[:, 42:51].copy(), "tau": comp[:, 51].copy(),
+               "w": comp[:, 52:61].copy(), "M": comp[:, 61].astype(int), "R": d[320:345].reshape(5, 5).copy(),
+               "L": d[345:370].reshape(5, 5).copy(), "fallback": int(fb)}
+        return out
+
+    def ghost(self, Q, f, G=None):
+        """(kind, average, gradient (15) or None, centroid) of the ghost cell of
+        boundary face f."""
+        Q = _f64(Q)
+        G = None if G is None else _f64(G)
+        q, g, c = np.zeros(5), np.zeros(15), np.zeros(3)
+        k = _load().orc_ghost(self.h, _ptr(Q), _ptr(G), int(f), _ptr(q), _ptr(g), _ptr(c))
+        if k < 0:
+            raise ValueError(f"face {f} is not a boundary face")
+        return k, q, (g if G is not None else None), c
+
+    def boundary_right(self, f, Wl, dWl):
+        """(kind, Wr, dWr (3, 5)): the right state and derivatives along
+        (n, t1, t2) of a boundary Gauss point, local frame."""
+        Wl, dWl = _f64(Wl), _f64(dWl)
+        Wr, dWr = np.zeros(5), np.zeros((3, 5))
+        k = _load().orc_boundary_right(self.h, int(f), _ptr(Wl), _ptr(dWl), _ptr(Wr), _ptr(dWr))
+        if k < 0:
+            raise ValueError(f"face {f} is not a boundary face")
+        return k, Wr, dWr
+
+    def cell_scales(self):
+        """(h, hdt): the scale of the cell's polynomial basis and its time-step length."""
+        h, hdt = np.zeros(self.N), np.zeros(self.N)
+        _load().orc_cell_scales(self.h, _ptr(h), _ptr(hdt))
+        return h, hdt
 
     def face_frame(self, f):
         out = np.zeros(9)

@@ -680,8 +680,13 @@ void fit_hweno(const orc_ctx& C, int i, const std::vector<int>& big,
 
 // Values and directional derivatives at the 3 Gauss points of face f on side
 // s, local frame.  Returns 1 if the positivity fallback (reading A24) was used.
+// If dbg is given, it receives per characteristic component c (64 doubles at
+// dbg + 64 c): the cell average, the 9 coefficients of P0, the 8 x 3
+// gradients of the P_m, their usable flags, beta_0 .. beta_8, tau_Z,
+// omega_0 .. omega_8 and M; then R* and its inverse (25 + 25 doubles at
+// dbg + 320).  Used by the tests that pin Sec. 3.4 and the projection.
 static int side_values(const orc_ctx& C, const double* Q, const double* G, int fidx, int side,
-                       double out[4][4][5]) {
+                       double out[4][4][5], double* dbg = nullptr) {
   const Face& f = C.faces[fidx];
   int i = side == 0 ? f.L : f.R;
   int j = side == 0 ? (f.R >= 0 ? f.R : C.N + (-f.R - 1)) : f.L;
@@ -754,6 +759,23 @@ static int side_values(const orc_ctx& C, const double* Q, const double* G, int f
         sum += wt[s + 1];
       }
       for (int k = 0; k <= nsub; ++k) w[k] = wt[k] / sum;
+      if (dbg) {
+        double* d = dbg + 64 * c;
+        d[42] = b0;
+        for (int s = 0; s < nsub; ++s) d[43 + s] = P[c].ok[s] ? bm[s] : 0.0;
+        d[51] = tz;
+      }
+    }
+    if (dbg) {
+      double* d = dbg + 64 * c;
+      d[0] = P[c].q0;
+      for (int k = 0; k < 9; ++k) d[1 + k] = P[c].a[k];
+      for (int s = 0; s < nsub; ++s) {
+        for (int k = 0; k < 3; ++k) d[10 + 3 * s + k] = P[c].ok[s] ? P[c].b[s][k] : 0.0;
+        d[34 + s] = P[c].ok[s] ? 1.0 : 0.0;
+      }
+      for (int k = 0; k <= nsub; ++k) d[52 + k] = w[k];
+      d[61] = M;
     }
     for (int g = 0; g < ng; ++g) {
       const V3& x = f.gp[g];
@@ -772,6 +794,12 @@ static int side_values(const orc_ctx& C, const double* Q, const double* G, int f
       qv[g][3][c] = dot(grd, f.t2);
     }
   }
+  if (dbg)
+    for (int r = 0; r < 5; ++r)
+      for (int c = 0; c < 5; ++c) {
+        dbg[320 + 5 * r + c] = Rs[r][c];
+        dbg[345 + 5 * r + c] = Ls[r][c];
+      }
   // back to conservative local-frame variables with R*
   for (int g = 0; g < ng; ++g)
     for (int d = 0; d < 4; ++d)
@@ -1829,6 +1857,67 @@ int32_t orc_side_values(const orc_ctx* C, const double* Q, const double* G, int6
   int r = side_values(*C, Q, G, (int)f, side, o);
   std::memcpy(out, o, sizeof(double) * 20 * C->faces[f].ng);
   return r;
+}
+// per-component polynomials, smoothness indicators and weights of one face
+// side, and R* with its inverse (layout at side_values)
+int32_t orc_side_debug(const orc_ctx* C, const double* Q, const double* G, int64_t f, int32_t side,
+                       double* dbg) {
+  std::vector<double> zero;
+  if (!G) {
+    zero.assign((size_t)15 * C->N, 0.0);
+    G = zero.data();
+  }
+  double o[4][4][5];
+  for (int k = 0; k < 370; ++k) dbg[k] = 0.0;
+  return side_values(*C, Q, G, (int)f, side, o, dbg);
+}
+// right eigenvectors of the x-split Euler flux Jacobian at a local-frame state
+// (columns u-c, u, u, u, u+c), row-major
+void orc_right_eigenvectors(double gamma, const double* q, double* R) {
+  V5 v{q[0], q[1], q[2], q[3], q[4]};
+  double r[5][5];
+  right_eigenvectors(v, gamma, r);
+  for (int a = 0; a < 5; ++a)
+    for (int b = 0; b < 5; ++b) R[5 * a + b] = r[a][b];
+}
+// ghost cell of boundary face f: its average (global frame), its gradient
+// (15, var-major) and its centroid, given the owner's state and gradients
+int32_t orc_ghost(const orc_ctx* C, const double* Q, const double* G, int64_t f, double* q, double* g,
+                  double* c) {
+  const Face& x = C->faces[f];
+  if (x.R >= 0) return -1;
+  int e = C->N + (-x.R - 1);
+  V5 s = state_of(*C, Q, e);
+  for (int k = 0; k < 5; ++k) q[k] = s[k];
+  if (G) grad_of(*C, G, e, g);
+  const V3& cc = C->c_of(e);
+  for (int d = 0; d < 3; ++d) c[d] = cc[d];
+  return x.kind;
+}
+// right state and derivatives (n, t1, t2) of a boundary Gauss point in the
+// local frame of boundary face f, given the left ones
+int32_t orc_boundary_right(const orc_ctx* C, int64_t f, const double* Wl, const double* dWl, double* Wr,
+                           double* dWr) {
+  const Face& x = C->faces[f];
+  if (x.R >= 0) return -1;
+  V5 l, r, dl[3], dr[3];
+  for (int k = 0; k < 5; ++k) {
+    l[k] = Wl[k];
+    for (int d = 0; d < 3; ++d) dl[d][k] = dWl[d * 5 + k];
+  }
+  boundary_right(*C, x, l, dl, r, dr);
+  for (int k = 0; k < 5; ++k) {
+    Wr[k] = r[k];
+    for (int d = 0; d < 3; ++d) dWr[d * 5 + k] = dr[d][k];
+  }
+  return x.kind;
+}
+// length scales: h of the scaled basis and the time-step length
+void orc_cell_scales(const orc_ctx* C, double* h, double* hdt) {
+  for (int i = 0; i < C->N; ++i) {
+    h[i] = C->hcell[i];
+    hdt[i] = C->hdt[i];
+  }
 }
 void orc_face_frame(const orc_ctx* C, int64_t f, double* out) {
   const Face& x = C->faces[f];

@@ -358,3 +358,60 @@ def test_kfvs_free_stream_preserved(oracle_lib):
     q = I.cons(prim[0], prim[1:4], prim[4])
     Q = np.repeat(q[:, None], o.N, axis=1)
     assert np.abs(o.residual(Q)).max() < 1e-14
+
+
+@pytest.mark.parametrize("seed", range(2))
+def test_discontinuous_flux_with_slopes_vs_quadrature(orc, seed):
+    """Different left and right states, each with its own slopes in the three
+    local directions: the time average of Eq. (flux) with every velocity
+    moment taken by quadrature and the time integral by a Gauss rule in t.
+    The slopes a^{l,r} solve <a psi> = dW / rho, the equilibrium slopes come
+    from the kinetic-weighted derivative of Q0 (both half spaces, reading A6),
+    and A^{l,r}, A-bar from the compatibility condition <a.u + A> = 0, all by
+    quadrature."""
+    rng = np.random.default_rng(40 + seed)
+    Wl = I.cons(rng.uniform(0.8, 1.3), rng.uniform(-0.5, 0.5, 3), rng.uniform(0.6, 1.1))
+    Wr = I.cons(rng.uniform(0.6, 1.1), rng.uniform(-0.5, 0.5, 3), rng.uniform(0.5, 1.0))
+    dWl = rng.normal(scale=0.3, size=(3, 5))
+    dWr = rng.normal(scale=0.3, size=(3, 5))
+    dt = 0.015
+    eps_t, C_t = 0.1, 1.0
+    o = orc(tau_eps=eps_t, tau_C=C_t)
+    got = o.gks_point(Wl, dWl, Wr, dWr, dt)
+
+    def side(W, dW, half):
+        rho, U, p, lam = lam_of(W)
+        M = I.maxwellian_moment_matrix(*U, lam)
+        full = VQuad(*U, lam)
+        a = [np.linalg.solve(M, dW[d] / rho) for d in range(3)]
+        A = np.linalg.solve(M, -full.E(sum(full.poly(a[d]) * [full.u, full.v, full.w][d] for d in range(3))))
+        return rho, p, a, A, VQuad(*U, lam, half)
+
+    rl, pl, al, Al, hl = side(Wl, dWl, +1)
+    rr, pr, ar, Ar, hr = side(Wr, dWr, -1)
+    Q0 = rl * hl.E(1.0) + rr * hr.E(1.0)
+    r0, U0, p0 = I.prim(Q0)
+    lam0 = r0 / (2 * p0)
+    M0 = I.maxwellian_moment_matrix(*U0, lam0)
+    q0 = VQuad(*U0, lam0)
+    ab = [np.linalg.solve(M0, (rl * hl.E(hl.poly(al[d])) + rr * hr.E(hr.poly(ar[d]))) / r0) for d in range(3)]
+    vel0 = [q0.u, q0.v, q0.w]
+    abu = sum(q0.poly(ab[d]) * vel0[d] for d in range(3))
+    Ab = np.linalg.solve(M0, -q0.E(abu))
+    alu = sum(hl.poly(al[d]) * [hl.u, hl.v, hl.w][d] for d in range(3))
+    aru = sum(hr.poly(ar[d]) * [hr.u, hr.v, hr.w][d] for d in range(3))
+    # the velocity moments of u psi times each term of Eq. (flux)
+    E_g0, E_g0a, E_g0A = q0.E(q0.u), q0.E(q0.u * abu), q0.E(q0.u * q0.poly(Ab))
+    E_l, E_la, E_lA = hl.E(hl.u), hl.E(hl.u * alu), hl.E(hl.u * hl.poly(Al))
+    E_r, E_ra, E_rA = hr.E(hr.u), hr.E(hr.u * aru), hr.E(hr.u * hr.poly(Ar))
+    tau = (eps_t + C_t * abs(pl - pr) / (pl + pr)) * dt
+    tg, wg = np.polynomial.legendre.leggauss(60)
+    ref = np.zeros(5)
+    for t, w in zip(0.5 * dt * (tg + 1), 0.5 * dt * wg):
+        e = np.exp(-t / tau)
+        f = r0 * ((1 - e) * E_g0 + ((t + tau) * e - tau) * E_g0a + (t - tau + tau * e) * E_g0A)
+        f += e * rl * (E_l - (t + tau) * E_la - tau * E_lA)
+        f += e * rr * (E_r - (t + tau) * E_ra - tau * E_rA)
+        ref += w * f
+    ref /= dt
+    np.testing.assert_allclose(got, ref, rtol=1e-9, atol=1e-11)
