@@ -203,6 +203,23 @@ hgks_status hgks_restore(hgks_ctx* ctx, const char* path);
 hgks_status hgks_residual_dev(hgks_ctx* ctx, const void* Q_dev, void* R_dev, void* stream);
 hgks_status hgks_jv_dev(hgks_ctx* ctx, const void* v_dev, double sigma, void* Av_dev, void* stream);
 
+/* Allocation-free twin of hgks_residual_dev, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same arguments and the same kernels and
+ * results (bitwise) as hgks_residual_dev, but the residual's work space
+ * (extended state, time steps, reconstruction coefficients, side values,
+ * face fluxes) lives in one static 64 MiB device buffer per GPU instead of the
+ * context, so the call allocates nothing; the buffer's device address is
+ * looked up on the first call on a device.  Meshes whose work space exceeds
+ * the buffer (hgks_residual_static_bytes; about 3 KB per tetrahedron, so up
+ * to roughly 22,000 tetrahedra) give HGKS_EINVAL before anything is queued.
+ * All calls on one GPU share the buffer and it keeps the last call's
+ * contents: calls that overlap on one GPU (concurrent streams or threads)
+ * race and must be serialised by the caller. */
+hgks_status hgks_residual_dev_static(hgks_ctx* ctx, const void* Q_dev, void* R_dev, void* stream);
+/* Work-space bytes hgks_residual_dev_static needs for the loaded mesh (0 if none). */
+size_t hgks_residual_static_bytes(const hgks_ctx* ctx);
+
 /* Number of cells / faces of the loaded mesh. */
 int64_t hgks_n_cells(const hgks_ctx* ctx);
 int64_t hgks_n_faces(const hgks_ctx* ctx);

@@ -994,6 +994,67 @@ hgks_status hgks_residual_dev(hgks_ctx* ctx, const void* Q_dev, void* R_dev, voi
   return HGKS_OK;
 }
 
+// Bytes of the residual work space of a mesh (extended state, time steps,
+// reconstruction coefficients, side values, face fluxes and face point
+// values), each part starting on a 256-byte boundary; offsets in off[6].
+static size_t residual_work_layout(const hgks_ctx* ctx, size_t off[6]) {
+  const HostMesh& H = ctx->H;
+  const size_t N = H.N, F = H.F, NX = H.N + H.Nb;
+  const bool ho = ctx->o.scheme != HGKS_KFVS1;
+  const size_t nsub = H.nf == 4 ? 4 : (ctx->o.scheme == HGKS_HWENO ? 6 : 8);
+  const size_t len[6] = {5 * NX, N, ho ? 5 * (9 + 3 * nsub) * N : 0, ho ? (size_t)20 * H.ng * 2 * F : 0, 5 * F, 5 * F};
+  size_t at = 0;
+  for (int k = 0; k < 6; ++k) {
+    off[k] = at;
+    at += (len[k] * sizeof(double) + 255) / 256 * 256;
+  }
+  return at;
+}
+
+hgks_status hgks_residual_dev_static(hgks_ctx* ctx, const void* Q_dev, void* R_dev, void* stream) {
+  TRY(require(ctx, false));
+  if (!Q_dev || !R_dev) return HGKS_EINVAL;
+  size_t off[6];
+  const size_t need = residual_work_layout(ctx, off);
+  if (need > STATIC_SCRATCH_BYTES) {
+    ctx->err = "mesh needs " + std::to_string(need) + " bytes of residual work space, more than the " +
+               std::to_string(STATIC_SCRATCH_BYTES) + " bytes of the static device buffer";
+    return HGKS_EINVAL;
+  }
+  void* base = nullptr;
+  HIPCHK(static_scratch_ptr(&base));
+  hipStream_t s = stream ? (hipStream_t)stream : ctx->stream;
+  TRY(sync_kinds(ctx));
+  // every part of the work space is written before it is read: nothing to clear
+  unsigned char* b = (unsigned char*)base;
+  const bool ho = ctx->o.scheme != HGKS_KFVS1;
+  Work<double> w;
+  w.Qx = (double*)(b + off[0]);
+  w.dt = (double*)(b + off[1]);
+  w.coef = ho ? (double*)(b + off[2]) : nullptr;
+  w.sv = ho ? (double*)(b + off[3]) : nullptr;
+  w.ff = (double*)(b + off[4]);
+  w.fq = (double*)(b + off[5]);
+  w.Gx = ctx->W64.Gx;  // the context's frozen gradients (compact scheme), read only
+  launch_perturb<double>((const double*)Q_dev, nullptr, nullptr, ctx->H.N, ctx->H.N + ctx->H.Nb, w.Qx, s);
+  launch_ghost<double>(ctx->M, ctx->P, w.Qx, (double*)nullptr, s);
+  launch_dt<double>(ctx->M, ctx->P, ctx->cfl_now, w.Qx, w.dt, s);
+  residual_pipeline<double, double>(ctx, ctx->M, w, w.Qx, w.dt, 0, (double*)R_dev, (const double*)nullptr,
+                                    (const double*)nullptr, (const double*)nullptr, (double*)nullptr, s);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) {
+    ctx->err = hipGetErrorString(e);
+    return HGKS_EDEVICE;
+  }
+  return HGKS_OK;
+}
+
+size_t hgks_residual_static_bytes(const hgks_ctx* ctx) {
+  if (!ctx || !ctx->mesh) return 0;
+  size_t off[6];
+  return residual_work_layout(ctx, off);
+}
+
 hgks_status hgks_jv_dev(hgks_ctx* ctx, const void* v_dev, double sigma, void* Av_dev, void* stream) {
   TRY(require(ctx, true));
   if (!v_dev || !Av_dev) return HGKS_EINVAL;

@@ -66,4 +66,10 @@ void launch_sigma(const double* vpart, const double* qq, double n, double eps, d
 
 constexpr int REDUCE_PARTS = 1024;  // partials of a reduction
 
+// Device work space of the allocation-free residual (64 MiB per GPU); its
+// device address on the current device (looked up on first use per device)
+constexpr size_t STATIC_SCRATCH_BYTES = size_t(64) << 20;
+constexpr int MAX_DEVICES = 64;
+hipError_t static_scratch_ptr(void** out);
+
 }  // namespace hgks

@@ -14,6 +14,8 @@
 //            deterministic), with the Jv / gradient-update epilogues fused
 #include "hgks_kernels.h"
 
+#include <mutex>
+
 #include "gks_flux.h"
 #include "hgks_device.h"
 
@@ -1243,6 +1245,31 @@ void launch_convert(const double* src, float* dst, size_t n, hipStream_t s) {
 void launch_sigma(const double* vpart, const double* qq, double n, double eps, double fixed, double* sigma,
                   hipStream_t s) {
   hipLaunchKernelGGL(k_sigma, dim3(1), dim3(RB), 0, s, vpart, qq, n, eps, fixed, sigma);
+}
+
+// Work space of the allocation-free residual entry point: one copy per GPU,
+// held until the process ends.  Host code never passes the array's name to a
+// kernel or a copy: on the host it is a stand-in, not a device address.  The
+// device address is looked up once per device (with that device current) and
+// cached.
+static __device__ __align__(256) unsigned char scratch[STATIC_SCRATCH_BYTES];
+
+hipError_t static_scratch_ptr(void** out) {
+  static std::mutex mu;
+  static void* ptrs[MAX_DEVICES] = {};
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= MAX_DEVICES) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!ptrs[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    ptrs[dev] = p;
+  }
+  *out = ptrs[dev];
+  return hipSuccess;
 }
 
 #define HGKS_INST(T)                                                                                              \

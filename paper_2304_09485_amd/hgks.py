@@ -28,7 +28,8 @@ STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EMESH", -4: "ESTATE", -5: "E
 # exported symbols declared in include/hgks.h
 SYMBOLS = ["hgks_default_options", "hgks_create", "hgks_load_mesh", "hgks_load_hex_mesh", "hgks_set_freestream", "hgks_set_bc",
            "hgks_set_state", "hgks_get_state", "hgks_residual", "hgks_time_step", "hgks_jv", "hgks_precond",
-           "hgks_implicit_step", "hgks_solve_steady", "hgks_residual_dev", "hgks_jv_dev", "hgks_n_cells",
+           "hgks_implicit_step", "hgks_solve_steady", "hgks_residual_dev", "hgks_residual_dev_static",
+           "hgks_residual_static_bytes", "hgks_jv_dev", "hgks_n_cells",
            "hgks_n_faces", "hgks_kernel_times", "hgks_last_error", "hgks_destroy", "hgks_estimate_bytes",
            "hgks_checkpoint", "hgks_restore",
            "hgks_server_create", "hgks_server_submit", "hgks_server_poll", "hgks_server_wait",
@@ -121,6 +122,8 @@ def load_library():
         "hgks_implicit_step": (i32, [vp, ctypes.POINTER(StepInfo)]),
         "hgks_solve_steady": (i32, [vp, d, i32, ctypes.POINTER(SolveInfo)]),
         "hgks_residual_dev": (i32, [vp, vp, vp, vp]),
+        "hgks_residual_dev_static": (i32, [vp, vp, vp, vp]),
+        "hgks_residual_static_bytes": (ctypes.c_size_t, [vp]),
         "hgks_jv_dev": (i32, [vp, vp, d, vp, vp]),
         "hgks_n_cells": (i64, [vp]),
         "hgks_n_faces": (i64, [vp]),
@@ -262,6 +265,15 @@ class Solver:
     def residual_dev(self, Q, R, stream=None):
         self._check(self._L.hgks_residual_dev(self.h, ctypes.c_void_p(Q.data_ptr()), ctypes.c_void_p(R.data_ptr()),
                                               ctypes.c_void_p(stream)))
+
+    def residual_dev_static(self, Q, R, stream=None):
+        """hgks_residual_dev with the work space in the library's static device
+        buffer (no allocation in the call)."""
+        self._check(self._L.hgks_residual_dev_static(self.h, ctypes.c_void_p(Q.data_ptr()),
+                                                     ctypes.c_void_p(R.data_ptr()), ctypes.c_void_p(stream)))
+
+    def residual_static_bytes(self):
+        return int(self._L.hgks_residual_static_bytes(self.h))
 
     def jv_dev(self, v, Av, sigma=0.0, stream=None):
         self._check(self._L.hgks_jv_dev(self.h, ctypes.c_void_p(v.data_ptr()), float(sigma),
