@@ -62,6 +62,7 @@ enum { HGKS_JV_FD = 0, HGKS_JV_APPROX = 1 };
  * cells (the LUSGS-WENO solver the paper compares with, Sec. 5); one residual
  * evaluation per step, jv_mode / precision / krylov options unused */
 enum { HGKS_SOLVER_GMRES = 0, HGKS_SOLVER_LUSGS = 1 };
+enum { HGKS_SUBS_FACES = 0, HGKS_SUBS_HEX_WENO = 1 };
 enum { HGKS_FARFIELD = 0, HGKS_SLIP_WALL = 1, HGKS_NOSLIP_ADIABATIC = 2,
        HGKS_SUP_IN = 3, HGKS_SUP_OUT = 4 };          /* Sec. 5 boundary conditions */
 
@@ -75,7 +76,12 @@ typedef struct {
   int32_t jacobi_sweeps; /* 2, Sec. 5 */
   int32_t jv_mode;       /* GMRES operator: HGKS_JV_FD (default) or HGKS_JV_APPROX */
   int32_t solver;        /* HGKS_SOLVER_GMRES (default) | HGKS_SOLVER_LUSGS */
-  int32_t reserved;      /* 0 */
+  int32_t compact_subs;  /* sub-stencils of the compact scheme (Sec. 3.1): HGKS_SUBS_FACES
+                            (default) the faces' {i, i_f}, fitted with the cell gradients;
+                            HGKS_SUBS_HEX_WENO (hexahedral meshes only) the eight non-compact
+                            sub-stencils {i, i_1 or i_6, two consecutive lateral neighbours},
+                            fitted from the cell averages alone, as the hexahedral sphere
+                            cases of Sec. 5 choose them */
   double gamma;          /* 1.4 */
   double cfl;            /* 10 */
   double tau_eps;        /* 0.1, inviscid collision time, Sec. 5 */
@@ -92,6 +98,19 @@ typedef struct {
                             throughout, as in the paper */
   double cfl_growth;     /* default 1.5 */
   void* stream;          /* hipStream_t to run on; NULL = library-owned stream */
+  /* Device allocator hook: every device buffer of a context (mesh data,
+   * state, work space, Krylov basis), and so of every served request, comes
+   * from dev_alloc(bytes, alloc_user) and goes back through
+   * dev_free(ptr, alloc_user) in hgks_destroy, after the context's stream has
+   * drained.  dev_alloc returns device memory of the current device, at least
+   * 256-byte aligned, or NULL (HGKS_ENOMEM; a misaligned block is handed back
+   * and refused the same way).  Both NULL (the default) = hipMalloc / hipFree;
+   * setting only one is HGKS_EINVAL.  The Python binding passes PyTorch's
+   * caching allocator here.  The hook may be called from the server's
+   * worker threads. */
+  void* (*dev_alloc)(size_t bytes, void* alloc_user);
+  void (*dev_free)(void* ptr, void* alloc_user);
+  void* alloc_user;
 } hgks_options;
 
 typedef struct {
@@ -188,13 +207,18 @@ hgks_status hgks_implicit_step(hgks_ctx* ctx, hgks_step_info* info);
 hgks_status hgks_solve_steady(hgks_ctx* ctx, double drop, int32_t max_steps, hgks_solve_info* info);
 
 /* Checkpoint / resume of a steady solve.  hgks_checkpoint writes the state,
- * the cell-averaged gradients (compact scheme) and the reference residual of
- * res_rel to path (written under path.tmp, then renamed over path), with a
- * 64-bit FNV-1a hash of the content.  hgks_restore reads such a file into a
- * context with the same mesh and scheme loaded; a file for another mesh or
- * scheme, a truncated or corrupted file gives HGKS_EINVAL and leaves the
- * context's state unchanged.  The file is host-endian and not portable across
- * byte orders. */
+ * the cell-averaged gradients (compact scheme), the reference residual of
+ * res_rel and the CFL number of the next step (the ramp of
+ * hgks_solve_steady) to path (written under path.tmp, then renamed over
+ * path), with a 64-bit FNV-1a hash of the content.  hgks_restore reads such a
+ * file into a context with the same mesh and scheme loaded; the next
+ * hgks_solve_steady then continues the interrupted solve: it keeps the
+ * restored reference residual and CFL number instead of starting a new ramp
+ * and measuring the drop from the resume point (hgks_set_state cancels
+ * this).  A file for another mesh or scheme, of another format version, a
+ * truncated or corrupted file gives HGKS_EINVAL and leaves the context's
+ * state unchanged.  The file is host-endian and not portable across byte
+ * orders. */
 hgks_status hgks_checkpoint(hgks_ctx* ctx, const char* path);
 hgks_status hgks_restore(hgks_ctx* ctx, const char* path);
 

@@ -55,7 +55,7 @@ class Options(ctypes.Structure):
                 ("tau_eps", ctypes.c_double), ("tau_C", ctypes.c_double), ("gamma_lin", ctypes.c_double),
                 ("weno_eps", ctypes.c_double), ("mu", ctypes.c_double), ("prandtl", ctypes.c_double),
                 ("fd_sigma", ctypes.c_double), ("cfl_flux", ctypes.c_double), ("jv_mode", ctypes.c_int32),
-                ("first_order", ctypes.c_int32), ("solver", ctypes.c_int32), ("pad", ctypes.c_int32)]
+                ("first_order", ctypes.c_int32), ("solver", ctypes.c_int32), ("compact_subs", ctypes.c_int32)]
 
 
 class StepInfo(ctypes.Structure):
@@ -102,6 +102,10 @@ def _declare(L):
     L.orc_ghost.argtypes = [_vp, _vp, _vp, _i64, _vp, _vp, _vp]
     L.orc_ghost.restype = _i32
     L.orc_cell_scales.argtypes = [_vp, _vp, _vp]
+    L.orc_residual_cells.argtypes = [_vp, _vp, _vp, _vp, _i64, _vp, _vp, _vp]
+    L.orc_residual_cells.restype = _i64
+    L.orc_face_fluxes.argtypes = [_vp, _vp, _vp, _vp, _i64, _vp, _vp]
+    L.orc_face_fluxes.restype = _i64
     L.orc_boundary_right.argtypes = [_vp, _i64, _vp, _vp, _vp, _vp]
     L.orc_boundary_right.restype = _i32
     L.orc_gks_point.argtypes = [_vp, _vp, _vp, _vp, _vp, _d, _vp, _vp]
@@ -135,7 +139,8 @@ def _f64(a):
 def default_options(**kw) -> Options:
     o = Options(scheme=WENO, physics=EULER, weights=0, krylov_dim=10, restarts=3, jacobi_sweeps=2,
                 gamma=1.4, cfl=10.0, tau_eps=0.1, tau_C=1.0, gamma_lin=0.025, weno_eps=1e-8,
-                mu=0.0, prandtl=1.0, fd_sigma=0.0, cfl_flux=1.0, jv_mode=0, first_order=0, solver=0)
+                mu=0.0, prandtl=1.0, fd_sigma=0.0, cfl_flux=1.0, jv_mode=0, first_order=0, solver=0,
+                compact_subs=0)
     for k, v in kw.items():
         setattr(o, k, v)
     return o
@@ -231,6 +236,28 @@ class Oracle:
         Gn = np.zeros((15, self.N)) if want_grad else None
         fb = _load().orc_residual(self.h, _ptr(Q), _ptr(G), _ptr(dt), _ptr(R), _ptr(Gn))
         return (R, Gn, int(fb)) if want_grad else R
+
+    def residual_cells(self, Q, cells, G=None, dt=None, want_grad=False):
+        """The residual (and compact gradient update) of the listed cells only:
+        R [5][len(cells)] (Gnew [15][len(cells)]), from the faces of those cells."""
+        Q = _f64(Q)
+        G = None if G is None else _f64(G)
+        dt = None if dt is None else _f64(dt)
+        cells = np.ascontiguousarray(cells, dtype=np.int64)
+        R = np.zeros((5, len(cells)))
+        Gn = np.zeros((15, len(cells))) if want_grad else None
+        _load().orc_residual_cells(self.h, _ptr(Q), _ptr(G), _ptr(dt), len(cells), _ptr(cells), _ptr(R), _ptr(Gn))
+        return (R, Gn) if want_grad else R
+
+    def face_fluxes(self, Q, faces, G=None, dt=None):
+        """Integrated fluxes [5][len(faces)] of the listed faces (oriented L -> R)."""
+        Q = _f64(Q)
+        G = None if G is None else _f64(G)
+        dt = None if dt is None else _f64(dt)
+        faces = np.ascontiguousarray(faces, dtype=np.int64)
+        F = np.zeros((5, len(faces)))
+        _load().orc_face_fluxes(self.h, _ptr(Q), _ptr(G), _ptr(dt), len(faces), _ptr(faces), _ptr(F))
+        return F
 
     def side_values(self, Q, f, side, G=None):
         Q = _f64(Q)

@@ -550,6 +550,9 @@ double beta_lin(const orc_ctx& C, int i, const double b[3]) {
   return std::pow(vol, 2.0 / 3.0 - 1.0) * vol * (b[0] * b[0] + b[1] * b[1] + b[2] * b[2]);
 }
 
+void fit_subs(const orc_ctx& C, int i, const std::vector<int>& big, const std::vector<std::vector<int>>& subs,
+              const std::vector<V5>& qs, Poly P[5]);
+
 // Non-compact WENO fits (Sec. 3.2): q[e] are projected averages keyed by
 // position in the big stencil list.
 void fit_weno(const orc_ctx& C, int i, const std::vector<int>& big,
@@ -577,6 +580,15 @@ void fit_weno(const orc_ctx& C, int i, const std::vector<int>& big,
       for (int k = 0; k < 3; ++k) P[c].a[k] = X[k * 5 + c];
     }
   }
+  fit_subs(C, i, big, subs, qs, P);
+}
+
+// Linear P_m of Sec. 3.2 on each sub-stencil by least squares on the cell
+// averages of its members (positions looked up in the big stencil list);
+// rank-deficient sub-stencils are marked unusable (reading A17).
+void fit_subs(const orc_ctx& C, int i, const std::vector<int>& big, const std::vector<std::vector<int>>& subs,
+              const std::vector<V5>& qs, Poly P[5]) {
+  std::vector<double> X;
   for (int s = 0; s < (int)subs.size(); ++s) {
     const std::vector<int>& st = subs[s];
     int ms = (int)st.size() - 1;
@@ -727,11 +739,15 @@ static int side_values(const orc_ctx& C, const double* Q, const double* G, int f
       }
     }
     fit_hweno(C, i, cbig, qs, gs, P);
+    // hexahedra, compact sub-stencil option 1: P0 stays the compact fit, the
+    // P_m are the averages-only fits on the eight S^WENO sub-stencils, whose
+    // members are all face neighbours (Sec. 3.1; the sphere cases of Sec. 5)
+    if (C.o.compact_subs == 1 && C.nf == 6) fit_subs(C, i, cbig, C.sub[i], qs, P);
   } else {
     fit_weno(C, i, big, C.sub[i], qs, P);
   }
   // weights and point values per characteristic component (Eq. (weno))
-  const int nsub = compact ? C.nf : (int)C.sub[i].size();
+  const int nsub = compact && !(C.o.compact_subs == 1 && C.nf == 6) ? C.nf : (int)C.sub[i].size();
   const int ng = f.ng;
   double qv[4][4][5];
   for (int c = 0; c < 5; ++c) {
@@ -1857,6 +1873,66 @@ int32_t orc_side_values(const orc_ctx* C, const double* Q, const double* G, int6
   int r = side_values(*C, Q, G, (int)f, side, o);
   std::memcpy(out, o, sizeof(double) * 20 * C->faces[f].ng);
   return r;
+}
+// Residual (and compact gradient update) of the listed cells only: the same
+// face sums as the full residual, evaluated for the faces of those cells (a
+// face shared by two listed cells is evaluated twice).  R [5][n], Gnew
+// [15][n] (may be NULL).  dt NULL: the local time steps of Q.
+int64_t orc_residual_cells(const orc_ctx* C, const double* Q, const double* G, const double* dt, int64_t n,
+                           const int64_t* cells, double* R, double* Gnew) {
+  std::vector<double> d, zero;
+  if (!dt) {
+    d.resize(C->N);
+    compute_dt(*C, Q, d.data());
+    dt = d.data();
+  }
+  if (!G) {
+    zero.assign((size_t)15 * C->N, 0.0);
+    G = zero.data();
+  }
+  int64_t fb = 0;
+#pragma omp parallel for schedule(dynamic, 16) reduction(+ : fb) num_threads(nthreads_req)
+  for (int64_t k = 0; k < n; ++k) {
+    const int i = (int)cells[k];
+    for (int v = 0; v < 5; ++v) R[(size_t)v * n + k] = 0.0;
+    if (Gnew)
+      for (int q = 0; q < 15; ++q) Gnew[(size_t)q * n + k] = 0.0;
+    for (int p = 0; p < C->nf; ++p) {
+      int fi = C->cf[i][p];
+      const Face& f = C->faces[fi];
+      V5 Ff, Qf;
+      fb += face_flux(*C, Q, G, dt, fi, Ff, Gnew ? &Qf : nullptr);
+      double sg = f.L == i ? 1.0 : -1.0;
+      for (int v = 0; v < 5; ++v) R[(size_t)v * n + k] -= sg * Ff[v];
+      if (Gnew)
+        for (int v = 0; v < 5; ++v)
+          for (int dd = 0; dd < 3; ++dd) Gnew[(size_t)(v * 3 + dd) * n + k] += sg * Qf[v] * f.n[dd] / C->vol[i];
+    }
+  }
+  return fb;
+}
+// Integrated face fluxes (global frame, oriented L -> R) of the listed
+// faces: F [5][n].  dt NULL: the local time steps of Q.
+int64_t orc_face_fluxes(const orc_ctx* C, const double* Q, const double* G, const double* dt, int64_t n,
+                        const int64_t* faces, double* Fout) {
+  std::vector<double> d, zero;
+  if (!dt) {
+    d.resize(C->N);
+    compute_dt(*C, Q, d.data());
+    dt = d.data();
+  }
+  if (!G) {
+    zero.assign((size_t)15 * C->N, 0.0);
+    G = zero.data();
+  }
+  int64_t fb = 0;
+#pragma omp parallel for schedule(dynamic, 64) reduction(+ : fb) num_threads(nthreads_req)
+  for (int64_t k = 0; k < n; ++k) {
+    V5 Ff;
+    fb += face_flux(*C, Q, G, dt, (int)faces[k], Ff, nullptr);
+    for (int v = 0; v < 5; ++v) Fout[(size_t)v * n + k] = Ff[v];
+  }
+  return fb;
 }
 // per-component polynomials, smoothness indicators and weights of one face
 // side, and R* with its inverse (layout at side_values)

@@ -44,7 +44,11 @@ typedef struct {
                             supersonic sphere retested with a first-order flux) */
   int32_t solver;        /* implicit step: 0 GMRES, 1 LU-SGS of the approximate matrix (the
                             LUSGS-WENO comparison solver of Sec. 5) */
-  int32_t pad;
+  int32_t compact_subs;   /* sub-stencils of the compact scheme: 0 the faces' {i, i_f} (Sec. 3.1,
+                            gradient-dominated), 1 on hexahedra the eight S^WENO sub-stencils
+                            {i, i_1 or i_6, two consecutive lateral neighbours}, fitted from the
+                            cell averages (the hexahedral compact choice of the sphere cases of
+                            Sec. 5) */
 } orc_options;
 
 /* boundary kinds */

@@ -22,23 +22,47 @@ using namespace hgks;
 
 namespace {
 
+// Device buffers of a context: from the caller's allocator hook if one is
+// given (e.g. PyTorch's caching allocator), else hipMalloc; all released in
+// hgks_destroy.
 struct DevAlloc {
   std::vector<void*> ptrs;
   hipError_t last = hipSuccess;
+  void* (*ualloc)(size_t, void*) = nullptr;
+  void (*ufree)(void*, void*) = nullptr;
+  void* user = nullptr;
   template <typename T>
   T* get(size_t n) {
     void* p = nullptr;
     if (n == 0) n = 1;
-    hipError_t e = hipMalloc(&p, n * sizeof(T));
-    if (e != hipSuccess) {
-      last = e;
-      return nullptr;
+    const size_t bytes = n * sizeof(T);
+    if (ualloc) {
+      p = ualloc(bytes, user);
+      if (p && ((uintptr_t)p & 255u) != 0) {  // kernels assume 256-byte aligned buffers
+        ufree(p, user);
+        p = nullptr;
+      }
+      if (!p) {
+        last = hipErrorOutOfMemory;
+        return nullptr;
+      }
+    } else {
+      hipError_t e = hipMalloc(&p, bytes);
+      if (e != hipSuccess) {
+        last = e;
+        return nullptr;
+      }
     }
     ptrs.push_back(p);
     return (T*)p;
   }
   void free_all() {
-    for (void* p : ptrs) (void)hipFree(p);
+    for (void* p : ptrs) {
+      if (ufree)
+        ufree(p, user);
+      else
+        (void)hipFree(p);
+    }
     ptrs.clear();
   }
 };
@@ -99,6 +123,7 @@ struct hgks_ctx {
   std::vector<int> cstart;  // LU-SGS colour classes: offsets into M.cord
   double res0 = -1.0;
   double cfl_now = 10.0;  // CFL of the local time steps (o.cfl, or the ramp of solve_steady)
+  bool resumed = false;   // restored from a checkpoint: solve_steady keeps res0 and the CFL ramp
   // timing of the residual kernels: a pool of event sextets recorded on the
   // stream, drained (one synchronisation) when full or when read
   bool prof = false;
@@ -162,6 +187,7 @@ void set_params(hgks_ctx* ctx) {
   P.physics = o.physics;
   P.weights = o.weights;
   P.scheme = o.scheme;
+  P.csubs = o.scheme == HGKS_HWENO && o.compact_subs == HGKS_SUBS_HEX_WENO ? 1 : 0;
 }
 
 template <typename T>
@@ -200,7 +226,10 @@ hgks_status upload_mesh_fp(hgks_ctx* ctx, DevMesh<T>& M) {
   if (H.ng == 4) TRY(upload_conv(ctx, H.fw, M.fw));
   if (ctx->o.scheme == HGKS_HWENO) {
     TRY(upload_conv(ctx, H.opH, M.opH));
-    TRY(upload_conv(ctx, H.hsub, M.hsub));
+    if (ctx->P.csubs)
+      TRY(upload_conv(ctx, H.opB, M.opB));  // the eight non-compact hexahedral sub-stencils
+    else
+      TRY(upload_conv(ctx, H.hsub, M.hsub));
   } else if (ctx->o.scheme == HGKS_WENO) {
     TRY(upload_conv(ctx, H.opA, M.opA));
     TRY(upload_conv(ctx, H.opB, M.opB));
@@ -217,7 +246,7 @@ hgks_status alloc_work(hgks_ctx* ctx, Work<T>& w) {
   const bool ho = ctx->o.scheme != HGKS_KFVS1;
   // 9 + 3 M coefficient vectors per cell (M sub-stencils: 4 on a tetrahedron,
   // 8 non-compact or 6 compact on a hexahedron); 20 values per Gauss point
-  const size_t nsub = H.nf == 4 ? 4 : (ctx->o.scheme == HGKS_HWENO ? 6 : 8);
+  const size_t nsub = H.nf == 4 ? 4 : (ctx->o.scheme == HGKS_HWENO && !ctx->P.csubs ? 6 : 8);
   w.coef = ho ? ctx->A.get<T>(5 * (9 + 3 * nsub) * N) : nullptr;
   w.sv = ho ? ctx->A.get<T>((size_t)20 * H.ng * 2 * F) : nullptr;
   w.ff = ctx->A.get<T>(5 * F);
@@ -460,14 +489,18 @@ hgks_status hgks_create(const hgks_options* opts, hgks_ctx** out) {
   if (opts->krylov_dim < 1 || opts->krylov_dim > MAXM || opts->restarts < 1 || opts->jacobi_sweeps < 0 ||
       !(opts->gamma > 1.0) || !(opts->cfl > 0.0) || opts->scheme < 0 || opts->scheme > 2 || opts->physics < 0 ||
       opts->physics > 1 || opts->precision < 0 || opts->precision > 1 || opts->jv_mode < 0 || opts->jv_mode > 1 ||
-      opts->solver < HGKS_SOLVER_GMRES || opts->solver > HGKS_SOLVER_LUSGS ||
+      opts->solver < HGKS_SOLVER_GMRES || opts->solver > HGKS_SOLVER_LUSGS || opts->compact_subs < 0 ||
+      opts->compact_subs > HGKS_SUBS_HEX_WENO ||
       (opts->physics == HGKS_NS && !(opts->mu > 0.0 && opts->prandtl > 0.0)) ||
-      (opts->physics == HGKS_NS && opts->scheme == HGKS_KFVS1))
+      (opts->physics == HGKS_NS && opts->scheme == HGKS_KFVS1) || (!opts->dev_alloc != !opts->dev_free))
     return HGKS_EINVAL;
   hgks_ctx* ctx = new (std::nothrow) hgks_ctx;
   if (!ctx) return HGKS_ENOMEM;
   ctx->o = *opts;
   ctx->cfl_now = opts->cfl;
+  ctx->A.ualloc = opts->dev_alloc;
+  ctx->A.ufree = opts->dev_free;
+  ctx->A.user = opts->alloc_user;
   for (int k = 0; k < 256; ++k) ctx->kind_of_tag[k] = HGKS_FARFIELD;
   if (opts->stream) {
     ctx->stream = (hipStream_t)opts->stream;
@@ -496,6 +529,10 @@ hgks_status hgks_load_mesh(hgks_ctx* ctx, int64_t n_nodes, const double* xyz, in
   }
   if ((n_bfaces > 0 && (!bface2node || !bface_tag)) || n_bfaces < 0) {
     ctx->err = "invalid boundary arrays";
+    return HGKS_EINVAL;
+  }
+  if (ctx->o.scheme == HGKS_HWENO && ctx->o.compact_subs == HGKS_SUBS_HEX_WENO) {
+    ctx->err = "compact_subs = HGKS_SUBS_HEX_WENO needs a hexahedral mesh";
     return HGKS_EINVAL;
   }
   int rc = build_host_mesh(ctx->H, n_nodes, xyz, n_tets, tet2node, n_bfaces, bface2node, bface_tag, ctx->err);
@@ -540,6 +577,9 @@ static hgks_status finish_load(hgks_ctx* ctx) {
   TRY(upload(ctx, H.nbf, M.nbf));
   if (ctx->o.scheme == HGKS_WENO) {
     TRY(upload(ctx, H.stn, M.stn));
+    TRY(upload(ctx, H.sstn, M.sstn));
+    TRY(upload(ctx, H.smask, M.smask));
+  } else if (ctx->P.csubs) {
     TRY(upload(ctx, H.sstn, M.sstn));
     TRY(upload(ctx, H.smask, M.smask));
   }
@@ -626,6 +666,7 @@ hgks_status hgks_set_state(hgks_ctx* ctx, const double* Q, const double* gradQ) 
   }
   ctx->have_state = true;
   ctx->res0 = -1.0;
+  ctx->resumed = false;
   HIPCHK(hipStreamSynchronize(s));
   return HGKS_OK;
 }
@@ -836,11 +877,16 @@ hgks_status hgks_solve_steady(hgks_ctx* ctx, double drop, int32_t max_steps, hgk
   TRY(require(ctx, true));
   auto t0 = std::chrono::steady_clock::now();
   hgks_solve_info si{};
-  ctx->res0 = -1.0;
   hgks_status st = HGKS_OK;
-  // optional CFL ramp from an impulsive start
+  // optional CFL ramp from an impulsive start; a solve resumed from a
+  // checkpoint continues the ramp where it stood and measures the drop
+  // against the reference residual of the interrupted solve
   const bool ramp = ctx->o.cfl_start > 0.0 && ctx->o.cfl_start < ctx->o.cfl;
-  ctx->cfl_now = ramp ? ctx->o.cfl_start : ctx->o.cfl;
+  if (!ctx->resumed) {
+    ctx->res0 = -1.0;
+    ctx->cfl_now = ramp ? ctx->o.cfl_start : ctx->o.cfl;
+  }
+  ctx->resumed = false;
   set_params(ctx);
   for (int k = 0; k < max_steps; ++k) {
     hgks_step_info s{};
@@ -851,7 +897,7 @@ hgks_status hgks_solve_steady(hgks_ctx* ctx, double drop, int32_t max_steps, hgk
     }
     si.steps = k + 1;
     si.n_resid_evals += s.n_resid_evals;
-    if (k == 0) si.res0 = s.res;
+    if (k == 0) si.res0 = ctx->res0 > 0 ? ctx->res0 : s.res;
     si.res_final = s.res;
     if (st != HGKS_OK) break;
     if (s.res_rel <= drop) {
@@ -876,13 +922,15 @@ namespace {
 // (compact scheme only), then an FNV-1a 64-bit hash of everything before it.
 struct CkptHeader {
   char magic[8];     // "HGKSCKP1"
-  int32_t version;   // 1
+  int32_t version;   // 2
   int32_t scheme;    // HGKS_WENO | HGKS_HWENO
   int64_t n_cells;
   int64_t n_bfaces;
   double res0;       // residual the relative residual is measured against (< 0: none yet)
   double gamma;
+  double cfl_now;    // CFL number the next step runs at (the solve_steady ramp)
 };
+constexpr int32_t CKPT_VERSION = 2;
 
 uint64_t fnv1a(uint64_t h, const void* p, size_t n) {
   const unsigned char* b = (const unsigned char*)p;
@@ -906,12 +954,13 @@ hgks_status hgks_checkpoint(hgks_ctx* ctx, const char* path) {
   TRY(hgks_get_state(ctx, Q.data(), hw ? G.data() : nullptr));
   CkptHeader h{};
   std::memcpy(h.magic, "HGKSCKP1", 8);
-  h.version = 1;
+  h.version = CKPT_VERSION;
   h.scheme = ctx->o.scheme;
   h.n_cells = N;
   h.n_bfaces = ctx->H.Nb;
   h.res0 = ctx->res0;
   h.gamma = ctx->o.gamma;
+  h.cfl_now = ctx->cfl_now;
   uint64_t hash = fnv1a(FNV_OFFSET, &h, sizeof(h));
   hash = fnv1a(hash, Q.data(), Q.size() * sizeof(double));
   if (hw) hash = fnv1a(hash, G.data(), G.size() * sizeof(double));
@@ -948,7 +997,7 @@ hgks_status hgks_restore(hgks_ctx* ctx, const char* path) {
     return HGKS_EINVAL;
   };
   CkptHeader h{};
-  if (std::fread(&h, sizeof(h), 1, f) != 1 || std::memcmp(h.magic, "HGKSCKP1", 8) != 0 || h.version != 1)
+  if (std::fread(&h, sizeof(h), 1, f) != 1 || std::memcmp(h.magic, "HGKSCKP1", 8) != 0 || h.version != CKPT_VERSION)
     return fail("not an HGKS checkpoint file (bad magic or version)");
   const int64_t N = ctx->H.N;
   if (h.n_cells != N || h.n_bfaces != ctx->H.Nb) return fail("checkpoint was written for a different mesh");
@@ -970,8 +1019,15 @@ hgks_status hgks_restore(hgks_ctx* ctx, const char* path) {
     ctx->err = "checkpoint file is corrupt (hash mismatch)";
     return HGKS_EINVAL;
   }
+  if (!(h.cfl_now > 0.0)) {
+    ctx->err = "checkpoint holds no valid CFL number";
+    return HGKS_EINVAL;
+  }
   TRY(hgks_set_state(ctx, Q.data(), hw ? G.data() : nullptr));
   ctx->res0 = h.res0;
+  ctx->cfl_now = h.cfl_now;
+  ctx->resumed = true;
+  set_params(ctx);
   return HGKS_OK;
 }
 
@@ -1001,7 +1057,7 @@ static size_t residual_work_layout(const hgks_ctx* ctx, size_t off[6]) {
   const HostMesh& H = ctx->H;
   const size_t N = H.N, F = H.F, NX = H.N + H.Nb;
   const bool ho = ctx->o.scheme != HGKS_KFVS1;
-  const size_t nsub = H.nf == 4 ? 4 : (ctx->o.scheme == HGKS_HWENO ? 6 : 8);
+  const size_t nsub = H.nf == 4 ? 4 : (ctx->o.scheme == HGKS_HWENO && !ctx->P.csubs ? 6 : 8);
   const size_t len[6] = {5 * NX, N, ho ? 5 * (9 + 3 * nsub) * N : 0, ho ? (size_t)20 * H.ng * 2 * F : 0, 5 * F, 5 * F};
   size_t at = 0;
   for (int k = 0; k < 6; ++k) {

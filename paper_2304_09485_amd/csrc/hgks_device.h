@@ -52,7 +52,8 @@ struct Params {
   double gamma, K, tau_eps, tau_C, gamma_lin, weno_eps, mu, prandtl;
   double flux_scale;  // time interval of the flux average / implicit time step
   double rhoinf, uinf0, uinf1, uinf2, pinf;
-  int physics, weights, scheme, pad;
+  int physics, weights, scheme;
+  int csubs;  // hexahedra, compact scheme: 1 = the eight S^WENO sub-stencils from the cell averages
 };
 
 // Tangent rule: t1 = normalise(n x e_k), e_k the axis of smallest |n_k|

@@ -314,7 +314,10 @@ __global__ void __launch_bounds__(256) k_recon_weno_hex(DevMesh<T> M, const T* _
   }
 }
 
-template <typename T>
+// SUBW: the sub-stencil polynomials are the eight non-compact ones fitted
+// from the cell averages (sstn / opB, as k_recon_weno_hex) instead of the six
+// face pairs {i, i_f} fitted with the gradients
+template <typename T, bool SUBW>
 __global__ void __launch_bounds__(256) k_recon_hweno_hex(DevMesh<T> M, const T* __restrict__ Qx,
                                                          const T* __restrict__ Gx, T* __restrict__ coef) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -355,6 +358,31 @@ __global__ void __launch_bounds__(256) k_recon_hweno_hex(DevMesh<T> M, const T* 
   for (int k = 0; k < 9; ++k)
 #pragma unroll
     for (int v = 0; v < 5; ++v) coef[(size_t)(k * 5 + v) * N + i] = acc[k][v];
+  if (SUBW) {
+    // the eight sub-stencils {i, i_1 or i_6, two consecutive lateral neighbours}
+    for (int sb = 0; sb < 8; ++sb) {
+      T ds[3][5];
+#pragma unroll
+      for (int r = 0; r < 3; ++r) {
+        const int c = M.sstn[(size_t)(sb * 3 + r) * N + i];
+#pragma unroll
+        for (int v = 0; v < 5; ++v) ds[r][v] = Qx[(size_t)v * NX + c] - q0[v];
+      }
+#pragma unroll
+      for (int t = 0; t < 3; ++t) {
+        T a5[5] = {T(0), T(0), T(0), T(0), T(0)};
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+          const T o = M.opB[(size_t)((sb * 3 + t) * 3 + r) * N + i];
+#pragma unroll
+          for (int v = 0; v < 5; ++v) a5[v] += o * ds[r][v];
+        }
+#pragma unroll
+        for (int v = 0; v < 5; ++v) coef[(size_t)((9 + sb * 3 + t) * 5 + v) * N + i] = a5[v];
+      }
+    }
+    return;
+  }
   // P_m on {i, i_m}: the constrained minimiser has a closed form
   for (int sb = 0; sb < 6; ++sb) {
     const T wi = M.hsub[(size_t)(sb * 6 + 0) * N + i], wm = M.hsub[(size_t)(sb * 6 + 1) * N + i];
@@ -1060,8 +1088,10 @@ template <typename T>
 void launch_recon(const DevMesh<T>& M, const Params& P, const T* Qx, const T* Gx, T* coef, hipStream_t s) {
   const dim3 g(nblk(M.N, 256)), b(256);
   if (M.nf == 6) {
-    if (P.scheme == 1)
-      hipLaunchKernelGGL(k_recon_hweno_hex<T>, g, b, 0, s, M, Qx, Gx, coef);
+    if (P.scheme == 1 && P.csubs)
+      hipLaunchKernelGGL((k_recon_hweno_hex<T, true>), g, b, 0, s, M, Qx, Gx, coef);
+    else if (P.scheme == 1)
+      hipLaunchKernelGGL((k_recon_hweno_hex<T, false>), g, b, 0, s, M, Qx, Gx, coef);
     else
       hipLaunchKernelGGL(k_recon_weno_hex<T>, g, b, 0, s, M, Qx, coef);
   } else if (P.scheme == 1) {
@@ -1081,7 +1111,7 @@ void launch_side(const DevMesh<T>& M, const Params& P, const T* Qx, const T* coe
     // quadrilateral faces: one lane per side, its 4 Gauss points evaluated
     // from the combined polynomials after the component loop
     const dim3 g(nblk(2 * (size_t)M.F, SIDE_SPB));
-    if (P.scheme == 1)
+    if (P.scheme == 1 && !P.csubs)
       hipLaunchKernelGGL((k_side<T, 6, 4, 1>), g, b, 0, s, M, P, Qx, coef, sv, nfall);
     else
       hipLaunchKernelGGL((k_side<T, 8, 4, 1>), g, b, 0, s, M, P, Qx, coef, sv, nfall);

@@ -71,7 +71,7 @@ __global__ void __launch_bounds__(128) k_side(DevMesh<T> M, Params P, const T* _
   T xi[NGL][3];
 #pragma unroll
   for (int k = 0; k < 3 * NGL; ++k) xi[k / 3][k % 3] = xis[(size_t)(3 * g_lo + k) * F + f];
-  unsigned mask = P.scheme == 1 ? (1u << NSUB) - 1u : (unsigned)M.smask[i];
+  unsigned mask = P.scheme == 1 && !P.csubs ? (1u << NSUB) - 1u : (unsigned)M.smask[i];
   int nsub = __popc(mask);
   const T gl = T(P.gamma_lin);
   const T g0 = T(1) - gl * T(nsub);

@@ -20,6 +20,7 @@ EULER, NS = 0, 1
 FP64, FP32_INNER = 0, 1
 JV_FD, JV_APPROX = 0, 1
 SOLVER_GMRES, SOLVER_LUSGS = 0, 1
+SUBS_FACES, SUBS_HEX_WENO = 0, 1
 WEIGHTS_NONLINEAR, WEIGHTS_LINEAR = 0, 1
 FARFIELD, SLIP_WALL, NOSLIP_ADIABATIC, SUP_IN, SUP_OUT = 0, 1, 2, 3, 4
 
@@ -46,11 +47,42 @@ class Options(ctypes.Structure):
     _fields_ = [("scheme", ctypes.c_int32), ("physics", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("weights", ctypes.c_int32), ("krylov_dim", ctypes.c_int32), ("restarts", ctypes.c_int32),
                 ("jacobi_sweeps", ctypes.c_int32), ("jv_mode", ctypes.c_int32), ("solver", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("gamma", ctypes.c_double), ("cfl", ctypes.c_double), ("tau_eps", ctypes.c_double),
+                ("compact_subs", ctypes.c_int32), ("gamma", ctypes.c_double), ("cfl", ctypes.c_double), ("tau_eps", ctypes.c_double),
                 ("tau_C", ctypes.c_double), ("gamma_lin", ctypes.c_double), ("weno_eps", ctypes.c_double),
                 ("mu", ctypes.c_double), ("prandtl", ctypes.c_double), ("fd_sigma", ctypes.c_double),
                 ("cfl_flux", ctypes.c_double), ("cfl_start", ctypes.c_double), ("cfl_growth", ctypes.c_double),
-                ("stream", ctypes.c_void_p)]
+                ("stream", ctypes.c_void_p), ("dev_alloc", ctypes.c_void_p), ("dev_free", ctypes.c_void_p),
+                ("alloc_user", ctypes.c_void_p)]
+
+
+# Device allocator hook: PyTorch's caching allocator, so that the library's
+# device buffers count in torch's memory statistics and reuse its pool.
+_ALLOC_T = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+_FREE_T = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+
+
+def _torch_alloc(nbytes, user):
+    try:
+        import torch
+        return torch.cuda.caching_allocator_alloc(int(nbytes))
+    except Exception:  # out of memory or torch torn down: NULL -> HGKS_ENOMEM
+        return None
+
+
+def _torch_free(ptr, user):
+    try:
+        import torch
+        torch.cuda.caching_allocator_delete(ptr)
+    except Exception:
+        pass
+
+
+_TORCH_HOOK = (_ALLOC_T(_torch_alloc), _FREE_T(_torch_free))  # kept alive for the process
+
+
+def torch_allocator_hook():
+    """(dev_alloc, dev_free) function pointers of PyTorch's caching allocator."""
+    return (ctypes.cast(_TORCH_HOOK[0], ctypes.c_void_p).value, ctypes.cast(_TORCH_HOOK[1], ctypes.c_void_p).value)
 
 
 class StepInfo(ctypes.Structure):
@@ -148,9 +180,16 @@ def load_library():
     return L
 
 
-def default_options(**kw) -> Options:
+def default_options(allocator="torch", **kw) -> Options:
+    """The library's defaults with kw applied.  allocator="torch" (default)
+    routes the context's device memory through PyTorch's caching allocator,
+    None through hipMalloc."""
     o = Options()
     load_library().hgks_default_options(ctypes.byref(o))
+    if allocator == "torch":
+        o.dev_alloc, o.dev_free = torch_allocator_hook()
+    elif allocator is not None:
+        raise ValueError(f"allocator must be 'torch' or None, not {allocator!r}")
     for k, v in kw.items():
         if not hasattr(o, k):
             raise AttributeError(k)

@@ -23,6 +23,24 @@ def flux_scale(mesh, prim):
     return f * area.max()
 
 
+def area_sums(mesh):
+    """Sum of the four face areas of every tet (computed from the nodes)."""
+    v = mesh.xyz[mesh.tets]
+    area = np.zeros(len(v))
+    for p in range(4):
+        tri = np.delete(v, p, axis=1)
+        area += 0.5 * np.linalg.norm(np.cross(tri[:, 1] - tri[:, 0], tri[:, 2] - tri[:, 0]), axis=1)
+    return area
+
+
+def grad_update_bound(mesh, Q, vol, rel=1e-12):
+    """Per-cell bound of the compact gradient update of Eq. (derivative):
+    it is (1/|Omega_i|) times a sum over the cell's faces of S_f times
+    Gauss-point values of size |Q|, which carry the same relative rounding
+    as the fluxes, so rel x max|Q| x (sum of face areas) / |Omega_i|."""
+    return rel * np.abs(Q).max() * area_sums(mesh) / vol
+
+
 def pair(oracle_mod, mesh, kinds, prim, **opts):
     from paper_2304_09485_amd import hgks
     o = oracle_mod.Oracle(mesh, kinds, prim, **{k: v for k, v in opts.items() if k != "precision"})

@@ -86,3 +86,36 @@ def test_bad_files_are_refused(tmp_path):
         a.restore(os.fspath(tmp_path / "missing.ckpt"))
     for s in (a, w, c):
         s.close()
+
+
+def test_resumed_solve_continues_the_ramp_and_the_drop(tmp_path):
+    """solve_steady with a CFL ramp, interrupted after 4 steps, written out and
+    resumed in a fresh context for 5 more: the same state, step count and
+    drop as 9 steps in one call (the restored reference residual and ramp
+    position are used, not restarted)."""
+    from paper_2304_09485_amd import hgks
+    mesh = shell_mesh(4, 4, grading=1.3, jitter=0.05, seed=2)
+    prim = freestream_prim(0.5)
+    opts = dict(scheme=1, cfl=10.0, cfl_start=1.0, cfl_growth=1.5)
+
+    def fresh():
+        s = hgks.Solver(mesh, {1: C.SLIP, 2: C.FAR}, prim, **opts)
+        s.set_state(perturbed_state(s.N, prim, seed=4), np.zeros((15, s.N)))
+        return s
+
+    a = fresh()
+    ia = a.solve_steady(drop=1e-30, max_steps=9)
+    Qa = a.get_state()
+    b = fresh()
+    b.solve_steady(drop=1e-30, max_steps=4)
+    path = os.fspath(tmp_path / "ramp.ckpt")
+    b.checkpoint(path)
+    c = fresh()
+    c.restore(path)
+    ic = c.solve_steady(drop=1e-30, max_steps=5)
+    Qc = c.get_state()
+    assert np.array_equal(Qa, Qc)
+    assert ia.res_final == ic.res_final
+    assert ia.res0 == ic.res0 and ia.drop == ic.drop
+    for s in (a, b, c):
+        s.close()

@@ -1,0 +1,72 @@
+"""The device allocator hook of the C ABI (hgks_options.dev_alloc / dev_free /
+alloc_user): a context whose buffers come from PyTorch's caching allocator
+gives bitwise the results of one on hipMalloc, its memory shows in torch's
+statistics while it lives and is handed back on destroy."""
+import numpy as np
+import pytest
+
+from inputs import freestream_prim, perturbed_state, shell_mesh
+
+FAR, SLIP = 0, 1
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("opts", [{"scheme": 1}, {"scheme": 0, "precision": 1}])
+def test_torch_allocator_context_matches_hipmalloc(opts):
+    import gc
+
+    import torch
+    # contexts of earlier tests that are still unreferenced would be freed
+    # (through torch) in the middle of the accounting below: collect them now
+    # and keep the collector off while measuring
+    gc.collect()
+    gc.disable()
+    try:
+        _check_allocators(torch, opts)
+    finally:
+        gc.enable()
+
+
+def _check_allocators(torch, opts):
+    from paper_2304_09485_amd import hgks
+    mesh = shell_mesh(5, 6, grading=1.2, jitter=0.05, seed=4)
+    kinds = {1: SLIP, 2: FAR}
+    prim = freestream_prim(0.5)
+    torch.cuda.synchronize()
+    base = torch.cuda.memory_allocated()
+    out = {}
+    for alloc in (None, "torch"):
+        print(f"allocator {alloc} opts {opts}", flush=True)
+        s = hgks.Solver(mesh, kinds, prim, allocator=alloc, **opts)
+        grew = torch.cuda.memory_allocated() - base
+        if alloc is None:
+            assert grew == 0
+        else:
+            # everything the context holds comes from torch's pool
+            assert grew >= hgks.estimate_bytes(s.N, len(mesh.bfaces), **opts) // 4, grew
+        Q = perturbed_state(s.N, prim, seed=3)
+        G = np.random.default_rng(3).normal(scale=0.01, size=(15, s.N))
+        R, Gn = s.residual(Q, G=G, want_grad=True) if opts["scheme"] == 1 else (s.residual(Q), None)
+        s.set_state(Q, G if opts["scheme"] == 1 else None)
+        res = [s.implicit_step().res for _ in range(3)]
+        Qf, Gf = s.get_state(want_grad=True)
+        out[alloc] = (R, Gn, res, Qf, Gf)
+        s.close()
+        torch.cuda.synchronize()
+        assert torch.cuda.memory_allocated() == base
+    a, b = out[None], out["torch"]
+    assert np.array_equal(a[0], b[0])
+    if a[1] is not None:
+        assert np.array_equal(a[1], b[1])
+    assert a[2] == b[2]
+    assert np.array_equal(a[3], b[3]) and np.array_equal(a[4], b[4])
+
+
+@pytest.mark.gpu
+def test_allocator_hook_must_be_complete():
+    from paper_2304_09485_amd import hgks
+    o = hgks.default_options(allocator="torch")
+    o.dev_free = None
+    import ctypes
+    h = ctypes.c_void_p()
+    assert hgks.load_library().hgks_create(ctypes.byref(o), ctypes.byref(h)) == -1

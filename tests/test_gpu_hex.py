@@ -18,18 +18,25 @@ HCASES = {
     "hshell": (lambda: shell_mesh(4, 4, grading=1.3, jitter=0.05, seed=2, hexahedra=True), {1: C.SLIP, 2: C.FAR}, 0.5),
     "hcube_noslip": (lambda: cube_mesh(3, jitter=0.1, seed=7, hexahedra=True), {t: C.NOSLIP for t in range(1, 7)}, 0.2),
 }
-SCHEMES = {"weno": dict(scheme=0), "hweno": dict(scheme=1), "kfvs": dict(scheme=2)}
+# "hweno_w": the compact scheme with the eight S^WENO sub-stencils (the
+# hexahedral sphere cases of Sec. 5)
+SCHEMES = {"weno": dict(scheme=0), "hweno": dict(scheme=1), "hweno_w": dict(scheme=1, compact_subs=1),
+           "kfvs": dict(scheme=2)}
+
+
+def _area_sums(o):
+    L, R, S, n, gp = o.faces()
+    area = np.zeros(o.N)
+    np.add.at(area, L, S)
+    np.add.at(area, R[R >= 0], S[R >= 0])
+    return area
 
 
 def _flux_scale(o, prim):
     """largest cell surface (from the oracle's faces) x the free stream's Euler flux"""
     from inputs import prim_to_cons
     from tests import _indep as I
-    L, R, S, n, gp = o.faces()
-    area = np.zeros(o.N)
-    np.add.at(area, L, S)
-    np.add.at(area, R[R >= 0], S[R >= 0])
-    return max(np.abs(I.euler_flux(prim_to_cons(prim), d)).max() for d in np.eye(3)) * area.max()
+    return max(np.abs(I.euler_flux(prim_to_cons(prim), d)).max() for d in np.eye(3)) * _area_sums(o).max()
 
 
 def _pair(oracle_lib, case, scheme, **opts):
@@ -53,7 +60,7 @@ def test_hex_residual_parity(oracle_lib, case, scheme):
     m, prim, o, s = _pair(oracle_lib, case, scheme)
     assert s.N == o.N and s.F == o.F
     Q = perturbed_state(o.N, prim, amp=0.03, seed=2)
-    hw = scheme == "hweno"
+    hw = scheme.startswith("hweno")
     G = np.random.default_rng(7).normal(scale=0.05, size=(15, o.N)) if hw else None
     Ro = o.residual(Q, G=G, want_grad=hw)
     Rg = s.residual(Q, G=G, want_grad=hw)
@@ -65,17 +72,21 @@ def test_hex_residual_parity(oracle_lib, case, scheme):
     print(f"{case} {scheme}: max|dR|/flux_scale = {err:.3e}")
     assert err <= 1e-12
     if hw:
-        vol = o.geometry()[0]
-        gscale = np.abs(Q).max() * fs / np.abs(prim).max() / vol.min() * 10
-        assert np.abs(Gng - Gno).max() <= 1e-12 * gscale
+        # the gradient update of Eq. (derivative): face sums of S_f times
+        # Gauss-point values of size |Q| with the flux's relative rounding,
+        # divided by the volume
+        bound = 1e-12 * np.abs(Q).max() * _area_sums(o) / o.geometry()[0]
+        gerr = np.abs(Gng - Gno).max(axis=0)
+        print(f"{case} {scheme}: gradient-update error / bound = {(gerr / bound).max():.3e}")
+        assert np.all(gerr <= bound)
     s.close()
 
 
-@pytest.mark.parametrize("scheme", ["weno", "hweno"])
+@pytest.mark.parametrize("scheme", ["weno", "hweno", "hweno_w"])
 def test_hex_jv_parity(oracle_lib, scheme):
     m, prim, o, s = _pair(oracle_lib, "hshell", scheme)
     Q = perturbed_state(o.N, prim, seed=4)
-    G = np.random.default_rng(9).normal(scale=0.05, size=(15, o.N)) if scheme == "hweno" else None
+    G = np.random.default_rng(9).normal(scale=0.05, size=(15, o.N)) if scheme.startswith("hweno") else None
     s.set_state(Q, G)
     dt = o.dt(Q)
     np.testing.assert_allclose(s.time_step(Q), dt, rtol=1e-13)
@@ -91,13 +102,13 @@ def test_hex_jv_parity(oracle_lib, scheme):
     s.close()
 
 
-@pytest.mark.parametrize("scheme,solver", [("weno", "approx"), ("hweno", "approx"), ("weno", "lusgs"),
-                                           ("kfvs", "lusgs")])
+@pytest.mark.parametrize("scheme,solver", [("weno", "approx"), ("hweno", "approx"), ("hweno_w", "approx"),
+                                           ("weno", "lusgs"), ("kfvs", "lusgs")])
 def test_hex_implicit_steps(oracle_lib, scheme, solver):
     from paper_2304_09485_amd import hgks
     opts = dict(jv_mode=1) if solver == "approx" else dict(solver=1)
     m, prim, o, s = _pair(oracle_lib, "hshell", scheme, **opts)
-    hw = scheme == "hweno"
+    hw = scheme.startswith("hweno")
     G0 = np.random.default_rng(3).normal(scale=0.02, size=(15, o.N)) if hw else None
     s.set_state(perturbed_state(o.N, prim, amp=0.05, seed=1), G0)
     for k in range(4):
@@ -139,7 +150,9 @@ def test_hex_fp32_inner_step(oracle_lib):
 def test_hex_full_size(oracle_lib):
     """A 135,168-hex sphere shell (the benchmark shell's cubed-sphere layout
     without the tetrahedral split, 32 x 32 per patch, 22 layers): residual of
-    the non-compact scheme and the first-order scheme at Mach 0.5."""
+    the non-compact scheme, the compact scheme with the eight S^WENO
+    sub-stencils (with its gradient update) and the first-order scheme at
+    Mach 0.5."""
     from paper_2304_09485_amd import hgks
     m = shell_mesh(32, 22, grading=1.1, jitter=0.02, seed=2, hexahedra=True)
     prim = freestream_prim(0.5)
@@ -147,14 +160,23 @@ def test_hex_full_size(oracle_lib):
     Q = perturbed_state(m.n_cells, prim, amp=0.03, seed=3)
     oracle_lib.set_threads(16)
     try:
-        for sch in (0, 2):
-            o = oracle_lib.Oracle(m, kinds, prim, **({"scheme": 0} if sch == 0 else {"first_order": 1}))
-            s = hgks.Solver(m, kinds, prim, scheme=sch)
-            Ro = o.residual(Q)
-            Rg = s.residual(Q)
+        G = np.random.default_rng(4).normal(scale=0.02, size=(15, m.n_cells))
+        for name in ("weno", "hweno_w", "kfvs"):
+            so = SCHEMES[name]
+            oo = {"first_order": 1} if name == "kfvs" else so
+            o = oracle_lib.Oracle(m, kinds, prim, **oo)
+            s = hgks.Solver(m, kinds, prim, **so)
+            hw = name == "hweno_w"
+            Ro = o.residual(Q, G=G, want_grad=hw)
+            Rg = s.residual(Q, G=G if hw else None, want_grad=hw)
+            if hw:
+                Ro, Gno, _ = Ro
+                Rg, Gng = Rg
+                bound = 1e-12 * np.abs(Q).max() * _area_sums(o) / o.geometry()[0]
+                assert np.all(np.abs(Gng - Gno).max(axis=0) <= bound)
             fs = _flux_scale(o, prim)
             err = np.abs(Rg - Ro).max() / fs
-            print(f"hex shell {m.n_cells} cells, scheme {sch}: max|dR|/flux_scale = {err:.3e}")
+            print(f"hex shell {m.n_cells} cells, {name}: max|dR|/flux_scale = {err:.3e}")
             assert err <= 1e-12
             s.close()
     finally:
@@ -175,7 +197,7 @@ def test_hex_repeat_and_free_stream(oracle_lib, scheme):
     s = hgks.Solver(m, far, prim, **SCHEMES[scheme])
     Q = perturbed_state(o.N, prim, amp=0.03, seed=9)
     U = uniform_state(o.N, prim)
-    G = np.zeros((15, o.N)) if scheme == "hweno" else None
+    G = np.zeros((15, o.N)) if scheme.startswith("hweno") else None
     r0 = s.residual(Q, G)
     for _ in range(3):
         assert np.abs(s.residual(U, G)).max() <= 1e-13 * _flux_scale(o, prim)

@@ -11,7 +11,10 @@ bilinear faces).
   * the eight sub-stencils of an interior cell of a regular grid span the
     eight octants;
   * linear data reproduced by every polynomial and by the nonlinear
-    combination, quadratic data with linear weights (WENO and HWENO);
+    combination, quadratic data with linear weights (WENO and HWENO, the
+    latter with either sub-stencil family);
+  * the compact scheme with the eight S^WENO sub-stencils fits its P_m from
+    cell averages alone (the non-compact P_m), with 8 weights;
   * free-stream preservation (WENO, HWENO, first-order KFVS) and
     conservation in a closed box;
   * the approximate matrix and two Jacobi sweeps against a direct assembly
@@ -23,7 +26,7 @@ import pytest
 
 from inputs import HexMesh, cube_mesh, freestream_prim, perturbed_state, shell_mesh, uniform_state
 from tests import _indep as I
-from tests.test_oracle_recon import lin, lin_grad, quad, quad_grad
+from tests.test_oracle_recon import GL, lin, lin_grad, quad, quad_grad
 
 ALL_FAR = {t: 0 for t in range(1, 7)}
 
@@ -136,10 +139,11 @@ def _expected(o, f, fv, fg, P):
     return out
 
 
-@pytest.mark.parametrize("scheme,weights,data", [(0, 0, "lin"), (1, 0, "lin"), (0, 1, "quad"), (1, 1, "quad")])
-def test_hex_reproduction(oracle_lib, scheme, weights, data):
+@pytest.mark.parametrize("scheme,weights,data,subs", [(0, 0, "lin", 0), (1, 0, "lin", 0), (0, 1, "quad", 0),
+                                                      (1, 1, "quad", 0), (1, 0, "lin", 1), (1, 1, "quad", 1)])
+def test_hex_reproduction(oracle_lib, scheme, weights, data, subs):
     m = cube_mesh(7, jitter=0.15, seed=3, hexahedra=True)
-    o = oracle_lib.Oracle(m, ALL_FAR, freestream_prim(0.3), scheme=scheme, weights=weights)
+    o = oracle_lib.Oracle(m, ALL_FAR, freestream_prim(0.3), scheme=scheme, weights=weights, compact_subs=subs)
     fv, fg = (lin, lin_grad) if data == "lin" else (quad, quad_grad)
     Q = I.cell_averages(m, fv, order=4)
     vol, cen, _ = o.geometry()
@@ -154,7 +158,8 @@ def test_hex_reproduction(oracle_lib, scheme, weights, data):
             np.testing.assert_allclose(got, exp, rtol=0, atol=1e-12)
 
 
-@pytest.mark.parametrize("opts", [dict(scheme=0), dict(scheme=1), dict(first_order=1)])
+@pytest.mark.parametrize("opts", [dict(scheme=0), dict(scheme=1), dict(scheme=1, compact_subs=1),
+                                  dict(first_order=1)])
 def test_hex_free_stream_preserved(oracle_lib, opts):
     m = shell_mesh(3, 3, grading=1.3, jitter=0.05, seed=2, hexahedra=True)
     prim = freestream_prim(0.6, direction=(1.0, 0.4, -0.3))
@@ -165,11 +170,11 @@ def test_hex_free_stream_preserved(oracle_lib, opts):
     assert np.abs(R).max() <= 1e-13 * scale
 
 
-@pytest.mark.parametrize("scheme", [0, 1])
-def test_hex_conservation_closed_box(oracle_lib, scheme):
+@pytest.mark.parametrize("scheme,subs", [(0, 0), (1, 0), (1, 1)])
+def test_hex_conservation_closed_box(oracle_lib, scheme, subs):
     m = jcube(4, seed=5)
     prim = freestream_prim(0.3)
-    o = oracle_lib.Oracle(m, {t: oracle_lib.SLIP for t in range(1, 7)}, prim, scheme=scheme)
+    o = oracle_lib.Oracle(m, {t: oracle_lib.SLIP for t in range(1, 7)}, prim, scheme=scheme, compact_subs=subs)
     Q = perturbed_state(o.N, prim, amp=0.05, seed=3)
     G = np.random.default_rng(1).normal(scale=0.05, size=(15, o.N)) if scheme == 1 else None
     R = o.residual(Q, G=G)
@@ -232,3 +237,36 @@ def test_hex_approximate_matrix_and_lusgs(oracle_lib):
     M = (Dm + Lm) @ np.linalg.inv(Dm) @ (Dm + Um)
     xs = np.linalg.solve(M, r.ravel()).reshape(5, N)
     np.testing.assert_allclose(o.lusgs(Q, dt, r), xs, rtol=0, atol=1e-12 * np.abs(xs).max())
+
+
+def test_hex_compact_weno_sub_stencils_use_averages_only(oracle_lib):
+    """With the eight S^WENO sub-stencils as the compact scheme's sub-stencils
+    (the hexahedral sphere cases of Sec. 5), each P_m is fitted from the cell
+    averages of its four cells alone: on linear data its gradient is the
+    exact one whatever the supplied cell gradients are, there are 8 of them
+    (gamma_0 = 1 - 8 x 0.025), and they are the non-compact scheme's P_m;
+    with the faces' {i, i_f} sub-stencils the garbage gradients do enter."""
+    m = cube_mesh(7, jitter=0.15, seed=4, hexahedra=True)
+    prim = freestream_prim(0.3)
+    Q = I.cell_averages(m, lin, order=4)
+    G = np.random.default_rng(2).normal(scale=1.0, size=(15, len(m.hexes)))
+    o1 = oracle_lib.Oracle(m, ALL_FAR, prim, scheme=1, compact_subs=1)
+    o0 = oracle_lib.Oracle(m, ALL_FAR, prim, scheme=1, compact_subs=0)
+    ow = oracle_lib.Oracle(m, ALL_FAR, prim, scheme=0)
+    faces, _ = _interior_faces(ow)
+    assert len(faces) > 5
+    for f in faces[:12]:
+        for side in (0, 1):
+            d1 = o1.side_debug(Q, f, side, G=G)
+            d0 = o0.side_debug(Q, f, side, G=G)
+            dw = ow.side_debug(Q, f, side)
+            Lc = d1["L"]
+            fr = o1.face_frame(f)
+            # exact gradient of each characteristic component of the linear data
+            Gl = GL.copy()
+            Gl[1:4] = fr @ GL[1:4]
+            exact = Lc @ Gl  # (5, 3)
+            assert (d1["M"] == 8).all() and (d0["M"] == 6).all()
+            np.testing.assert_allclose(d1["b"], np.repeat(exact[:, None, :], 8, axis=1), rtol=0, atol=1e-12)
+            np.testing.assert_allclose(d1["b"], dw["b"], rtol=0, atol=1e-13)
+            assert np.abs(d0["b"][:, :6] - exact[:, None, :]).max() > 1e-3

@@ -258,3 +258,19 @@ def test_gmres_breakdown_single_tet_is_exact(oracle_lib):
     assert np.abs(b).max() > 1e-4  # the inflow makes a residual of size
     ref = b / D
     np.testing.assert_allclose(Q1 - Q, ref, rtol=0, atol=1e-12 * np.abs(ref).max())
+
+
+@pytest.mark.parametrize("scheme", [0, 1])
+def test_sampled_residual_equals_full(oracle_lib, scheme):
+    """The residual of a sample of cells (used at sizes where the full oracle
+    residual is too slow) is the same as those cells' entries of the full
+    residual, gradient update included."""
+    from inputs import freestream_prim, perturbed_state, shell_mesh
+    m = shell_mesh(4, 4, grading=1.3, jitter=0.05, seed=2)
+    o = oracle_lib.Oracle(m, {1: 1, 2: 0}, freestream_prim(0.5), scheme=scheme)
+    Q = perturbed_state(o.N, freestream_prim(0.5), seed=3)
+    G = np.random.default_rng(1).normal(scale=0.01, size=(15, o.N))
+    R, Gn, _ = o.residual(Q, G=G, want_grad=True)
+    cells = np.random.default_rng(2).choice(o.N, 50, replace=False)
+    Rs, Gs = o.residual_cells(Q, cells, G=G, want_grad=True)
+    assert np.array_equal(Rs, R[:, cells]) and np.array_equal(Gs, Gn[:, cells])
