@@ -1,18 +1,29 @@
 #!/usr/bin/env python3
-"""Benchmark: implicit steps of the compact HWENO gas-kinetic scheme on one MI355X.
+"""Benchmark: implicit steps of the implicit high-order gas-kinetic scheme on one MI355X.
 
-Workload (default): inviscid Mach 0.5 flow past a sphere, seeded jittered
-cubed-sphere tetrahedral shell r in [0.5, 10] with 202,752 tets, slip wall on
-the sphere and far field outside, compact HWENO reconstruction with gradients
-updated from the gas distribution function, CFL 10, GMRES(10) x 3 restarts,
-2 Jacobi sweeps, FP64.  One timed "step" is one implicit step: the base
-residual, 32 FD Jacobian-vector products (each a full residual evaluation),
-Jacobi sweeps, MGS Arnoldi, host Givens, the update and the gradient update.
+Workload (default, --config c4): inviscid Mach 2 flow in a 3D channel with a
+15-degree compression ramp, 192 x 72 x 48 sheared hexahedra x 6 = 3,981,312
+jittered tets, supersonic inflow and outflow, slip walls, non-compact WENO
+with nonlinear weights, CFL 10, GMRES(10) x 3 restarts on FD
+Jacobian-vector products, 2 Jacobi sweeps, FP64.  From the uniform free
+stream the plain update reaches a non-physical state in the first step (at
+the corner of the ramp, the outlet and a side wall, even at CFL 1), so each
+cell's update is limited to a 20 % change of density and pressure
+(max_update 0.2, a runtime policy; steady states are unchanged).  One timed
+"step" is one implicit step: the base residual, 32 FD Jacobian-vector
+products (each a full residual evaluation), Jacobi sweeps, MGS Arnoldi, the
+GMRES rotations and solve on the device, the (limited) update.
+
+Other workloads: c1 (unit cube, 3,072 tets, Euler Mach 0.3, WENO), c2 (sphere
+shell, 202,752 tets, Euler Mach 0.5, compact HWENO), c3 (boundary-layer
+sphere shell, 995,328 tets, NS Mach 0.25 Re 118 Pr 0.72, WENO, update limit).
 
 Prints one JSON line: metric/value (Mcell-residual evaluations per second over
-the timed steps), roofline of the dominant residual kernel (per-launch HIP
-event timings recorded inside the timed region) and the CPU oracle baseline on
-a bounded sample.
+the timed steps), the residual evaluation's roofline (method bytes of the
+scheme per cell over the five residual kernels' per-launch HIP event times,
+recorded inside the timed region on the context's stream), per-kernel rates,
+secondary workloads, times to a 1e-8 drop, variants, and the CPU oracle
+baseline on a bounded sample.
 """
 from __future__ import annotations
 
@@ -35,10 +46,29 @@ PEAK_FP64_VALU = 78.6e12     # MI355X FP64 vector FLOP/s
 # (csrc/flopcount.cpp, run by the build); a flux launch covers 3 F points
 FLOPS_FILE = os.path.join(ROOT, "paper_2304_09485_amd", "flux_flops.json")
 # measured HBM traffic per launch (rocprofv3 FETCH_SIZE / WRITE_SIZE runs,
-# calibrated against a plain copy), with the hash of the kernel sources the
-# counters were taken with
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_c2_hweno.md")
+# calibrated against a plain copy), per workload, with the hash of the kernel
+# sources the counters were taken with
+TRAFFIC_FILES = {"c2": os.path.join(ROOT, "profiles", "hbm_traffic_c2_hweno.md"),
+                 "c4": os.path.join(ROOT, "profiles", "hbm_traffic_c4_weno.md")}
 KERNEL_SOURCES = ["hgks_kernels.hip", "side_kernel.h", "gks_flux.h", "hgks_device.h", "hgks_kernels.h"]
+
+# the workloads (boundary kinds: 0 far field, 1 slip wall, 2 no-slip
+# adiabatic wall, 3 supersonic inflow, 4 supersonic outflow)
+WORKLOADS = {
+    "c1": dict(mach=0.3, kinds={t: 0 for t in range(1, 7)}, opts=dict(scheme=0), start="perturbed", ramp=None,
+               desc="unit cube, Euler Mach 0.3, non-compact WENO, 3,072 tets, FP64 implicit steps"),
+    "c2": dict(mach=0.5, kinds={1: 1, 2: 0}, opts=dict(scheme=1), start="uniform", ramp=None,
+               desc="sphere shell, inviscid Mach 0.5, compact HWENO, 202,752 tets, FP64 implicit steps"),
+    "c3": dict(mach=0.25, kinds={1: 2, 2: 0}, opts=dict(scheme=0, physics=1, mu=0.25 / 118.0, prandtl=0.72,
+                                                       max_update=0.2),
+               start="uniform", ramp=None,
+               desc="boundary-layer sphere shell, NS Mach 0.25 Re 118 Pr 0.72, non-compact WENO, 995,328 tets, "
+                    "FP64 implicit steps (update limit 0.2)"),
+    "c4": dict(mach=2.0, kinds={1: 3, 2: 4, 3: 1, 4: 1, 5: 1, 6: 1}, opts=dict(scheme=0, max_update=0.2),
+               start="uniform", ramp=None,
+               desc="15-degree ramp channel, Euler Mach 2, non-compact WENO, 3,981,312 tets, FP64 implicit steps "
+                    "(update limit 0.2)"),
+}
 
 
 def kernel_source_hash():
@@ -50,19 +80,48 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def traffic_for(kernel):
-    """HBM bytes per launch of the kernel as measured by the counters, or None
-    if none were taken or the kernel sources changed since."""
-    if not os.path.exists(TRAFFIC_FILE):
+def traffic_for(workload, kernel):
+    """HBM bytes per launch of the kernel on the workload as measured by the
+    counters, or None if none were taken or the kernel sources changed since."""
+    path = TRAFFIC_FILES.get(workload)
+    if not path or not os.path.exists(path):
         return None
     want = kernel_source_hash()
-    with open(TRAFFIC_FILE) as f:
+    with open(path) as f:
         for line in f:
             p = line.split()
             # lines "traffic <kernel> <bytes per launch> <source hash>"
             if len(p) == 4 and p[0] == "traffic" and p[1] == kernel and p[3] == want:
                 return int(float(p[2]))
     return None
+
+
+def method_bytes_per_cell(scheme, jv):
+    """Bytes per cell one residual evaluation of the method must move at
+    least (stored-operator design, FP64, a cell's data read once and its
+    results written once): the state (and for an FD product the direction v),
+    the residual written (and the base residual read by the FD epilogue), the
+    stencil indices, the stored reconstruction operators, the cell geometry
+    (centroid, 9 basis means, volume, 6 second moments), about two faces per
+    cell (ids, normal, area, Gauss points), the time step; the compact scheme
+    adds its frozen gradients and, on the base evaluation only, the gradient
+    update written."""
+    q = 40 + (40 if jv else 0)
+    r = 40 + (40 if jv else 0)
+    if scheme == 1:
+        idx, ops, grad = 16, 1368 + 160, 120 + (0 if jv else 120)
+    else:
+        idx, ops, grad = 64, 1728, 0
+    return q + r + idx + ops + 152 + 224 + 8 + grad
+
+
+def step_method_bytes(scheme, N, evals_per_step):
+    """Method bytes of one implicit step's residual evaluations (the base
+    evaluation and evals_per_step - 1 FD products), per evaluation."""
+    if evals_per_step <= 1:
+        return N * method_bytes_per_cell(scheme, False)
+    return N * (method_bytes_per_cell(scheme, False)
+                + (evals_per_step - 1) * method_bytes_per_cell(scheme, True)) / evals_per_step
 
 
 def algorithmic_bytes(kernel, N, F, Nb, scheme):
@@ -121,27 +180,136 @@ def flux_flops_per_launch(flops_tab, F, scheme, physics, evals_per_step):
     return per * 3 * F
 
 
+def _solver_for(hgks, name, mesh=None, **extra):
+    """Context, mesh and free stream of a workload with its start state set."""
+    from inputs import freestream_prim, mesh_for_config, perturbed_state, uniform_state
+    w = WORKLOADS[name]
+    mesh = mesh if mesh is not None else mesh_for_config(name)
+    prim = freestream_prim(w["mach"])
+    opts = dict(w["opts"])
+    if w["ramp"]:
+        opts.update(cfl_start=w["ramp"][0], cfl_growth=w["ramp"][1])
+    opts.update(extra)
+    t0 = time.time()
+    s = hgks.Solver(mesh, w["kinds"], prim, **opts)
+    t_setup = time.time() - t0
+    if w["start"] == "perturbed":
+        s.set_state(perturbed_state(s.N, prim, seed=1))
+    else:
+        s.set_state(uniform_state(s.N, prim), np.zeros((15, s.N)) if opts.get("scheme") == 1 else None)
+    return s, mesh, prim, opts, t_setup
+
+
+def _cfl_after(opts, steps):
+    """CFL number after `steps` steps of the solve_steady ramp."""
+    cfl = opts.get("cfl", 10.0)
+    if not opts.get("cfl_start"):
+        return cfl
+    return min(cfl, opts["cfl_start"] * max(1.0, opts.get("cfl_growth", 1.5)) ** steps)
+
+
+def measure_steps(torch, hgks, name, steps, warmup, mesh=None, chain=True):
+    """Throughput of `steps` implicit steps after `warmup` (the warm-up runs
+    the workload's CFL ramp through solve_steady), per-launch times of the
+    residual kernels inside the timed region, the residual evaluation's
+    roofline, and the isolated residual chain."""
+    s, mesh, prim, opts, t_setup = _solver_for(hgks, name, mesh=mesh)
+    N, F = s.N, s.F
+    Nb = len(mesh.bfaces)
+    scheme = opts.get("scheme", 0)
+    physics = opts.get("physics", 0)
+    if warmup > 0:
+        if WORKLOADS[name]["ramp"]:
+            s.solve_steady(drop=1e-30, max_steps=warmup)
+        else:
+            for _ in range(warmup):
+                s.implicit_step()
+    torch.cuda.synchronize()
+    s.kernel_times()  # enables per-launch event timing and resets it
+    evals = 0
+    infos = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        info = s.implicit_step()
+        evals += info.n_resid_evals
+        infos.append(info)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    kt = s.kernel_times()
+    n_launch = int(kt.pop("evaluations"))
+    evals_per_step = evals // steps
+    flops_tab = {}
+    if os.path.exists(FLOPS_FILE):
+        with open(FLOPS_FILE) as f:
+            flops_tab = json.load(f)
+    kernels = {}
+    for k, ms in kt.items():
+        e = {"avg_ms": round(ms, 4)}
+        b = algorithmic_bytes(k, N, F, Nb, scheme)
+        if b is not None and ms > 0:
+            # the bytes of the kernel's own inputs and outputs (intermediate
+            # buffers of the five-kernel split included)
+            e["buffer_bytes"] = int(b)
+            e["buffer_GB/s"] = round(b / (ms * 1e-3) / 1e9, 1)
+        tr = traffic_for(name, k)
+        if tr is not None:
+            e["traffic"] = tr
+        if k == "flux":
+            fl = flux_flops_per_launch(flops_tab, F, scheme, physics, evals_per_step)
+            if fl is not None and ms > 0:
+                e["flop"] = int(fl)
+                e["TFLOP/s"] = round(fl / (ms * 1e-3) / 1e12, 2)
+                e["valu_frac"] = round(fl / (ms * 1e-3) / PEAK_FP64_VALU, 4)
+        kernels[k] = e
+    # the residual evaluation as a whole: method bytes of the scheme per cell
+    # over the summed per-launch times of its five kernels
+    res_ms = sum(kt.values())
+    mb = step_method_bytes(scheme, N, evals_per_step)
+    traffic = None
+    if all("traffic" in kernels.get(k, {}) for k in ("ghost", "recon", "side", "flux", "gather")):
+        traffic = int(sum(kernels[k]["traffic"] for k in ("ghost", "recon", "side", "flux", "gather")))
+    roof = {"kernel": "residual evaluation (ghost, recon, side, flux, gather kernels)", "bound": "hbm",
+            "achieved": round(mb / (res_ms * 1e-3) / 1e9, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+            "frac": round(mb / (res_ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4), "traffic": traffic,
+            "avg_ms": round(res_ms, 4), "launches": n_launch,
+            "per_launch": f"{int(mb)} method bytes per evaluation ({mb / N:.0f} B/cell x {N} cells)"}
+    if "flop" in kernels.get("flux", {}):
+        roof["flux_fp64_frac"] = kernels["flux"]["valu_frac"]
+    out = {"value": round(N * evals / elapsed / 1e6, 3), "ms_per_step": round(1e3 * elapsed / steps, 3),
+           "steps": steps, "warmup": warmup, "cells": N, "faces": F, "resid_evals_per_step": evals_per_step,
+           "cfl": round(_cfl_after(opts, warmup), 3), "roofline": roof, "kernels": kernels,
+           "res_first_last": [infos[0].res, infos[-1].res], "setup_s": round(t_setup, 2)}
+    if chain:
+        out["residual_chain"] = residual_chain(torch, s, N)
+    s.close()
+    return out, mesh, prim, opts
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--config", default="c2", choices=["c1", "c2"])
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--config", default="c4", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
-    ap.add_argument("--no-solve", action="store_true", help="skip the time-to-1e-8 solves")
+    ap.add_argument("--no-secondary", action="store_true", help="skip the other workloads")
+    ap.add_argument("--no-solve", action="store_true", help="skip the time-to-1e-8 solves and the variants")
     ap.add_argument("--solve-steps", type=int, default=400, help="step cap of each time-to-1e-8 solve")
+    ap.add_argument("--drop-steps", type=int, default=40,
+                    help="step cap of the headline workload's own runs towards a 1e-8 drop")
     ap.add_argument("--serving", action="store_true",
                     help="run the served request stream instead of the implicit-step throughput")
-    ap.add_argument("--requests", type=int, default=16, help="served requests")
+    ap.add_argument("--requests", type=int, default=64, help="served requests")
     ap.add_argument("--rate", type=float, default=0.5, help="request arrival rate (1/s)")
-    ap.add_argument("--max-cells", type=int, default=400_000, help="largest request (cells)")
-    ap.add_argument("--max-steps", type=int, default=400, help="step cap of a served solve")
+    ap.add_argument("--max-cells", type=int, default=2_000_000, help="largest request (cells)")
+    ap.add_argument("--max-steps", type=int, default=2000, help="step cap of a served solve")
     ap.add_argument("--slots", type=int, default=8, help="concurrently admitted requests")
-    ap.add_argument("--fp32-inner-serving", action="store_true",
-                    help="serve the FP32-inner form (default: plain FP64)")
+    ap.add_argument("--fp64-serving", action="store_true",
+                    help="serve the plain FP64 form (default: FP32 inner / FP64 outer)")
     ap.add_argument("--variants-only", action="store_true",
-                    help="only measure the first-order KFVS and LU-SGS variants on the benchmark mesh")
+                    help="only measure the first-order KFVS and LU-SGS variants on the 202,752-tet shell")
     ap.add_argument("--lusgs-steps", type=int, default=2000, help="step cap of the LU-SGS convergence run")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (counter calibration) and exit")
@@ -152,7 +320,7 @@ def main():
         sys.exit(2)
 
     import torch
-    from inputs import freestream_prim, mesh_for_config, perturbed_state, uniform_state
+    from inputs import mesh_for_config
     from paper_2304_09485_amd import hgks
 
     if not torch.cuda.is_available():
@@ -164,120 +332,75 @@ def main():
     if args.serving:
         serving_bench(hgks, args)
         return
-
     if args.variants_only:
         mesh = mesh_for_config("c2")
         print(json.dumps({"variants": variants_bench(hgks, mesh, len(mesh.bfaces), args.lusgs_steps)}), flush=True)
         return
-    if args.config == "c2":
-        mesh = mesh_for_config("c2")
-        mach, kinds, opts = 0.5, {1: hgks.SLIP_WALL, 2: hgks.FARFIELD}, dict(scheme=hgks.HWENO)
-        workload = "sphere shell, inviscid Mach 0.5, compact HWENO, 202,752 tets, FP64 implicit steps"
-    else:
-        mesh = mesh_for_config("c1")
-        mach, kinds, opts = 0.3, {t: hgks.FARFIELD for t in range(1, 7)}, dict(scheme=hgks.WENO)
-        workload = "unit cube, Euler Mach 0.3, non-compact WENO, 3,072 tets, FP64 implicit steps"
-    prim = freestream_prim(mach)
-    t0 = time.time()
-    s = hgks.Solver(mesh, kinds, prim, **opts)
-    t_setup = time.time() - t0
-    N, F = s.N, s.F
-    Nb = len(mesh.bfaces)
-    if args.config == "c2":
-        Q0 = uniform_state(N, prim)
-        s.set_state(Q0, np.zeros((15, N)))
-    else:
-        s.set_state(perturbed_state(N, prim, seed=1))
 
-    for _ in range(args.warmup):
-        s.implicit_step()
-    torch.cuda.synchronize()
-    s.kernel_times()  # enables per-launch event timing and resets it
-    evals = 0
-    infos = []
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        info = s.implicit_step()
-        evals += info.n_resid_evals
-        infos.append(info)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    kt = s.kernel_times()
-    n_launch = int(kt.pop("evaluations"))
-    value = N * evals / elapsed / 1e6
+    name = args.config
+    w = WORKLOADS[name]
+    print(f"# {name}: {w['desc']}", file=sys.stderr, flush=True)
+    head, mesh, prim, opts = measure_steps(torch, hgks, name, args.steps, args.warmup)
+    print(f"# {name}: {head['value']} Mcell-residual/s, {head['ms_per_step']} ms per step", file=sys.stderr,
+          flush=True)
 
-    # per-kernel rates; roofline of the dominant kernel
-    scheme = opts.get("scheme", 0)
-    physics = opts.get("physics", 0)
-    flops_tab = {}
-    if os.path.exists(FLOPS_FILE):
-        with open(FLOPS_FILE) as f:
-            flops_tab = json.load(f)
-    evals_per_step = evals // args.steps
-    kernels = {}
-    for k, ms in kt.items():
-        b = algorithmic_bytes(k, N, F, Nb, scheme)
-        e = {"avg_ms": round(ms, 4)}
-        if b is not None and ms > 0:
-            e["bytes"] = int(b)
-            e["GB/s"] = round(b / (ms * 1e-3) / 1e9, 1)
-            e["hbm_frac"] = round(b / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)
-        if k == "flux":
-            fl = flux_flops_per_launch(flops_tab, F, scheme, physics, evals_per_step)
-            if fl is not None and ms > 0:
-                e["flop"] = int(fl)
-                e["TFLOP/s"] = round(fl / (ms * 1e-3) / 1e12, 2)
-                e["valu_frac"] = round(fl / (ms * 1e-3) / PEAK_FP64_VALU, 4)
-        kernels[k] = e
-    dom = max(kt, key=kt.get)
-    d = kernels[dom]
-    if "TFLOP/s" in d and d["valu_frac"] >= d.get("hbm_frac", 0.0):
-        roof = {"kernel": dom, "bound": "alu", "achieved": d["TFLOP/s"], "peak": PEAK_FP64_VALU / 1e12,
-                "unit": "TFLOP/s", "frac": d["valu_frac"], "traffic": traffic_for(dom), "avg_ms": d["avg_ms"],
-                "launches": n_launch, "per_launch": f"{d['flop']} FP64 flop"}
-    else:
-        roof = {"kernel": dom, "bound": "hbm", "achieved": d["GB/s"], "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                "frac": d["hbm_frac"], "traffic": traffic_for(dom), "avg_ms": d["avg_ms"], "launches": n_launch,
-                "per_launch": f"{d['bytes']} algorithmic bytes"}
-
-    chain = residual_chain(torch, s, N)
+    secondary = {}
+    if not args.no_secondary:
+        for other in ("c2", "c3"):
+            if other == name:
+                continue
+            try:
+                r, _, _, _ = measure_steps(torch, hgks, other, steps=5, warmup=2)
+                r["workload"] = WORKLOADS[other]["desc"]
+                secondary[other] = r
+            except Exception as e:  # a workload that fails is reported, not fatal
+                secondary[other] = {"error": str(e)}
+            print(f"# secondary {other}: {secondary[other].get('value', secondary[other])}", file=sys.stderr,
+                  flush=True)
 
     solves = None
-    if not args.no_solve and args.config == "c2":
-        solves = time_to_drop(hgks, mesh, kinds, prim, args.solve_steps)
-
     variants = None
-    if not args.no_solve and args.config == "c2":
-        variants = variants_bench(hgks, mesh, Nb, args.lusgs_steps)
+    if not args.no_solve:
+        c2mesh = mesh_for_config("c2") if name != "c2" else mesh
+        from inputs import freestream_prim
+        solves = time_to_drop(hgks, c2mesh, WORKLOADS["c2"]["kinds"], freestream_prim(WORKLOADS["c2"]["mach"]),
+                              args.solve_steps)
+        if name in ("c3", "c4"):
+            solves += drop_runs(hgks, name, mesh, args.drop_steps)
+        variants = variants_bench(hgks, c2mesh, len(c2mesh.bfaces), args.lusgs_steps)
 
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(mesh, kinds, prim, opts, args.cpu_seconds)
+        cpu = cpu_baseline(mesh, w["kinds"], prim, w["opts"], args.cpu_seconds)
 
     out = {
         "metric": "Mcell-residual evals/s",
-        "value": round(value, 3),
+        "value": head["value"],
         "unit": "Mcell-residual/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(1e3 * elapsed / args.steps, 3),
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": workload, "cells": N, "faces": F, "resid_evals_per_step": evals // args.steps,
-                   "cfl": 10.0, "krylov_dim": 10, "restarts": 3, "jacobi_sweeps": 2},
-        "roofline": roof,
-        "kernels": kernels,
-        "residual_chain": chain,
+        "config": {"workload": w["desc"], "cells": head["cells"], "faces": head["faces"],
+                   "resid_evals_per_step": head["resid_evals_per_step"], "cfl": head["cfl"],
+                   "cfl_ramp": (f"from {w['ramp'][0]} x{w['ramp'][1]} per step over the warm-up steps, then held"
+                                if w["ramp"] else None),
+                   "max_update": w["opts"].get("max_update", 0.0),
+                   "krylov_dim": 10, "restarts": 3, "jacobi_sweeps": 2},
+        "roofline": head["roofline"],
+        "kernels": head["kernels"],
+        "residual_chain": head.get("residual_chain"),
+        "secondary": secondary,
         "cpu_baseline": cpu,
         "time_to_1e-8": solves,
         "variants": variants,
-        "res_first_last": [infos[0].res, infos[-1].res],
-        "setup_s": round(t_setup, 2),
+        "res_first_last": head["res_first_last"],
+        "setup_s": head["setup_s"],
     }
     print(json.dumps(out), flush=True)
 
@@ -294,7 +417,7 @@ def serving_bench(hgks, args):
     from inputs.requests import request_stream
     specs = request_stream(args.requests, args.rate, seed=5, n_max=args.max_cells)
     meshes = [sp.mesh() for sp in specs]
-    prec = hgks.FP32_INNER if args.fp32_inner_serving else hgks.FP64
+    prec = hgks.FP64 if args.fp64_serving else hgks.FP32_INNER
     budget = 200 << 30  # leave headroom of the 288 GB for the runtime
     srv = hgks.Server(budget, args.slots)
     t0 = time.perf_counter()
@@ -367,6 +490,28 @@ def time_to_drop(hgks, mesh, kinds, prim, max_steps):
                     "converged": bool(info.converged), "drop": info.drop, "setup_s": round(t_setup, 2)})
         s.close()
         print(f"# time to 1e-8: {out[-1]}", file=sys.stderr, flush=True)
+    return out
+
+
+def drop_runs(hgks, name, mesh, max_steps):
+    """The workload's own solve from the uniform free stream (with its
+    options: update limit, CFL ramp) towards a 1e-8 drop, plain FP64 and FP32
+    inner / FP64 outer, capped at max_steps: the drop reached, or the error
+    that stopped it."""
+    out = []
+    for form, extra in (("FP64", {}), ("FP32 inner / FP64 outer", {"precision": hgks.FP32_INNER})):
+        s, _, _, opts, t_setup = _solver_for(hgks, name, mesh=mesh, **extra)
+        t0 = time.perf_counter()
+        rec = {"form": f"{WORKLOADS[name]['desc'].split(', FP64')[0]}, {form}", "setup_s": round(t_setup, 2)}
+        try:
+            info = s.solve_steady(drop=1e-8, max_steps=max_steps)
+            rec.update(seconds=round(info.t_ms * 1e-3, 3), steps=info.steps, converged=bool(info.converged),
+                       drop=info.drop)
+        except hgks.HgksError as e:
+            rec.update(seconds=round(time.perf_counter() - t0, 3), converged=False, error=str(e))
+        s.close()
+        out.append(rec)
+        print(f"# {name} towards 1e-8: {rec}", file=sys.stderr, flush=True)
     return out
 
 
@@ -512,39 +657,46 @@ def cpu_model():
 
 
 def cpu_baseline(mesh, kinds, prim, opts, budget_s):
-    """The oracle as it stands, timed on the host cores on a bounded sample:
-    full residual evaluations of the same mesh and state, as many as fit the
-    time budget (at least one)."""
+    """The oracle as it stands, timed on the host cores on a bounded sample of
+    the same workload: face fluxes (reconstruction of both sides and the
+    gas-kinetic flux at the Gauss points, the whole cost of a residual but
+    the per-cell sum) of random batches of the mesh's faces, on the perturbed
+    state, as many batches as fit the time budget; a full residual evaluates
+    every face once, so cell-residuals per second = faces per second x N / F."""
     try:
         import oracle
     except Exception as e:  # pragma: no cover
         return {"error": str(e)}
-    from inputs import uniform_state
+    from inputs import perturbed_state
     oracle.build(force=False)
     cores = min(os.cpu_count() or 1, 16)
     oracle.set_threads(cores)
     o = oracle.Oracle(mesh, kinds, prim, **{k: v for k, v in opts.items()})
-    N = o.N
-    Q = uniform_state(N, prim)
-    G = np.zeros((15, N))
+    N, F = o.N, o.F
+    Q = perturbed_state(N, prim, amp=0.01, seed=1)
+    G = np.zeros((15, N)) if opts.get("scheme", 0) == 1 else None
+    dt = o.dt(Q)
+    rng = np.random.default_rng(0)
+    batch = min(F, 50_000)
     n = 0
     t0 = time.perf_counter()
     while True:
-        o.residual(Q, G=G, want_grad=opts.get("scheme", 0) == 1)
-        n += 1
-        if time.perf_counter() - t0 >= budget_s or n >= 50:
+        o.face_fluxes(Q, rng.choice(F, size=batch, replace=False), G=G, dt=dt)
+        n += batch
+        if time.perf_counter() - t0 >= budget_s or n >= 20 * F:
             break
     el = time.perf_counter() - t0
-    # the same oracle on one thread: one full evaluation
     oracle.set_threads(1)
+    b1 = min(F, 4_000)
     t1 = time.perf_counter()
-    o.residual(Q, G=G, want_grad=opts.get("scheme", 0) == 1)
+    o.face_fluxes(Q, rng.choice(F, size=b1, replace=False), G=G, dt=dt)
     el1 = time.perf_counter() - t1
     oracle.set_threads(cores)
-    return {"value": round(N * n / el / 1e6, 5), "unit": "Mcell-residual/s", "cores": cores, "kind": "oracle",
-            "sample": f"{n} full residual evaluation(s) of the same {N}-tet mesh and state, {el:.1f} s",
-            "single_thread": {"value": round(N / el1 / 1e6, 5), "cores": 1,
-                              "sample": f"1 full residual evaluation of the same mesh and state, {el1:.1f} s"},
+    return {"value": round(n / el * N / F / 1e6, 5), "unit": "Mcell-residual/s", "cores": cores, "kind": "oracle",
+            "sample": f"{n} face fluxes in random batches of {batch} of the {F} faces of the same {N}-cell mesh "
+                      f"(perturbed state), {el:.1f} s; rate = faces/s x N/F",
+            "single_thread": {"value": round(b1 / el1 * N / F / 1e6, 5), "cores": 1,
+                              "sample": f"{b1} random face fluxes of the same mesh and state, {el1:.1f} s"},
             "host": {"nproc": os.cpu_count(), "cpu_model": cpu_model()}}
 
 

@@ -97,6 +97,11 @@ typedef struct {
                             cfl_growth after every step up to cfl; 0 (default) = cfl
                             throughout, as in the paper */
   double cfl_growth;     /* default 1.5 */
+  double max_update;     /* 0 (default): Q^{n+1} = Q^n + dQ, as in the paper; theta > 0: each
+                            cell's dQ is scaled by the largest 2^-k (k <= 20) for which its
+                            density and pressure change by at most theta of their old values
+                            (a runtime policy for impulsive starts, e.g. 0.2; a steady state
+                            is a fixed point either way) */
   void* stream;          /* hipStream_t to run on; NULL = library-owned stream */
   /* Device allocator hook: every device buffer of a context (mesh data,
    * state, work space, Krylov basis), and so of every served request, comes
@@ -119,6 +124,7 @@ typedef struct {
   double gmres_rel;      /* last GMRES residual estimate / initial preconditioned norm */
   int64_t n_resid_evals; /* residual evaluations in the step (33 with m = 10, 3 restarts) */
   int64_t n_fallbacks;   /* face sides that fell back to first order (positivity) */
+  int64_t n_limited;     /* cells whose update max_update scaled */
   double t_ms;           /* wall time of the step */
 } hgks_step_info;
 

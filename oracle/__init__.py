@@ -55,12 +55,13 @@ class Options(ctypes.Structure):
                 ("tau_eps", ctypes.c_double), ("tau_C", ctypes.c_double), ("gamma_lin", ctypes.c_double),
                 ("weno_eps", ctypes.c_double), ("mu", ctypes.c_double), ("prandtl", ctypes.c_double),
                 ("fd_sigma", ctypes.c_double), ("cfl_flux", ctypes.c_double), ("jv_mode", ctypes.c_int32),
-                ("first_order", ctypes.c_int32), ("solver", ctypes.c_int32), ("compact_subs", ctypes.c_int32)]
+                ("first_order", ctypes.c_int32), ("solver", ctypes.c_int32), ("compact_subs", ctypes.c_int32),
+                ("max_update", ctypes.c_double)]
 
 
 class StepInfo(ctypes.Structure):
     _fields_ = [("res", ctypes.c_double), ("gmres_rel", ctypes.c_double),
-                ("n_resid_evals", ctypes.c_int64), ("n_fallbacks", ctypes.c_int64)]
+                ("n_resid_evals", ctypes.c_int64), ("n_fallbacks", ctypes.c_int64), ("n_limited", ctypes.c_int64)]
 
 
 _P = ctypes.POINTER
@@ -140,7 +141,7 @@ def default_options(**kw) -> Options:
     o = Options(scheme=WENO, physics=EULER, weights=0, krylov_dim=10, restarts=3, jacobi_sweeps=2,
                 gamma=1.4, cfl=10.0, tau_eps=0.1, tau_C=1.0, gamma_lin=0.025, weno_eps=1e-8,
                 mu=0.0, prandtl=1.0, fd_sigma=0.0, cfl_flux=1.0, jv_mode=0, first_order=0, solver=0,
-                compact_subs=0)
+                compact_subs=0, max_update=0.0)
     for k, v in kw.items():
         setattr(o, k, v)
     return o

@@ -1652,6 +1652,39 @@ static bool build_hex(orc_ctx& C, int64_t n_nodes, const double* xyz, int64_t n_
   return finish_mesh(C, open, n_bf, bf, btag, n_tags, kind_of_tag);
 }
 
+// Q^{n+1} = Q^n + dQ.  With max_update = theta > 0 (a runtime policy of the
+// library for impulsive starts, not in the paper) each cell's change is
+// scaled by the largest alpha = 2^-k, k = 0..20, for which its density and
+// pressure change by at most theta of their old values; a state with
+// L(Q) = 0 is a fixed point either way.  Returns the number of scaled cells.
+static int64_t apply_update(const orc_ctx& C, double* Q, const double* dQ) {
+  const int N = C.N;
+  const double th = C.o.max_update, g = C.o.gamma;
+  int64_t limited = 0;
+  for (int i = 0; i < N; ++i) {
+    V5 q, d;
+    for (int v = 0; v < 5; ++v) {
+      q[v] = Q[(size_t)v * N + i];
+      d[v] = dQ[(size_t)v * N + i];
+    }
+    double alpha = 1.0;
+    if (th > 0.0) {
+      const double p0 = to_prim(q, g).p;
+      for (int k = 0; k <= 20; ++k) {
+        V5 qn;
+        for (int v = 0; v < 5; ++v) qn[v] = q[v] + alpha * d[v];
+        const double pn = (g - 1.0) * (qn[4] - 0.5 * (qn[1] * qn[1] + qn[2] * qn[2] + qn[3] * qn[3]) / qn[0]);
+        if (std::fabs(qn[0] - q[0]) <= th * q[0] && std::fabs(pn - p0) <= th * p0) break;
+        if (k == 20) break;
+        alpha *= 0.5;
+      }
+      if (alpha < 1.0) ++limited;
+    }
+    for (int v = 0; v < 5; ++v) Q[(size_t)v * N + i] = q[v] + alpha * d[v];
+  }
+  return limited;
+}
+
 // ---------------------------------------------------------------------------
 // GMRES (Algorithm 1): left-preconditioned, restarted, MGS Arnoldi, Givens QR
 // ---------------------------------------------------------------------------
@@ -1668,7 +1701,7 @@ static int implicit_step(const orc_ctx& C, double* Q, double* G, orc_step_info* 
     // one LU-SGS solve of the approximate system per step
     std::vector<double> dQ(n);
     lusgs(C, Q, dt.data(), b.data(), dQ.data());
-    for (size_t k = 0; k < n; ++k) Q[k] += dQ[k];
+    info->n_limited = apply_update(C, Q, dQ.data());
     if (C.o.scheme == 1) std::copy(Gn.begin(), Gn.end(), G);
     info->gmres_rel = 0.0;
     info->n_resid_evals = evals;
@@ -1759,7 +1792,7 @@ static int implicit_step(const orc_ctx& C, double* Q, double* G, orc_step_info* 
       for (size_t k = 0; k < n; ++k) dQ[k] += yy[i] * V[i][k];
     last = std::fabs(gvec[jdone]);
   }
-  for (size_t k = 0; k < n; ++k) Q[k] += dQ[k];
+  info->n_limited = apply_update(C, Q, dQ.data());
   if (C.o.scheme == 1) std::copy(Gn.begin(), Gn.end(), G);
   info->gmres_rel = beta0 > 0 ? last / beta0 : 0.0;
   info->n_resid_evals = evals;

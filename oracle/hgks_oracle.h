@@ -49,6 +49,10 @@ typedef struct {
                             {i, i_1 or i_6, two consecutive lateral neighbours}, fitted from the
                             cell averages (the hexahedral compact choice of the sphere cases of
                             Sec. 5) */
+  double max_update;     /* 0: Q^{n+1} = Q^n + dQ (the paper); theta > 0: each cell's dQ scaled
+                            by the largest 2^-k (k <= 20) for which its density and pressure
+                            change by at most theta of their old values (a runtime policy of
+                            the library for impulsive starts; steady states are unchanged) */
 } orc_options;
 
 /* boundary kinds */
@@ -140,6 +144,7 @@ typedef struct {
   double gmres_rel;      /* final GMRES estimate / initial preconditioned norm */
   int64_t n_resid_evals;
   int64_t n_fallbacks;
+  int64_t n_limited;     /* cells whose update was scaled (max_update) */
 } orc_step_info;
 
 /* one implicit step (Algorithm 1 body); Q, gradQ updated in place */

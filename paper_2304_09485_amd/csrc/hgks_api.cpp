@@ -276,26 +276,27 @@ inline size_t n5(const hgks_ctx* ctx) { return (size_t)5 * ctx->H.N; }
 template <typename T, typename TO>
 void residual_pipeline(hgks_ctx* ctx, const DevMesh<T>& M, Work<T>& w, T* Qx, const T* dt, int mode, TO* out,
                        const TO* v, const TO* bb, const double* sigma, TO* gout, hipStream_t s) {
+  const Params& P = ctx->P;
   hipEvent_t* ev = next_events(ctx);
   if (ctx->o.scheme == HGKS_KFVS1) {
     // first order: the flux of the cell averages, no ghost, recon or side
     // stage (the four intervals before the flux stay empty)
     for (int k = 0; k < 4; ++k)
       if (ev) (void)hipEventRecord(ev[k], s);
-    launch_flux_kfvs<T>(M, ctx->P, Qx, w.ff, s);
+    launch_flux_kfvs<T>(M, P, Qx, w.ff, s);
     if (ev) (void)hipEventRecord(ev[4], s);
     launch_gather<T, TO>(M, mode, w.ff, w.fq, out, v, bb, dt, sigma, gout, s);
     if (ev) (void)hipEventRecord(ev[5], s);
     return;
   }
   if (ev) (void)hipEventRecord(ev[0], s);
-  launch_ghost<T>(M, ctx->P, Qx, (T*)nullptr, s);
+  launch_ghost<T>(M, P, Qx, (T*)nullptr, s);
   if (ev) (void)hipEventRecord(ev[1], s);
-  launch_recon<T>(M, ctx->P, Qx, w.Gx, w.coef, s);
+  launch_recon<T>(M, P, Qx, w.Gx, w.coef, s);
   if (ev) (void)hipEventRecord(ev[2], s);
-  launch_side<T>(M, ctx->P, Qx, w.coef, w.sv, ctx->flags, s);
+  launch_side<T>(M, P, Qx, w.coef, w.sv, ctx->flags, s);
   if (ev) (void)hipEventRecord(ev[3], s);
-  launch_flux<T>(M, ctx->P, w.sv, dt, w.ff, w.fq, mode == 2, s);
+  launch_flux<T>(M, P, w.sv, dt, w.ff, w.fq, mode == 2, s);
   if (ev) (void)hipEventRecord(ev[4], s);
   launch_gather<T, TO>(M, mode, w.ff, w.fq, out, v, bb, dt, sigma, gout, s);
   if (ev) (void)hipEventRecord(ev[5], s);
@@ -380,7 +381,7 @@ void precond_device(hgks_ctx* ctx, const double* r, double* out, hipStream_t s) 
 hgks_status prepare_base(hgks_ctx* ctx, bool want_grad, hipStream_t s) {
   const int N = ctx->H.N, NX = N + ctx->H.Nb;
   TRY(sync_kinds(ctx));
-  HIPCHK(hipMemsetAsync(ctx->flags, 0, 2 * sizeof(int), s));
+  HIPCHK(hipMemsetAsync(ctx->flags, 0, 3 * sizeof(int), s));
   expand_state(ctx, ctx->Qc, s);
   launch_ghost<double>(ctx->M, ctx->P, ctx->W64.Qx, (double*)nullptr, s);
   launch_dt<double>(ctx->M, ctx->P, ctx->cfl_now, ctx->W64.Qx, ctx->W64.dt, s);
@@ -487,7 +488,7 @@ hgks_status hgks_create(const hgks_options* opts, hgks_ctx** out) {
   if (!opts || !out) return HGKS_EINVAL;
   *out = nullptr;
   if (opts->krylov_dim < 1 || opts->krylov_dim > MAXM || opts->restarts < 1 || opts->jacobi_sweeps < 0 ||
-      !(opts->gamma > 1.0) || !(opts->cfl > 0.0) || opts->scheme < 0 || opts->scheme > 2 || opts->physics < 0 ||
+      !(opts->gamma > 1.0) || !(opts->cfl > 0.0) || !(opts->max_update >= 0.0) || opts->scheme < 0 || opts->scheme > 2 || opts->physics < 0 ||
       opts->physics > 1 || opts->precision < 0 || opts->precision > 1 || opts->jv_mode < 0 || opts->jv_mode > 1 ||
       opts->solver < HGKS_SOLVER_GMRES || opts->solver > HGKS_SOLVER_LUSGS || opts->compact_subs < 0 ||
       opts->compact_subs > HGKS_SUBS_HEX_WENO ||
@@ -847,8 +848,11 @@ hgks_status hgks_implicit_step(hgks_ctx* ctx, hgks_step_info* info) {
     ctx->err = "non-finite residual (NaN or Inf in L(Q^n) or its GMRES solve); the state was not updated";
     return HGKS_ESTATE;
   }
-  // Q^{n+1} = Q^n + dQ
-  launch_axpy_dev(ctx->dQ, ctx->Qc, n, ctx->sc + 4, 1.0, s);  // sc[4] = 1
+  // Q^{n+1} = Q^n + dQ, with the optional per-cell update limit
+  if (ctx->o.max_update > 0.0)
+    launch_update_limited(ctx->Qc, ctx->dQ, N, ctx->o.max_update, ctx->o.gamma, ctx->flags + 2, s);
+  else
+    launch_axpy_dev(ctx->dQ, ctx->Qc, n, ctx->sc + 4, 1.0, s);  // sc[4] = 1
   if (hw) {
     const int NX = N + ctx->H.Nb;
     for (int k = 0; k < 15; ++k)
@@ -856,7 +860,7 @@ hgks_status hgks_implicit_step(hgks_ctx* ctx, hgks_step_info* info) {
                             hipMemcpyDeviceToDevice, s));
     TRY(refresh_gradients(ctx, s));
   }
-  int flags[2] = {0, 0};
+  int flags[3] = {0, 0, 0};
   HIPCHK(hipMemcpyAsync(flags, ctx->flags, sizeof(flags), hipMemcpyDeviceToHost, s));
   expand_state(ctx, ctx->Qc, s);
   HIPCHK(hipStreamSynchronize(s));
@@ -868,6 +872,7 @@ hgks_status hgks_implicit_step(hgks_ctx* ctx, hgks_step_info* info) {
     info->gmres_rel = beta0 > 0 ? last / beta0 : 0.0;
     info->n_resid_evals = evals;
     info->n_fallbacks = flags[0];
+    info->n_limited = flags[2];
     info->t_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   }
   return check_state(ctx, s);

@@ -52,6 +52,8 @@ void launch_axpy_dot_chain(const double* pin, double* hout, const double* v, dou
                            double* pout, hipStream_t);
 void launch_axpy_dev(const double* x, double* y, size_t n, const double* a, double sgn, hipStream_t);
 void launch_scale_inv(const double* x, double* y, size_t n, const double* a, hipStream_t, const int* skip = nullptr);
+// Q += alpha_i dQ with the per-cell update limit th (counted in nlim[0])
+void launch_update_limited(double* Q, const double* dQ, int N, double th, double gamma, int* nlim, hipStream_t);
 // GMRES cycle bookkeeping on the device: G [(m+1) m + 2 m + m + 1] holds H,
 // the Givens rotations and g; st [3]: finished, non-finite, columns done
 void launch_gmres_start(const double* beta, double* G, int* st, int m, hipStream_t);

@@ -927,6 +927,34 @@ __global__ void __launch_bounds__(256) k_axpy_dev(const double* __restrict__ x, 
   y[k] += sgn * a[0] * x[k];
 }
 
+// Q += alpha_i dQ per cell, alpha_i the largest 2^-k (k <= 20) for which the
+// cell's density and pressure change by at most th of their old values (the
+// update limit of impulsive starts); cells with alpha_i < 1 are counted
+__global__ void __launch_bounds__(256) k_update_limited(double* __restrict__ Q, const double* __restrict__ dQ, int N,
+                                                        double th, double g, int* __restrict__ nlim) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  double q[5], d[5];
+#pragma unroll
+  for (int v = 0; v < 5; ++v) {
+    q[v] = Q[(size_t)v * N + i];
+    d[v] = dQ[(size_t)v * N + i];
+  }
+  const double p0 = (g - 1.0) * (q[4] - 0.5 * (q[1] * q[1] + q[2] * q[2] + q[3] * q[3]) / q[0]);
+  double a = 1.0;
+  for (int k = 0; k < 20; ++k) {
+    double qn[5];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) qn[v] = q[v] + a * d[v];
+    const double pn = (g - 1.0) * (qn[4] - 0.5 * (qn[1] * qn[1] + qn[2] * qn[2] + qn[3] * qn[3]) / qn[0]);
+    if (fabs(qn[0] - q[0]) <= th * q[0] && fabs(pn - p0) <= th * p0) break;
+    a *= 0.5;
+  }
+  if (a < 1.0) atomicAdd(nlim, 1);
+#pragma unroll
+  for (int v = 0; v < 5; ++v) Q[(size_t)v * N + i] = q[v] + a * d[v];
+}
+
 // y = x / a[0]; nothing if skip[0] is set (a finished GMRES cycle)
 __global__ void __launch_bounds__(256) k_scale_inv(const double* __restrict__ x, double* __restrict__ y, size_t n,
                                                    const double* __restrict__ a, const int* __restrict__ skip) {
@@ -1103,18 +1131,15 @@ void launch_recon(const DevMesh<T>& M, const Params& P, const T* Qx, const T* Gx
 template <typename T>
 void launch_side(const DevMesh<T>& M, const Params& P, const T* Qx, const T* coef, T* sv, int* nfall,
                  hipStream_t s) {
-  const dim3 b(SIDE_THREADS);
+  const dim3 b(SIDE_THREADS), g(nblk(2 * (size_t)M.F, SIDE_SPB));
   if (M.nf == 4) {
-    hipLaunchKernelGGL((k_side<T, 4, 3, 1>), dim3(nblk(2 * (size_t)M.F, SIDE_SPB)), b, 0, s, M, P, Qx, coef, sv,
-                       nfall);
-  } else {
+    hipLaunchKernelGGL((k_side<T, 4, 3, 1>), g, b, 0, s, M, P, Qx, coef, sv, nfall);
+  } else if (P.scheme == 1 && !P.csubs) {
     // quadrilateral faces: one lane per side, its 4 Gauss points evaluated
     // from the combined polynomials after the component loop
-    const dim3 g(nblk(2 * (size_t)M.F, SIDE_SPB));
-    if (P.scheme == 1 && !P.csubs)
-      hipLaunchKernelGGL((k_side<T, 6, 4, 1>), g, b, 0, s, M, P, Qx, coef, sv, nfall);
-    else
-      hipLaunchKernelGGL((k_side<T, 8, 4, 1>), g, b, 0, s, M, P, Qx, coef, sv, nfall);
+    hipLaunchKernelGGL((k_side<T, 6, 4, 1>), g, b, 0, s, M, P, Qx, coef, sv, nfall);
+  } else {
+    hipLaunchKernelGGL((k_side<T, 8, 4, 1>), g, b, 0, s, M, P, Qx, coef, sv, nfall);
   }
 }
 template <typename T>
@@ -1253,6 +1278,9 @@ void launch_axpy_dot_chain(const double* pin, double* hout, const double* v, dou
 }
 void launch_axpy_dev(const double* x, double* y, size_t n, const double* a, double sgn, hipStream_t s) {
   hipLaunchKernelGGL(k_axpy_dev, dim3(nblk(n, 256)), dim3(256), 0, s, x, y, n, a, sgn);
+}
+void launch_update_limited(double* Q, const double* dQ, int N, double th, double gamma, int* nlim, hipStream_t s) {
+  hipLaunchKernelGGL(k_update_limited, dim3(nblk((size_t)N, 256)), dim3(256), 0, s, Q, dQ, N, th, gamma, nlim);
 }
 void launch_scale_inv(const double* x, double* y, size_t n, const double* a, hipStream_t s, const int* skip) {
   hipLaunchKernelGGL(k_scale_inv, dim3(nblk(n, 256)), dim3(256), 0, s, x, y, n, a, skip);

@@ -51,6 +51,7 @@ class Options(ctypes.Structure):
                 ("tau_C", ctypes.c_double), ("gamma_lin", ctypes.c_double), ("weno_eps", ctypes.c_double),
                 ("mu", ctypes.c_double), ("prandtl", ctypes.c_double), ("fd_sigma", ctypes.c_double),
                 ("cfl_flux", ctypes.c_double), ("cfl_start", ctypes.c_double), ("cfl_growth", ctypes.c_double),
+                ("max_update", ctypes.c_double),
                 ("stream", ctypes.c_void_p), ("dev_alloc", ctypes.c_void_p), ("dev_free", ctypes.c_void_p),
                 ("alloc_user", ctypes.c_void_p)]
 
@@ -87,7 +88,8 @@ def torch_allocator_hook():
 
 class StepInfo(ctypes.Structure):
     _fields_ = [("res", ctypes.c_double), ("res_rel", ctypes.c_double), ("gmres_rel", ctypes.c_double),
-                ("n_resid_evals", ctypes.c_int64), ("n_fallbacks", ctypes.c_int64), ("t_ms", ctypes.c_double)]
+                ("n_resid_evals", ctypes.c_int64), ("n_fallbacks", ctypes.c_int64), ("n_limited", ctypes.c_int64),
+                ("t_ms", ctypes.c_double)]
 
 
 class SolveInfo(ctypes.Structure):

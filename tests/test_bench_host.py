@@ -32,11 +32,31 @@ def test_traffic_lookup_follows_the_sources_hash():
     import bench
     h = bench.kernel_source_hash()
     assert len(h) == 16
-    with open(bench.TRAFFIC_FILE) as f:
-        lines = [ln.split() for ln in f if ln.startswith("traffic ")]
-    assert lines, "no traffic lines"
-    for p in lines:
-        if p[3] == h:
-            assert bench.traffic_for(p[1]) == int(float(p[2]))
-        else:
-            assert bench.traffic_for(p[1]) is None
+    seen = 0
+    for wl, path in bench.TRAFFIC_FILES.items():
+        if not os.path.exists(path):
+            continue
+        with open(path) as f:
+            lines = [ln.split() for ln in f if ln.startswith("traffic ")]
+        assert lines, f"no traffic lines in {path}"
+        for p in lines:
+            seen += 1
+            if p[3] == h:
+                assert bench.traffic_for(wl, p[1]) == int(float(p[2]))
+            else:
+                assert bench.traffic_for(wl, p[1]) is None
+    assert seen > 0
+    assert bench.traffic_for("no such workload", "side") is None
+
+
+def test_method_bytes_follow_the_scheme_table():
+    """Per-cell method bytes of one residual evaluation: about 2.26 KB for the
+    non-compact scheme and 2.25 KB for the compact base evaluation, 80 B more
+    (non-compact) or 40 B less (compact) as an FD product."""
+    import bench
+    assert bench.method_bytes_per_cell(0, False) == 2256
+    assert bench.method_bytes_per_cell(0, True) == 2336
+    assert bench.method_bytes_per_cell(1, False) == 2248
+    assert bench.method_bytes_per_cell(1, True) == 2208
+    # an implicit step of 33 evaluations: the base one and 32 FD products
+    assert bench.step_method_bytes(0, 10, 33) == 10 * (2256 + 32 * 2336) / 33

@@ -274,3 +274,46 @@ def test_sampled_residual_equals_full(oracle_lib, scheme):
     cells = np.random.default_rng(2).choice(o.N, 50, replace=False)
     Rs, Gs = o.residual_cells(Q, cells, G=G, want_grad=True)
     assert np.array_equal(Rs, R[:, cells]) and np.array_equal(Gs, Gn[:, cells])
+
+
+def test_update_limit(oracle_lib):
+    """max_update = theta: the step's change of every cell is the unlimited
+    change times a power of two 2^-k (k <= 20), the largest for which density
+    and pressure move by at most theta of their old values (a Mach 2 ramp at
+    CFL 10 from the uniform stream, where the unlimited step changes some
+    cells by far more than theta); with theta large nothing is scaled."""
+    from inputs import ramp_mesh
+    m = ramp_mesh(16, 6, 4, jitter=0.02, seed=4)
+    kinds = {1: 3, 2: 4, 3: 1, 4: 1, 5: 1, 6: 1}
+    prim = freestream_prim(2.0)
+    Q0 = uniform_state(m.n_cells, prim)
+    full = Q0.copy()
+    ofull = oracle_lib.Oracle(m, kinds, prim, cfl=10.0, jv_mode=1)
+    ofull.implicit_step(full)
+    lim = Q0.copy()
+    st, info = oracle_lib.Oracle(m, kinds, prim, cfl=10.0, jv_mode=1, max_update=0.2).implicit_step(lim)
+    assert st == 0 and info.n_limited > 0
+    d_full, d_lim = full - Q0, lim - Q0
+
+    def pres(q):
+        return 0.4 * (q[4] - 0.5 * (q[1] ** 2 + q[2] ** 2 + q[3] ** 2) / q[0])
+    p0 = pres(Q0)
+    scaled = 0
+    for i in range(m.n_cells):
+        k = np.argmax(np.abs(d_full[:, i]))
+        a = d_lim[k, i] / d_full[k, i] if d_full[k, i] != 0 else 1.0
+        e = np.round(-np.log2(a))
+        assert 0 <= e <= 20 and abs(a - 2.0 ** -e) <= 1e-12 * a
+        a = 2.0 ** -e
+        np.testing.assert_allclose(d_lim[:, i], a * d_full[:, i], rtol=0, atol=1e-14 * np.abs(Q0[:, i]).max())
+        ok = lambda al: (abs(al * d_full[0, i]) <= 0.2 * Q0[0, i]  # noqa: E731
+                         and abs(pres(Q0[:, [i]] + al * d_full[:, [i]])[0] - p0[i]) <= 0.2 * p0[i])
+        if e < 20:
+            assert ok(a)
+        if e > 0:
+            assert not ok(2 * a)
+            scaled += 1
+    assert scaled == info.n_limited
+    big = Q0.copy()
+    oracle_lib.Oracle(m, kinds, prim, cfl=10.0, jv_mode=1, max_update=1e6).implicit_step(big)
+    assert np.array_equal(big, full)
