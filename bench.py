@@ -50,7 +50,8 @@ FLOPS_FILE = os.path.join(ROOT, "paper_2304_09485_amd", "flux_flops.json")
 # sources the counters were taken with
 TRAFFIC_FILES = {"c2": os.path.join(ROOT, "profiles", "hbm_traffic_c2_hweno.md"),
                  "c4": os.path.join(ROOT, "profiles", "hbm_traffic_c4_weno.md")}
-KERNEL_SOURCES = ["hgks_kernels.hip", "side_kernel.h", "gks_flux.h", "hgks_device.h", "hgks_kernels.h"]
+KERNEL_SOURCES = ["hgks_kernels.hip", "side_kernel.h", "gks_flux.h", "hgks_device.h",
+                  "hgks_kernels.h"]
 
 # the workloads (boundary kinds: 0 far field, 1 slip wall, 2 no-slip
 # adiabatic wall, 3 supersonic inflow, 4 supersonic outflow)
@@ -304,7 +305,7 @@ def main():
     ap.add_argument("--requests", type=int, default=64, help="served requests")
     ap.add_argument("--rate", type=float, default=0.5, help="request arrival rate (1/s)")
     ap.add_argument("--max-cells", type=int, default=2_000_000, help="largest request (cells)")
-    ap.add_argument("--max-steps", type=int, default=2000, help="step cap of a served solve")
+    ap.add_argument("--max-steps", type=int, default=200, help="step cap of a served solve")
     ap.add_argument("--slots", type=int, default=8, help="concurrently admitted requests")
     ap.add_argument("--fp64-serving", action="store_true",
                     help="serve the plain FP64 form (default: FP32 inner / FP64 outer)")
@@ -369,6 +370,14 @@ def main():
             solves += drop_runs(hgks, name, mesh, args.drop_steps)
         variants = variants_bench(hgks, c2mesh, len(c2mesh.bfaces), args.lusgs_steps)
 
+    served = None
+    if not args.no_solve:
+        # the request stream's first 8 arrivals, meshes up to 200k cells, 120
+        # steps at most: a short served run for the record (the full stream is
+        # bench.py --serving)
+        served = serve_stream(hgks, 8, args.rate, 200_000, 120, args.slots)
+        served.pop("per_request", None)
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(mesh, w["kinds"], prim, w["opts"], args.cpu_seconds)
@@ -399,6 +408,7 @@ def main():
         "cpu_baseline": cpu,
         "time_to_1e-8": solves,
         "variants": variants,
+        "serving_short": served,
         "res_first_last": head["res_first_last"],
         "setup_s": head["setup_s"],
     }
@@ -406,33 +416,41 @@ def main():
 
 
 def serving_bench(hgks, args):
+    """The served request stream (--serving): prints its JSON line."""
+    out = serve_stream(hgks, args.requests, args.rate, args.max_cells, args.max_steps, args.slots,
+                       fp64=args.fp64_serving)
+    print(json.dumps(out), flush=True)
+
+
+def serve_stream(hgks, n_requests, rate, max_cells, max_steps, slots, fp64=False):
     """The served request stream: seeded requests (sphere shell or ramp
     channel, log-uniform cell counts, Mach 0.2-2, Euler or NS) arrive as a
     Poisson process and are submitted to the server as they arrive; each is
-    solved from the free stream to a 1e-8 residual drop (or the step cap).
-    Reports time-to-steady percentiles (arrival to result) and throughput over
-    the makespan.  Meshes are generated before the clock starts (the client
-    side of a request)."""
+    solved from the free stream towards a 1e-8 residual drop (or the step
+    cap) with the update limit of impulsive starts.  Reports time-to-steady
+    percentiles (arrival to result), the fraction converged and throughput
+    over the makespan.  Meshes are generated before the clock starts (the
+    client side of a request)."""
     from inputs import freestream_prim
     from inputs.requests import request_stream
-    specs = request_stream(args.requests, args.rate, seed=5, n_max=args.max_cells)
+    specs = request_stream(n_requests, rate, seed=5, n_max=max_cells)
     meshes = [sp.mesh() for sp in specs]
-    prec = hgks.FP64 if args.fp64_serving else hgks.FP32_INNER
+    prec = hgks.FP64 if fp64 else hgks.FP32_INNER
     budget = 200 << 30  # leave headroom of the 288 GB for the runtime
-    srv = hgks.Server(budget, args.slots)
+    srv = hgks.Server(budget, slots)
     t0 = time.perf_counter()
     tickets = []
     for sp, m in zip(specs, meshes):
         delay = sp.arrival_s - (time.perf_counter() - t0)
         if delay > 0:
             time.sleep(delay)
-        # impulsive starts (supersonic ramps, no-slip walls) ramp the CFL
-        # number from 1 to 10 over the first steps
-        opts = dict(scheme=hgks.WENO, precision=prec, cfl_start=1.0, cfl_growth=1.5)
+        # impulsive starts (supersonic ramps, no-slip walls): each cell's
+        # update is limited to a 20 % change of density and pressure
+        opts = dict(scheme=hgks.WENO, precision=prec, max_update=0.2)
         if sp.viscous:
             opts.update(physics=hgks.NS, mu=sp.mach / sp.reynolds, prandtl=0.72)
         tickets.append(srv.submit(m, sp.boundary_kinds(), freestream_prim(sp.mach), drop=1e-8,
-                                  max_steps=args.max_steps, **opts))
+                                  max_steps=max_steps, **opts))
         print(f"# submitted request {sp.index}: {sp.kind} {m.n_cells} cells Mach {sp.mach:.2f} "
               f"{'NS' if sp.viscous else 'Euler'} at {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
     res = []
@@ -446,7 +464,13 @@ def serving_bench(hgks, args):
     lat = np.array([r.t_total_ms for r in res]) * 1e-3
     conv = [r.status == 0 for r in res]
     cell_evals = sum(r.n_cells * r.n_resid_evals for r in res)
-    out = {
+    kinds = {}
+    for sp, r in zip(specs, res):
+        key = f"{sp.kind}, {'NS' if sp.viscous else 'Euler'}, {'supersonic' if sp.mach > 1 else 'subsonic'}"
+        k = kinds.setdefault(key, {"requests": 0, "converged": 0})
+        k["requests"] += 1
+        k["converged"] += int(r.status == 0)
+    return {
         "metric": "p50/p99 solve latency (served stream)",
         "value": round(float(np.percentile(lat, 50)), 3),
         "unit": "s",
@@ -455,16 +479,16 @@ def serving_bench(hgks, args):
         "higher_is_better": False,
         "throughput": {"Mcell-residual/s": round(cell_evals / makespan / 1e6, 3),
                        "solves/s": round(len(res) / makespan, 4), "makespan_s": round(makespan, 2)},
-        "requests": len(res), "converged": int(sum(conv)),
-        "dtype": "f32 inner / f64 outer" if prec == hgks.FP32_INNER else "f64",
+        "requests": len(res), "converged": int(sum(conv)), "by_kind": kinds,
+        "dtype": "f64" if fp64 else "f32 inner / f64 outer",
         "data": "synthetic",
-        "config": {"workload": f"{len(res)} Poisson requests at {args.rate}/s, shell or ramp tet meshes of "
-                               f"50k-{args.max_cells // 1000}k cells, Mach 0.2-2, Euler or NS, WENO, drop 1e-8, "
-                               f"cap {args.max_steps} steps", "slots": args.slots},
-        "per_request": [{"cells": r.n_cells, "status": r.status, "steps": r.steps, "t_total_s": round(r.t_total_ms * 1e-3, 3),
+        "config": {"workload": f"{len(res)} Poisson requests at {rate}/s, shell or ramp tet meshes of "
+                               f"50k-{max_cells // 1000}k cells, Mach 0.2-2, Euler or NS, WENO, drop 1e-8, "
+                               f"cap {max_steps} steps, update limit 0.2", "slots": slots},
+        "per_request": [{"cells": r.n_cells, "status": r.status, "steps": r.steps,
+                         "drop": r.res_final / max(r.res0, 1e-300), "t_total_s": round(r.t_total_ms * 1e-3, 3),
                          "t_queue_s": round(r.t_queue_ms * 1e-3, 3)} for r in res],
     }
-    print(json.dumps(out), flush=True)
 
 
 def time_to_drop(hgks, mesh, kinds, prim, max_steps):

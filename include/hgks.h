@@ -87,7 +87,7 @@ typedef struct {
   double tau_eps;        /* 0.1, inviscid collision time, Sec. 5 */
   double tau_C;          /* 1, pressure-jump term of the collision time, Sec. 5 */
   double gamma_lin;      /* 0.025, linear weights gamma_m, Sec. 3.4 */
-  double weno_eps;       /* 1e-8, epsilon of the nonlinear weights */
+  double weno_eps;       /* 1e-5, epsilon of the nonlinear weights (Sec. 3.4 leaves it open) */
   double mu;             /* dynamic viscosity (NS) */
   double prandtl;        /* Prandtl number (NS), 1 = plain BGK */
   double fd_sigma;       /* FD step of Eq. (frechet); 0 = sqrt(eps) max(1,rms Q)/rms v */

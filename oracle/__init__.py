@@ -139,7 +139,7 @@ def _f64(a):
 
 def default_options(**kw) -> Options:
     o = Options(scheme=WENO, physics=EULER, weights=0, krylov_dim=10, restarts=3, jacobi_sweeps=2,
-                gamma=1.4, cfl=10.0, tau_eps=0.1, tau_C=1.0, gamma_lin=0.025, weno_eps=1e-8,
+                gamma=1.4, cfl=10.0, tau_eps=0.1, tau_C=1.0, gamma_lin=0.025, weno_eps=1e-5,
                 mu=0.0, prandtl=1.0, fd_sigma=0.0, cfl_flux=1.0, jv_mode=0, first_order=0, solver=0,
                 compact_subs=0, max_update=0.0)
     for k, v in kw.items():

@@ -33,7 +33,7 @@ typedef struct {
   double tau_eps;        /* 0.1 */
   double tau_C;          /* 1 */
   double gamma_lin;      /* 0.025 */
-  double weno_eps;       /* 1e-8 */
+  double weno_eps;       /* 1e-5 (reading A8) */
   double mu;             /* dynamic viscosity (NS) */
   double prandtl;        /* NS */
   double fd_sigma;       /* 0 = automatic */

@@ -474,7 +474,7 @@ void hgks_default_options(hgks_options* o) {
   o->tau_eps = 0.1;
   o->tau_C = 1.0;
   o->gamma_lin = 0.025;
-  o->weno_eps = 1e-8;
+  o->weno_eps = 1e-5;
   o->mu = 0.0;
   o->prandtl = 1.0;
   o->fd_sigma = 0.0;

@@ -58,19 +58,20 @@ def test_converged_state_is_an_oracle_steady_state(oracle_lib, c2):
         oracle_lib.set_threads(1)
 
 
-def test_fp32_inner_reaches_the_same_drop_with_linear_weights(c2):
-    """With linear weights the FP32-inner / FP64-outer form converges like the
-    plain FP64 form: same 1e-8 drop, step counts within 5 %, and the two
-    converged states agree to the accuracy the drop allows."""
+def test_fp32_inner_reaches_the_same_drop(c2):
+    """With the scheme's nonlinear weights the FP32-inner / FP64-outer form
+    converges like the plain FP64 form: the same 1e-8 drop, step counts
+    within 10 %, and the two converged states agree within 1e-9 relative
+    (both are the fixed point of the same FP64 residual)."""
     from paper_2304_09485_amd import hgks
-    i64, Q64 = _solve(hgks, c2, weights=hgks.WEIGHTS_LINEAR)
-    i32, Q32 = _solve(hgks, c2, weights=hgks.WEIGHTS_LINEAR, precision=hgks.FP32_INNER)
+    i64, Q64 = _solve(hgks, c2)
+    i32, Q32 = _solve(hgks, c2, precision=hgks.FP32_INNER)
     diff = np.abs(Q64 - Q32).max() / np.abs(Q64).max()
     print(f"FP64: {i64.steps} steps {i64.t_ms / 1e3:.2f} s; FP32-inner: {i32.steps} steps {i32.t_ms / 1e3:.2f} s; "
           f"field difference {diff:.3e}")
     assert i64.converged and i32.converged
-    assert abs(i32.steps - i64.steps) <= 0.05 * i64.steps + 1
-    assert diff <= 1e-6
+    assert abs(i32.steps - i64.steps) <= 0.1 * i64.steps + 1
+    assert diff <= 1e-9
 
 
 def test_fp32_inner_product_matches_fp64_at_fixed_step():

@@ -8,7 +8,7 @@ arithmetic that does not come from the oracle.
   |Omega|^(2|l|/3 - 1) factors and every distinct multi-index once;
 * the weights (Sec. 3.4): from those betas by the WENO-Z type formula with
   tau_Z = sum_m |beta_0 - beta_m| / M; on a contact discontinuity every
-  sub-stencil that reaches across it gets a weight below 1e-3, and so does
+  sub-stencil that reaches across it gets a weight below 1e-2, and so does
   P0, while the sub-stencils on one side carry the weight;
 * R* (Sec. 5): J_x(Q*) R* = R* diag(u - c, u, u, u, u + c) with the x-split
   Euler Jacobian taken by complex steps, at Q* = the mean of the two cell
@@ -137,7 +137,7 @@ def test_smoothness_indicators_vs_quadrature(oracle_lib, smooth_case, scheme):
     assert checked > 24 * 5 * 3
 
 
-def _weights_from_betas(beta, M, gam=0.025, eps=1e-8):
+def _weights_from_betas(beta, M, gam, eps):
     b0, bm = beta[0], beta[1:1 + M]
     tz = np.sum(np.abs(b0 - bm)) / M
     g0 = 1.0 - gam * M
@@ -158,14 +158,15 @@ def test_weights_from_pinned_betas(oracle_lib, smooth_case, scheme):
         d = o.side_debug(Q, f, side, G=G)
         for c in range(5):
             M = int(d["M"][c])
-            w, tz = _weights_from_betas(d["beta"][c], M)
+            w, tz = _weights_from_betas(d["beta"][c], M, o.opts.gamma_lin, o.opts.weno_eps)
             assert abs(d["tau"][c] - tz) <= 1e-12 * max(tz, 1e-300) + 1e-300
             assert np.allclose(d["w"][c, :M + 1], w, rtol=1e-12, atol=1e-15), (f, side, c)
             assert abs(d["w"][c, :M + 1].sum() - 1.0) < 1e-14
             # the same with tau_Z summed without 1/M
             b0, bm = d["beta"][c, 0], d["beta"][c, 1:1 + M]
             tzM = np.sum(np.abs(b0 - bm))
-            wt = np.concatenate([[(1 - 0.025 * M) * (1 + tzM / (b0 + 1e-8))], 0.025 * (1 + tzM / (bm + 1e-8))])
+            eps = o.opts.weno_eps
+            wt = np.concatenate([[(1 - 0.025 * M) * (1 + tzM / (b0 + eps))], 0.025 * (1 + tzM / (bm + eps))])
             if np.abs(wt / wt.sum() - w).max() > 1e-3:
                 sensitive += 1
     assert sensitive >= 10
@@ -175,8 +176,10 @@ def test_crossing_sub_stencils_get_no_weight(oracle_lib):
     """A contact discontinuity (density jump at uniform velocity and pressure)
     across the plane x = 0.52: on every face side whose cell has at least one
     sub-stencil entirely on its own side, P0 and every sub-stencil that reaches
-    across the jump carry a weight below 1e-3 in the entropy component, the
-    only one the jump projects onto."""
+    across the jump carry a weight below 1e-2 in the entropy component, the
+    only one the jump projects onto, and the one-sided sub-stencils more than
+    0.98 (with epsilon = 1e-5 the crossing weights scale as epsilon / tau_Z,
+    a few 1e-3 for this jump)."""
     mesh = cube_mesh(6, jitter=0.1, seed=21)
     kinds = {t: FAR for t in range(1, 7)}
     prim = freestream_prim(0.3)
@@ -202,11 +205,11 @@ def test_crossing_sub_stencils_get_no_weight(oracle_lib):
                 continue
             d = o.side_debug(Q, f, side)
             w = d["w"][1]
-            assert w[0] < 1e-3, (f, side, w)
+            assert w[0] < 1e-2, (f, side, w)
             for m in range(4):
                 if d["ok"][1, m] and cross[m]:
-                    assert w[1 + m] < 1e-3, (f, side, m, w)
-            assert sum(w[1 + m] for m in range(4) if not cross[m]) > 0.99
+                    assert w[1 + m] < 1e-2, (f, side, m, w)
+            assert sum(w[1 + m] for m in range(4) if not cross[m]) > 0.98
             seen += 1
             if seen >= 40:
                 return

@@ -50,7 +50,7 @@ def test_server_reports_failed_requests_without_gpu():
 
 
 REQS = [
-    (lambda: shell_mesh(4, 4, grading=1.3, jitter=0.05, seed=11), {1: 1, 2: 0}, 0.5, dict(scheme=1)),
+    (lambda: shell_mesh(4, 4, grading=1.3, jitter=0.05, seed=11), {1: 1, 2: 0}, 0.5, dict(scheme=1, max_update=0.2)),
     (lambda: cube_mesh(6, jitter=0.1, seed=12), {k: 0 for k in range(1, 7)}, 0.3, dict()),
     (lambda: shell_mesh(4, 3, grading=1.4, jitter=0.05, seed=13), {1: 2, 2: 0}, 0.25,
      dict(physics=1, mu=0.25 / 118.0, prandtl=0.72, precision=1)),
