@@ -344,7 +344,17 @@ hgks_status jv_device(hgks_ctx* ctx, const double* v, double sigma_fixed, double
   launch_dot_part(v, v, n, ctx->part, s);  // partials of |v|^2, summed by the sigma kernel
   bool f32 = inner && ctx->o.precision == HGKS_FP32_INNER;
   double eps = f32 ? std::ldexp(1.0, -23) : std::ldexp(1.0, -52);
-  launch_sigma(ctx->part, ctx->sc + 0, (double)n, eps, sigma_fixed, ctx->sc + 2, s);
+  if (f32) {
+    // the FP32 step (sqrt(2^-23) relative) is large enough that a direction
+    // concentrated on a few cells could perturb them out of the physical
+    // states: cap it so that no cell's density or energy moves by more than
+    // 1 % of itself (the second half of the partials is free here)
+    launch_ratio_part(ctx->Qc, v, N, ctx->part + REDUCE_PARTS, s);
+    launch_sigma(ctx->part, ctx->sc + 0, (double)n, eps, sigma_fixed, ctx->sc + 2, s, ctx->part + REDUCE_PARTS,
+                 1e-2);
+  } else {
+    launch_sigma(ctx->part, ctx->sc + 0, (double)n, eps, sigma_fixed, ctx->sc + 2, s);
+  }
   if (!f32) {
     launch_perturb<double>(ctx->Qc, v, ctx->sc + 2, N, NX, ctx->Qp64, s);
     residual_pipeline<double, double>(ctx, ctx->M, ctx->W64, ctx->Qp64, ctx->W64.dt, 1, out, v, ctx->b,

@@ -62,9 +62,12 @@ void launch_gmres_solve(int m, const double* G, const int* st, double* y, double
 void launch_combine(const double* V, const double* c, int nv, size_t n, const double* x, double* y, hipStream_t);
 void launch_convert(const double* src, float* dst, size_t n, hipStream_t);
 // FD step of the Jv product from the block partials of |v|^2 (vpart) and the
-// reduced |Q|^2 (qq[0]) into sigma[0]
+// reduced |Q|^2 (qq[0]) into sigma[0]; with rpart (block maxima of
+// launch_ratio_part) the step is also capped at eta / max ratio
 void launch_sigma(const double* vpart, const double* qq, double n, double eps, double fixed, double* sigma,
-                  hipStream_t);
+                  hipStream_t, const double* rpart = nullptr, double eta = 0.0);
+// block maxima of max(|v_rho| / rho, |v_E| / E) over the cells into part[REDUCE_PARTS]
+void launch_ratio_part(const double* Q, const double* v, int N, double* part, hipStream_t);
 
 constexpr int REDUCE_PARTS = 1024;  // partials of a reduction
 

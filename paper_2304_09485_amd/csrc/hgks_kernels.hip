@@ -1074,11 +1074,47 @@ __global__ void __launch_bounds__(256) k_convert(const double* __restrict__ src,
 // automatic FD step of Eq. (frechet): sqrt(eps) max(1, rms Q) / rms v
 // (|v|^2 is summed here from its block partials, in the fixed order of
 // k_reduce_final, so no separate reduction launch precedes this one)
+// block maxima of the relative size of a direction v against the state Q:
+// max over cells of |v_rho| / rho and |v_E| / E (both positive in a
+// physical state)
+__global__ void __launch_bounds__(RB) k_ratio_part(const double* __restrict__ Q, const double* __restrict__ v, int N,
+                                                   double* __restrict__ part) {
+  double m = 0.0;
+  for (int i = blockIdx.x * RB + threadIdx.x; i < N; i += RGRID * RB) {
+    m = fmax(m, fabs(v[i]) / Q[i]);
+    m = fmax(m, fabs(v[4 * (size_t)N + i]) / Q[4 * (size_t)N + i]);
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_down(m, off, 64));
+  __shared__ double sh[RB / 64];
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = sh[0];
+#pragma unroll
+    for (int k = 1; k < RB / 64; ++k) t = fmax(t, sh[k]);
+    part[blockIdx.x] = t;
+  }
+}
+
 __global__ void __launch_bounds__(RB) k_sigma(const double* __restrict__ vpart, const double* __restrict__ qq,
-                                              double n, double eps, double fixed, double* __restrict__ sigma) {
+                                              double n, double eps, double fixed, double* __restrict__ sigma,
+                                              const double* __restrict__ rpart, double eta) {
   double s0 = 0.0;
   for (int k = threadIdx.x; k < RGRID; k += RB) s0 += vpart[k];
   const double vv = block_sum(s0);
+  // the largest relative perturbation of density and energy a unit step makes
+  double r = 0.0;
+  if (rpart) {
+    __syncthreads();
+    __shared__ double shr[RB];
+    double m = 0.0;
+    for (int k = threadIdx.x; k < RGRID; k += RB) m = fmax(m, rpart[k]);
+    shr[threadIdx.x] = m;
+    __syncthreads();
+    if (threadIdx.x == 0)
+      for (int k = 0; k < RB; ++k) r = fmax(r, shr[k]);
+  }
   if (threadIdx.x != 0) return;
   double rv = sqrt(vv / n);
   if (rv == 0.0) {
@@ -1090,7 +1126,10 @@ __global__ void __launch_bounds__(RB) k_sigma(const double* __restrict__ vpart, 
     return;
   }
   double rq = sqrt(qq[0] / n);
-  sigma[0] = sqrt(eps) * fmax(1.0, rq) / rv;
+  double sg = sqrt(eps) * fmax(1.0, rq) / rv;
+  // no cell's density or energy moves by more than eta of itself
+  if (r > 0.0) sg = fmin(sg, eta / r);
+  sigma[0] = sg;
 }
 
 template <typename T>
@@ -1301,8 +1340,11 @@ void launch_convert(const double* src, float* dst, size_t n, hipStream_t s) {
   if (n) hipLaunchKernelGGL(k_convert, dim3(nblk(n, 256)), dim3(256), 0, s, src, dst, n);
 }
 void launch_sigma(const double* vpart, const double* qq, double n, double eps, double fixed, double* sigma,
-                  hipStream_t s) {
-  hipLaunchKernelGGL(k_sigma, dim3(1), dim3(RB), 0, s, vpart, qq, n, eps, fixed, sigma);
+                  hipStream_t s, const double* rpart, double eta) {
+  hipLaunchKernelGGL(k_sigma, dim3(1), dim3(RB), 0, s, vpart, qq, n, eps, fixed, sigma, rpart, eta);
+}
+void launch_ratio_part(const double* Q, const double* v, int N, double* part, hipStream_t s) {
+  hipLaunchKernelGGL(k_ratio_part, dim3(RGRID), dim3(RB), 0, s, Q, v, N, part);
 }
 
 // Work space of the allocation-free residual entry point: one copy per GPU,
