@@ -97,6 +97,27 @@ def traffic_for(workload, kernel):
     return None
 
 
+SQ_FILES = {"c4": os.path.join(ROOT, "profiles", "sq_issue_c4_weno.md")}
+
+
+def valu_for(workload, kernel):
+    """FP64 rate, fraction of the FP64 vector peak and VALU-issuing share of
+    the kernel from the SQ instruction counters (rocprofv3), or None if none
+    were taken or the kernel sources changed since."""
+    path = SQ_FILES.get(workload)
+    if not path or not os.path.exists(path):
+        return None
+    want = kernel_source_hash()
+    with open(path) as f:
+        for line in f:
+            p = line.split()
+            # lines "valu <kernel> <FP64 TFLOP/s> <fraction of peak> <issue share> <source hash>"
+            if len(p) == 6 and p[0] == "valu" and p[1] == kernel and p[5] == want:
+                return {"fp64_TFLOP/s": float(p[2]), "fp64_frac": float(p[3]), "valu_issue_share": float(p[4]),
+                        "source": "SQ counters"}
+    return None
+
+
 def method_bytes_per_cell(scheme, jv):
     """Bytes per cell one residual evaluation of the method must move at
     least (stored-operator design, FP64, a cell's data read once and its
@@ -256,6 +277,9 @@ def measure_steps(torch, hgks, name, steps, warmup, mesh=None, chain=True):
         tr = traffic_for(name, k)
         if tr is not None:
             e["traffic"] = tr
+        sq = valu_for(name, k)
+        if sq is not None:
+            e["sq"] = sq
         if k == "flux":
             fl = flux_flops_per_launch(flops_tab, F, scheme, physics, evals_per_step)
             if fl is not None and ms > 0:
@@ -277,6 +301,10 @@ def measure_steps(torch, hgks, name, steps, warmup, mesh=None, chain=True):
             "per_launch": f"{int(mb)} method bytes per evaluation ({mb / N:.0f} B/cell x {N} cells)"}
     if "flop" in kernels.get("flux", {}):
         roof["flux_fp64_frac"] = kernels["flux"]["valu_frac"]
+    if "sq" in kernels.get("side", {}):
+        # the side kernel's own method bytes are small: its binding roof is
+        # the FP64 vector rate, measured by the instruction counters
+        roof["side_fp64_frac"] = kernels["side"]["sq"]["fp64_frac"]
     out = {"value": round(N * evals / elapsed / 1e6, 3), "ms_per_step": round(1e3 * elapsed / steps, 3),
            "steps": steps, "warmup": warmup, "cells": N, "faces": F, "resid_evals_per_step": evals_per_step,
            "cfl": round(_cfl_after(opts, warmup), 3), "roofline": roof, "kernels": kernels,

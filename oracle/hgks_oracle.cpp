@@ -860,6 +860,14 @@ static void gks_point(const orc_ctx& C, const V5& Wl, const V5 dWl[3], const V5&
     V5 a = Mlh.psi(0, 0, 0, 0), b = Mrh.psi(0, 0, 0, 0);
     for (int k = 0; k < 5; ++k) Q0[k] = l.rho * a[k] + r.rho * b[k];
   }
+  // vacuum interface (reading A34): the two half-space tails that reach the
+  // point carry less than 2^-40 of the adjacent densities; no flux, no
+  // point value
+  if (!(Q0[0] > std::ldexp(1.0, -40) * (l.rho + r.rho))) {
+    F = V5{0, 0, 0, 0, 0};
+    if (QG) *QG = V5{0, 0, 0, 0, 0};
+    return;
+  }
   Prim z = to_prim(Q0, g);
   M0.init(z.U, z.V, z.W, z.lam, K, 0);
   // slopes of the initial distributions in the three local directions

@@ -53,6 +53,7 @@ inline C operator/(C a, C b) {
   ++n_div;
   return C::val(a.v / b.v);
 }
+inline bool operator>(C a, C b) { return a.v > b.v; }  // a comparison, not counted
 inline C& operator+=(C& a, C b) { a = a + b; return a; }
 inline C& operator-=(C& a, C b) { a = a - b; return a; }
 inline C& operator*=(C& a, C b) { a = a * b; return a; }

@@ -312,6 +312,19 @@ HGKS_HD void gks_flux(const T Wl[5], const T dWl[3][5], const T Wr[5], const T d
     Q0[3] += rr * u[0] * M.w[1];
     Q0[4] += rr * T(0.5) * (u[2] + u[0] * (M.v[2] + M.w[2] + M.x2));
   }
+  // Two receding half-space tails that carry less than 2^-40 of the
+  // adjacent densities meet at this point: the interface is vacuum and
+  // transports nothing.  (Below that fraction the interface temperature,
+  // 1/rho0 and, for Navier-Stokes, tau = mu/p0 are dominated by rounding or
+  // overflow, while the exact flux is of that relative size.)
+  if (!(Q0[0] > T(1.0 / 1099511627776.0) * (rl + rr))) {
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+      F[k] = T(0);
+      if (want_qg) QG[k] = T(0);
+    }
+    return;
+  }
   T r0 = Q0[0], i0 = T(1) / r0, U0 = Q0[1] * i0, V0 = Q0[2] * i0, W0 = Q0[3] * i0;
   T p0 = (g - T(1)) * (Q0[4] - T(0.5) * r0 * (U0 * U0 + V0 * V0 + W0 * W0));
   T l0 = r0 / (T(2) * p0), h0 = p0 * i0;

@@ -347,8 +347,9 @@ hgks_status jv_device(hgks_ctx* ctx, const double* v, double sigma_fixed, double
   if (f32) {
     // the FP32 step (sqrt(2^-23) relative) is large enough that a direction
     // concentrated on a few cells could perturb them out of the physical
-    // states: cap it so that no cell's density or energy moves by more than
-    // 1 % of itself (the second half of the partials is free here)
+    // states: cap it so that no cell's density, momentum (against
+    // sqrt(rho E)) or energy moves by more than 1 % (the second half of the
+    // partials is free here)
     launch_ratio_part(ctx->Qc, v, N, ctx->part + REDUCE_PARTS, s);
     launch_sigma(ctx->part, ctx->sc + 0, (double)n, eps, sigma_fixed, ctx->sc + 2, s, ctx->part + REDUCE_PARTS,
                  1e-2);

@@ -66,7 +66,7 @@ void launch_convert(const double* src, float* dst, size_t n, hipStream_t);
 // launch_ratio_part) the step is also capped at eta / max ratio
 void launch_sigma(const double* vpart, const double* qq, double n, double eps, double fixed, double* sigma,
                   hipStream_t, const double* rpart = nullptr, double eta = 0.0);
-// block maxima of max(|v_rho| / rho, |v_E| / E) over the cells into part[REDUCE_PARTS]
+// block maxima of max(|v_rho| / rho, |v_m| / sqrt(rho E), |v_E| / E) over the cells into part[REDUCE_PARTS]
 void launch_ratio_part(const double* Q, const double* v, int N, double* part, hipStream_t);
 
 constexpr int REDUCE_PARTS = 1024;  // partials of a reduction

@@ -1075,14 +1075,18 @@ __global__ void __launch_bounds__(256) k_convert(const double* __restrict__ src,
 // (|v|^2 is summed here from its block partials, in the fixed order of
 // k_reduce_final, so no separate reduction launch precedes this one)
 // block maxima of the relative size of a direction v against the state Q:
-// max over cells of |v_rho| / rho and |v_E| / E (both positive in a
-// physical state)
+// max over cells of |v_rho| / rho, |v_m| / sqrt(rho E) and |v_E| / E (all
+// scales positive in a physical state; the momentum one bounds the change of
+// the kinetic energy by a fraction of E)
 __global__ void __launch_bounds__(RB) k_ratio_part(const double* __restrict__ Q, const double* __restrict__ v, int N,
                                                    double* __restrict__ part) {
   double m = 0.0;
   for (int i = blockIdx.x * RB + threadIdx.x; i < N; i += RGRID * RB) {
-    m = fmax(m, fabs(v[i]) / Q[i]);
-    m = fmax(m, fabs(v[4 * (size_t)N + i]) / Q[4 * (size_t)N + i]);
+    const double rho = Q[i], E = Q[4 * (size_t)N + i];
+    const double v1 = v[(size_t)N + i], v2 = v[2 * (size_t)N + i], v3 = v[3 * (size_t)N + i];
+    m = fmax(m, fabs(v[i]) / rho);
+    m = fmax(m, fabs(v[4 * (size_t)N + i]) / E);
+    m = fmax(m, sqrt((v1 * v1 + v2 * v2 + v3 * v3) / (rho * E)));
   }
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_down(m, off, 64));

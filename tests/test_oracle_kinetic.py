@@ -415,3 +415,49 @@ def test_discontinuous_flux_with_slopes_vs_quadrature(orc, seed):
         ref += w * f
     ref /= dt
     np.testing.assert_allclose(got, ref, rtol=1e-9, atol=1e-11)
+
+
+def _receding_pair(x, rng, mirror=True):
+    """Two states that both stream away from the face, the normal speed being
+    x thermal speeds (x = sqrt(lam) |U|): the left one towards -n, the right
+    one towards +n (a mirror pair is the slip-wall case)."""
+    rl, pl = rng.uniform(0.2, 1.5), rng.uniform(0.01, 1.0)
+    Ul = -x / np.sqrt(rl / (2 * pl))
+    Wl = I.cons(rl, [Ul, *rng.normal(size=2)], pl)
+    if mirror:
+        Wr = Wl * np.array([1, -1, 1, 1, 1])
+    else:
+        rr, pr = rng.uniform(0.2, 1.5), rng.uniform(0.01, 1.0)
+        Wr = I.cons(rr, [x / np.sqrt(rr / (2 * pr)), *rng.normal(size=2)], pr)
+    return Wl, Wr
+
+
+@pytest.mark.parametrize("physics", [0, 1])
+def test_vacuum_interface(orc, physics):
+    """Reading A34: where the half-space tails that reach the face carry less
+    than 2^-40 of the adjacent densities (checked here by quadrature of the
+    two tails, independently of the oracle's erfc), the face is vacuum and
+    its flux and point value are zero.  Just above that fraction the flux is
+    still of the size of the tails (zero slopes: below 1e-9 of the stream's
+    momentum flux), so the rule does not cut off anything the residual sums
+    would resolve."""
+    o = orc(physics=1, mu=0.006, prandtl=0.72) if physics else orc()
+    rng = np.random.default_rng(71 + physics)
+    z = np.zeros((3, 5))
+    for x, mirror in [(8.0, True), (9.0, False), (6.5, True)]:
+        Wl, Wr = _receding_pair(x, rng, mirror)
+        rl, Ul, pl, ll = lam_of(Wl)
+        rr, Ur, pr, lr = lam_of(Wr)
+        tail = rl * VQuad(*Ul, ll, +1).E(1.0)[0] + rr * VQuad(*Ur, lr, -1).E(1.0)[0]
+        assert tail < 2.0 ** -40 * (rl + rr)
+        d = rng.normal(size=(2, 3, 5))
+        F, QG = o.gks_point(Wl, d[0], Wr, d[1], 0.05, want_qg=True)
+        assert np.all(F == 0.0) and np.all(QG == 0.0)
+    if not physics:
+        # x = 4.8: tail fraction about 1e-11, above the cut
+        Wl, Wr = _receding_pair(4.8, rng, True)
+        rl, Ul, pl, ll = lam_of(Wl)
+        tail = 2 * rl * VQuad(*Ul, ll, +1).E(1.0)[0]
+        assert 2.0 ** -40 * 2 * rl < tail < 1e-9 * 2 * rl
+        F = o.gks_point(Wl, z, Wr, z, 0.05)
+        assert np.all(np.isfinite(F)) and np.abs(F).max() < 1e-9 * rl * (Ul @ Ul + pl / rl)
