@@ -14,6 +14,23 @@
 // Included inside namespace hgks of hgks_kernels.hip.
 #pragma once
 
+// Element i of row r of a row-major [rows][N] array, read through a buffer
+// resource whose base is the row (uniform, scalar registers) and a 32-bit
+// per-lane byte offset (a single VGPR shared by all rows), so that no 64-bit
+// address per row is formed or held in vector registers.  The resource's
+// range is the row: an offset past it reads 0 instead of faulting.
+template <typename T>
+__device__ __forceinline__ T row_elem(const T* __restrict__ row0, size_t r, int N, unsigned boff) {
+  // word 3 of the buffer resource for gfx9-family (CDNA) parts: raw 32-bit
+  // data, no swizzle
+  const __amdgpu_buffer_rsrc_t rs =
+      __builtin_amdgcn_make_buffer_rsrc((void*)(row0 + r * (size_t)N), (short)0, N * (int)sizeof(T), 0x00020000);
+  if constexpr (sizeof(T) == 8)
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(rs, boff, 0, 0));
+  else
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(rs, boff, 0, 0));
+}
+
 constexpr int SIDE_SPB = 128;      // face sides per block
 constexpr int SIDE_THREADS = 128;  // threads per block
 
@@ -27,12 +44,16 @@ __global__ void __launch_bounds__(128) k_side(DevMesh<T> M, Params P, const T* _
                                               int* __restrict__ nfall) {
   constexpr int NGL = NG / LPS;  // Gauss points of this lane
   const int tid = xcd_block() * blockDim.x + threadIdx.x;  // contiguous side ranges per XCD
-  int sidx = tid / LPS;
+  const int q = tid / LPS;
   const int g_lo = (tid % LPS) * NGL;
   const int F = M.F, N = M.N, NX = M.NX;
-  if (sidx >= 2 * F) return;  // whole lane groups (LPS divides the block)
-  int side = sidx >= F;
-  int f = side ? sidx - F : sidx;
+  if (q >= 2 * F) return;  // whole lane groups (LPS divides the block)
+  // the two sides of a face are neighbouring lane groups, so that the side
+  // cells' coefficients are read close together in time (the second read of
+  // a cell's rows then tends to hit in L2)
+  const int side = q & 1;
+  const int f = q >> 1;
+  const int sidx = side * F + f;
   int L = M.fL[f], R = M.fR[f];
   if (side && R >= N) return;
   int i = side ? R : L, j = side ? L : R;
@@ -80,6 +101,7 @@ __global__ void __launch_bounds__(128) k_side(DevMesh<T> M, Params P, const T* _
   // outputs are formed from these after the component loop
   __shared__ T pqs[50][SIDE_THREADS];  // [cc * 10 + k][lane of the block]
   const int lt = threadIdx.x;
+  const unsigned cbo = (unsigned)i * (unsigned)sizeof(T);  // byte offset of the cell in a coefficient row
 #pragma unroll 1
   for (int cc = 0; cc < 5; ++cc) {
     // row cc of L* = R*^{-1} (x-split Euler eigenvectors at Q*, columns
@@ -111,18 +133,18 @@ __global__ void __launch_bounds__(128) k_side(DevMesh<T> M, Params P, const T* _
 #pragma unroll
     for (int d = 0; d < 3; ++d) tc[1 + d] = l[1] * e[0][d] + l[2] * e[1][d] + l[3] * e[2][d];
     T q0 = tc[0] * qi[0] + tc[1] * qi[1] + tc[2] * qi[2] + tc[3] * qi[3] + tc[4] * qi[4];
+    auto co = [&](int r) { return row_elem(coef, (size_t)r, N, cbo); };
     T a[9], b[NSUB][3];
 #pragma unroll
-    for (int k = 0; k < 9; ++k) {
-      const T* cp = coef + (size_t)(k * 5) * N + i;
-      a[k] = tc[0] * cp[0] + tc[1] * cp[N] + tc[2] * cp[2 * N] + tc[3] * cp[3 * N] + tc[4] * cp[4 * N];
-    }
+    for (int k = 0; k < 9; ++k)
+      a[k] = tc[0] * co(k * 5) + tc[1] * co(k * 5 + 1) + tc[2] * co(k * 5 + 2) + tc[3] * co(k * 5 + 3) +
+             tc[4] * co(k * 5 + 4);
 #pragma unroll
     for (int s = 0; s < NSUB; ++s)
 #pragma unroll
       for (int t = 0; t < 3; ++t) {
-        const T* cp = coef + (size_t)((9 + s * 3 + t) * 5) * N + i;
-        b[s][t] = tc[0] * cp[0] + tc[1] * cp[N] + tc[2] * cp[2 * N] + tc[3] * cp[3 * N] + tc[4] * cp[4 * N];
+        const int r = (9 + s * 3 + t) * 5;
+        b[s][t] = tc[0] * co(r) + tc[1] * co(r + 1) + tc[2] * co(r + 2) + tc[3] * co(r + 3) + tc[4] * co(r + 4);
       }
     // weights
     T w0, ws[NSUB];
@@ -251,3 +273,4 @@ __global__ void __launch_bounds__(128) k_side(DevMesh<T> M, Params P, const T* _
       for (int v = 0; v < 5; ++v) sv[(size_t)(((g_lo + gp) * 4 + d) * 5 + v) * ld + sidx] = out[d][v];
   }
 }
+
