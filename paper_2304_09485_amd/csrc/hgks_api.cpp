@@ -351,8 +351,11 @@ hgks_status jv_device(hgks_ctx* ctx, const double* v, double sigma_fixed, double
     // sqrt(rho E)) or energy moves by more than 1 % (the second half of the
     // partials is free here)
     launch_ratio_part(ctx->Qc, v, N, ctx->part + REDUCE_PARTS, s);
+    // and balance the FD truncation against the FP32 rounding (sc[41]: the
+    // rounding of the base residual, sc[42]: |A u| / |u| of the previous
+    // FP32 product; sc[43] receives |v|)
     launch_sigma(ctx->part, ctx->sc + 0, (double)n, eps, sigma_fixed, ctx->sc + 2, s, ctx->part + REDUCE_PARTS,
-                 1e-2);
+                 1e-2, ctx->sc + 41, ctx->sc + 43);
   } else {
     launch_sigma(ctx->part, ctx->sc + 0, (double)n, eps, sigma_fixed, ctx->sc + 2, s);
   }
@@ -364,6 +367,7 @@ hgks_status jv_device(hgks_ctx* ctx, const double* v, double sigma_fixed, double
     launch_perturb<float>(ctx->Qc, v, ctx->sc + 2, N, NX, ctx->Qp32, s);
     residual_pipeline<float, double>(ctx, ctx->Mf, ctx->W32, ctx->Qp32, ctx->W32.dt, 1, out, v, ctx->b32,
                                      ctx->sc + 2, (double*)nullptr, s);
+    launch_norm_ratio(out, n, ctx->sc + 43, ctx->part, ctx->sc + 42, s);
   }
   return HGKS_OK;
 }
@@ -409,6 +413,8 @@ hgks_status prepare_base(hgks_ctx* ctx, bool want_grad, hipStream_t s) {
     residual_pipeline<float, double>(ctx, ctx->Mf, ctx->W32, ctx->W32.Qx, ctx->W32.dt, 0, ctx->b32,
                                      (const double*)nullptr, (const double*)nullptr, (const double*)nullptr,
                                      (double*)nullptr, s);
+    // rounding level of one FP32 residual evaluation at the base point
+    launch_diff_norm(ctx->b32, ctx->b, n5(ctx), ctx->part, ctx->sc + 41, s);
   }
   return HGKS_OK;
 }
@@ -631,9 +637,11 @@ static hgks_status finish_load(hgks_ctx* ctx) {
   ctx->gst = ctx->A.get<int>(4);
   if (ctx->sc) {
     // device constant sc[4] = 1 (the unit coefficient of the update axpys),
-    // set once so that no host copy sits between queued kernels
-    const double one = 1.0;
-    HIPCHK(hipMemcpy(ctx->sc + 4, &one, sizeof(double), hipMemcpyHostToDevice));
+    // set once so that no host copy sits between queued kernels; the other
+    // scalars start at 0 (sc[41..42]: no FP32 rounding estimate yet)
+    std::vector<double> init(64 + MAXM + 1, 0.0);
+    init[4] = 1.0;
+    HIPCHK(hipMemcpy(ctx->sc, init.data(), init.size() * sizeof(double), hipMemcpyHostToDevice));
   }
   if (!ctx->Qc || !ctx->dtc || !ctx->b || !ctx->V || !ctx->flags || !ctx->sc || !ctx->part || !ctx->gm || !ctx->gst) {
     ctx->err = "device allocation failed";

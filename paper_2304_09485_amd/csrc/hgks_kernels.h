@@ -64,8 +64,16 @@ void launch_convert(const double* src, float* dst, size_t n, hipStream_t);
 // FD step of the Jv product from the block partials of |v|^2 (vpart) and the
 // reduced |Q|^2 (qq[0]) into sigma[0]; with rpart (block maxima of
 // launch_ratio_part) the step is also capped at eta / max ratio
+// vnorm (if set) receives |v|; noise (if set) = {rounding of one inner-precision
+// residual evaluation, |A u| / |u| of the last inner product} caps the step
+// where it balances rounding against truncation
 void launch_sigma(const double* vpart, const double* qq, double n, double eps, double fixed, double* sigma,
-                  hipStream_t, const double* rpart = nullptr, double eta = 0.0);
+                  hipStream_t, const double* rpart = nullptr, double eta = 0.0, const double* noise = nullptr,
+                  double* vnorm = nullptr);
+// out[0] = |x - y| (fixed-order sum)
+void launch_diff_norm(const double* x, const double* y, size_t n, double* part, double* out, hipStream_t);
+// out[0] = |x| / den[0] (0 if den[0] is 0)
+void launch_norm_ratio(const double* x, size_t n, const double* den, double* part, double* out, hipStream_t);
 // block maxima of max(|v_rho| / rho, |v_m| / sqrt(rho E), |v_E| / E) over the cells into part[REDUCE_PARTS]
 void launch_ratio_part(const double* Q, const double* v, int N, double* part, hipStream_t);
 

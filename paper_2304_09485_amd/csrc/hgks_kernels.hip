@@ -853,6 +853,11 @@ __global__ void __launch_bounds__(256) k_jacobi(DevMesh<T> M, Params P, const T*
 // ---------------------------------------------------------------------------
 constexpr int RB = 256;     // reduction block
 constexpr int RGRID = REDUCE_PARTS; // fixed grid -> fixed summation order
+// relative truncation error of an FD product per unit step length |sigma v|,
+// assumed when the step is balanced against the rounding of the inner
+// precision (measured 2 to 200 on shells and ramps; the balance is within a
+// factor 2 of the best step over that range)
+constexpr double FD_TRUNC = 10.0;
 
 // sum over the block in a fixed order: a shuffle tree within each 64-lane
 // wave, then the wave sums in index order; every lane gets the result.  A
@@ -880,7 +885,8 @@ __global__ void __launch_bounds__(RB) k_reduce_part(const double* __restrict__ x
   double s = 0.0;
   for (size_t k = (size_t)blockIdx.x * RB + threadIdx.x; k < n; k += (size_t)RGRID * RB) {
     if (OP == 0) s += x[k] * y[k];
-    else s += fabs(x[k]);
+    else if (OP == 1) s += fabs(x[k]);
+    else s += (x[k] - y[k]) * (x[k] - y[k]);
   }
   double t = block_sum(s);
   if (threadIdx.x == 0) part[blockIdx.x] = t;
@@ -893,6 +899,15 @@ __global__ void __launch_bounds__(RB) k_reduce_final(const double* __restrict__ 
   for (int k = threadIdx.x; k < RGRID; k += RB) s += part[k];
   double t = block_sum(s);
   if (threadIdx.x == 0) out[0] = SQRT ? sqrt(t) : t;
+}
+
+// out[0] = sqrt(sum(part)) / den[0] (0 if den[0] is 0)
+__global__ void __launch_bounds__(RB) k_reduce_norm_ratio(const double* __restrict__ part,
+                                                          const double* __restrict__ den, double* __restrict__ out) {
+  double s = 0.0;
+  for (int k = threadIdx.x; k < RGRID; k += RB) s += part[k];
+  double t = block_sum(s);
+  if (threadIdx.x == 0) out[0] = den[0] > 0.0 ? sqrt(t) / den[0] : 0.0;
 }
 
 // one modified Gram-Schmidt step fused with the partials of the next inner
@@ -1103,7 +1118,8 @@ __global__ void __launch_bounds__(RB) k_ratio_part(const double* __restrict__ Q,
 
 __global__ void __launch_bounds__(RB) k_sigma(const double* __restrict__ vpart, const double* __restrict__ qq,
                                               double n, double eps, double fixed, double* __restrict__ sigma,
-                                              const double* __restrict__ rpart, double eta) {
+                                              const double* __restrict__ rpart, double eta,
+                                              const double* __restrict__ noise, double* __restrict__ vnorm) {
   double s0 = 0.0;
   for (int k = threadIdx.x; k < RGRID; k += RB) s0 += vpart[k];
   const double vv = block_sum(s0);
@@ -1120,6 +1136,7 @@ __global__ void __launch_bounds__(RB) k_sigma(const double* __restrict__ vpart, 
       for (int k = 0; k < RB; ++k) r = fmax(r, shr[k]);
   }
   if (threadIdx.x != 0) return;
+  if (vnorm) vnorm[0] = sqrt(vv);
   double rv = sqrt(vv / n);
   if (rv == 0.0) {
     sigma[0] = 0.0;
@@ -1131,8 +1148,18 @@ __global__ void __launch_bounds__(RB) k_sigma(const double* __restrict__ vpart, 
   }
   double rq = sqrt(qq[0] / n);
   double sg = sqrt(eps) * fmax(1.0, rq) / rv;
-  // no cell's density or energy moves by more than eta of itself
+  // no cell's density, momentum or energy moves by more than eta
   if (r > 0.0) sg = fmin(sg, eta / r);
+  // rounding-aware step: noise[0] = |L~(Q) - L(Q)| (the rounding of one
+  // evaluation in the inner precision), noise[1] = |A u| of the last inner
+  // product per unit |u|.  The FD product then carries a rounding error of
+  // about sqrt(2) noise[0] / s relative to |A v| / |v| and a truncation error
+  // of about FD_TRUNC s, s = sigma |v|; s = sqrt(sqrt(2) noise[0] / (FD_TRUNC
+  // noise[1])) balances the two
+  if (noise && noise[0] > 0.0 && noise[1] > 0.0) {
+    const double st = sqrt(sqrt(2.0) * noise[0] / (FD_TRUNC * noise[1]));
+    if (st > 0.0 && isfinite(st)) sg = fmin(sg, st / sqrt(vv));
+  }
   sigma[0] = sg;
 }
 
@@ -1344,8 +1371,16 @@ void launch_convert(const double* src, float* dst, size_t n, hipStream_t s) {
   if (n) hipLaunchKernelGGL(k_convert, dim3(nblk(n, 256)), dim3(256), 0, s, src, dst, n);
 }
 void launch_sigma(const double* vpart, const double* qq, double n, double eps, double fixed, double* sigma,
-                  hipStream_t s, const double* rpart, double eta) {
-  hipLaunchKernelGGL(k_sigma, dim3(1), dim3(RB), 0, s, vpart, qq, n, eps, fixed, sigma, rpart, eta);
+                  hipStream_t s, const double* rpart, double eta, const double* noise, double* vnorm) {
+  hipLaunchKernelGGL(k_sigma, dim3(1), dim3(RB), 0, s, vpart, qq, n, eps, fixed, sigma, rpart, eta, noise, vnorm);
+}
+void launch_diff_norm(const double* x, const double* y, size_t n, double* part, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_reduce_part<2>, dim3(RGRID), dim3(RB), 0, s, x, y, n, part);
+  hipLaunchKernelGGL(k_reduce_final<true>, dim3(1), dim3(RB), 0, s, part, out);
+}
+void launch_norm_ratio(const double* x, size_t n, const double* den, double* part, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_reduce_part<0>, dim3(RGRID), dim3(RB), 0, s, x, x, n, part);
+  hipLaunchKernelGGL(k_reduce_norm_ratio, dim3(1), dim3(RB), 0, s, part, den, out);
 }
 void launch_ratio_part(const double* Q, const double* v, int N, double* part, hipStream_t s) {
   hipLaunchKernelGGL(k_ratio_part, dim3(RGRID), dim3(RB), 0, s, Q, v, N, part);
