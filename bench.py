@@ -1,9 +1,10 @@
 #!/usr/bin/env python3
 """Benchmark: implicit steps of the implicit high-order gas-kinetic scheme on one MI355X.
 
-Workload (default, --config c4): inviscid Mach 2 flow in a 3D channel with a
-15-degree compression ramp, 192 x 72 x 48 sheared hexahedra x 6 = 3,981,312
-jittered tets, supersonic inflow and outflow, slip walls, non-compact WENO
+Workload (default, --config c4): inviscid Mach 2 flow in a 3D channel (3 x 2 x 1)
+with a 15-degree compression ramp (from x = 1 to 1.5, flat after it), 192 x 72 x
+48 sheared hexahedra x 6 = 3,981,312 jittered tets, supersonic inflow and
+outflow, slip walls, non-compact WENO
 with nonlinear weights, CFL 10, GMRES(10) x 3 restarts on FD
 Jacobian-vector products, 2 Jacobi sweeps, FP64.  From the uniform free
 stream the plain update reaches a non-physical state in the first step (at
@@ -67,8 +68,8 @@ WORKLOADS = {
                     "FP64 implicit steps (update limit 0.2)"),
     "c4": dict(mach=2.0, kinds={1: 3, 2: 4, 3: 1, 4: 1, 5: 1, 6: 1}, opts=dict(scheme=0, max_update=0.2),
                start="uniform", ramp=None,
-               desc="15-degree ramp channel, Euler Mach 2, non-compact WENO, 3,981,312 tets, FP64 implicit steps "
-                    "(update limit 0.2)"),
+               desc="15-degree compression ramp in a 3 x 2 x 1 channel, Euler Mach 2, non-compact WENO, "
+                    "3,981,312 tets, FP64 implicit steps (update limit 0.2)"),
 }
 
 

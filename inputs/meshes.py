@@ -272,16 +272,27 @@ def shell_mesh(n: int, nr: int, r0: float = 0.5, r1: float = 10.0, grading: floa
 
 
 def ramp_mesh(nx: int, ny: int, nz: int, angle_deg: float = 15.0, length: float = 3.0,
-              ramp_start: float = 1.0, jitter: float = 0.0, seed: int = 0) -> TetMesh:
-    """Channel x in [0, length], y from max(0, (x - ramp_start) tan(angle)) to 1,
-    z in [0, 1], with sheared hexes.  Interior nodes are jittered.
-    Tags: 1 inlet (x=0), 2 outlet (x=length), 3 bottom/ramp, 4 top,
-    5 z=0 side, 6 z=1 side."""
+              ramp_start: float = 1.0, jitter: float = 0.0, seed: int = 0, ramp_end: float | None = None,
+              height: float = 1.0) -> TetMesh:
+    """Channel x in [0, length], z in [0, 1], y from the floor to `height`, with
+    sheared hexes.  The floor rises at `angle_deg` from x = ramp_start to
+    x = ramp_end (None: to the outlet) and is flat after it.  Interior nodes
+    are jittered.  Tags: 1 inlet (x=0), 2 outlet (x=length), 3 bottom/ramp,
+    4 top, 5 z=0 side, 6 z=1 side.
+
+    A floor that rises to the outlet of a unit-height channel closes it to
+    0.46 of its inlet area at x = 3, below the sonic area of any supersonic
+    inflow from Mach 1 to 2 (0.59 at Mach 2): such a channel has no started
+    steady flow.  A ramp of finite length (the floor 0.13 up after half a
+    unit) in a channel of height 2 keeps the Mach 2 stream started."""
     i, j, k = [a.ravel() for a in np.meshgrid(np.arange(nx + 1), np.arange(ny + 1), np.arange(nz + 1), indexing="ij")]
     lat = np.stack([i, j, k], axis=1)
     x = length * i / nx
-    yb = np.maximum(0.0, (x - ramp_start) * math.tan(math.radians(angle_deg)))
-    y = yb + (1.0 - yb) * j / ny
+    run = np.maximum(0.0, x - ramp_start)
+    if ramp_end is not None:
+        run = np.minimum(run, ramp_end - ramp_start)
+    yb = run * math.tan(math.radians(angle_deg))
+    y = yb + (height - yb) * j / ny
     z = k / nz
     xyz = np.stack([x, y, z], axis=1)
     nid = lambda a, b, c: (a * (ny + 1) + b) * (nz + 1) + c  # noqa: E731
@@ -310,5 +321,5 @@ def mesh_for_config(name: str) -> TetMesh:
     if name == "c3":   # 995,328 tets
         return shell_mesh(24, 48, first=1e-3, jitter=0.02, seed=3, bl_layers=10)
     if name == "c4":   # 3,981,312 tets
-        return ramp_mesh(192, 72, 48, jitter=0.02, seed=4)
+        return ramp_mesh(192, 72, 48, jitter=0.02, seed=4, ramp_end=1.5, height=2.0)
     raise KeyError(name)

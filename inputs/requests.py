@@ -37,7 +37,8 @@ class RequestSpec:
             return shell_mesh(n, nr, grading=1.1, jitter=0.02, seed=self.seed)
         # ramp channel: hexes nx : ny : nz = 4 : 1.5 : 1 (as the 3,981,312-tet channel)
         nz = max(2, int(round((self.target_cells / (6 * 4 * 1.5)) ** (1.0 / 3.0))))
-        return ramp_mesh(4 * nz, max(2, int(round(1.5 * nz))), nz, jitter=0.02, seed=self.seed)
+        return ramp_mesh(4 * nz, max(2, int(round(1.5 * nz))), nz, jitter=0.02, seed=self.seed, ramp_end=1.5,
+                         height=2.0)
 
     def boundary_kinds(self) -> dict:
         """Boundary kind per tag (far field 0, slip wall 1, no-slip adiabatic 2,
