@@ -482,12 +482,28 @@ def serve_stream(hgks, n_requests, rate, max_cells, max_steps, slots, fp64=False
                                   max_steps=max_steps, **opts))
         print(f"# submitted request {sp.index}: {sp.kind} {m.n_cells} cells Mach {sp.mach:.2f} "
               f"{'NS' if sp.viscous else 'Euler'} at {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
-    res = []
-    for sp, t in zip(specs, tickets):
-        r = srv.wait(t)
-        res.append(r)
-        print(f"# request {sp.index}: status {r.status} steps {r.steps} drop {r.res_final / max(r.res0, 1e-300):.2e} "
-              f"queue {r.t_queue_ms:.0f} ms total {r.t_total_ms:.0f} ms", file=sys.stderr, flush=True)
+    # results in the order they finish; between them, a line per 500
+    # implicit steps the server has completed over all requests
+    res = [None] * len(tickets)
+    pending = set(range(len(tickets)))
+    next_report = 500
+    while pending:
+        for k in sorted(pending):
+            r = srv.poll(tickets[k])
+            if r is None:
+                continue
+            res[k] = r
+            pending.discard(k)
+            print(f"# request {specs[k].index}: status {r.status} steps {r.steps} "
+                  f"drop {r.res_final / max(r.res0, 1e-300):.2e} queue {r.t_queue_ms:.0f} ms "
+                  f"total {r.t_total_ms:.0f} ms", file=sys.stderr, flush=True)
+        steps = srv.stats().steps_done
+        if steps >= next_report:
+            print(f"# {steps} implicit steps done, {len(pending)} requests pending at "
+                  f"{time.perf_counter() - t0:.0f} s", file=sys.stderr, flush=True)
+            next_report = (steps // 500 + 1) * 500
+        if pending:
+            time.sleep(0.2)
     makespan = time.perf_counter() - t0
     srv.close()
     lat = np.array([r.t_total_ms for r in res]) * 1e-3

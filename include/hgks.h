@@ -253,6 +253,10 @@ size_t hgks_residual_static_bytes(const hgks_ctx* ctx);
 /* Number of cells / faces of the loaded mesh. */
 int64_t hgks_n_cells(const hgks_ctx* ctx);
 int64_t hgks_n_faces(const hgks_ctx* ctx);
+/* Implicit steps the context has completed (hgks_implicit_step, and the
+ * steps of hgks_solve_steady); safe to call from another thread while the
+ * context works, for progress reporting. */
+int64_t hgks_steps_done(const hgks_ctx* ctx);
 
 /* Per-kernel timing of the last residual evaluation, in ms (HIP events on
  * the context stream): names[k] and ms[k] for k < *n (cap entries). */
@@ -263,10 +267,11 @@ void hgks_destroy(hgks_ctx* ctx);
 
 /* ---------------------------------------------------------------------------
  * Serving: continuous batching of steady solves (Algorithm 1 run to a residual
- * drop) on one GPU.  Requests are queued on submission and admitted, in
- * arrival order with smaller requests allowed to pass a waiting large one, as
- * soon as a slot is free and their estimated device footprint fits the HBM
- * budget.  Every admitted request owns a context (mesh data, state, Krylov
+ * drop) on one GPU.  Requests are queued on submission and admitted as soon
+ * as a slot is free and their estimated device footprint fits the HBM budget:
+ * of the queued requests that fit, the smallest footprint first (ties in
+ * arrival order); a request that has waited more than 60 s goes next and is
+ * passed by no other.  Every admitted request owns a context (mesh data, state, Krylov
  * basis resident in HBM) and a HIP stream driven by its own host thread, so
  * the work of concurrent requests overlaps on the device.  Results of a
  * request do not depend on what else runs (no shared mutable device state,
@@ -307,6 +312,7 @@ typedef struct {
   int32_t queued, active, done;
   size_t bytes_in_use, budget;
   int64_t cell_resid_evals; /* sum over finished requests of cells x residual evaluations */
+  int64_t steps_done;       /* implicit steps of all requests so far, finished and running */
 } hgks_server_info;
 
 /* Device bytes a request of this size needs (the admission estimate). */

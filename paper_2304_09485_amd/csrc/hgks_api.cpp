@@ -7,6 +7,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -85,6 +86,7 @@ const char* KNAMES[5] = {"ghost", "recon", "side", "flux", "gather"};
 
 struct hgks_ctx {
   hgks_options o{};
+  std::atomic<int64_t> n_steps{0};  // implicit steps taken (read by other threads)
   std::string err;
   hipStream_t stream = nullptr;
   bool own_stream = false;
@@ -894,6 +896,7 @@ hgks_status hgks_implicit_step(hgks_ctx* ctx, hgks_step_info* info) {
     info->n_limited = flags[2];
     info->t_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   }
+  ctx->n_steps.fetch_add(1, std::memory_order_relaxed);
   return check_state(ctx, s);
 }
 
@@ -1150,6 +1153,7 @@ hgks_status hgks_jv_dev(hgks_ctx* ctx, const void* v_dev, double sigma, void* Av
 }
 
 int64_t hgks_n_cells(const hgks_ctx* ctx) { return ctx && ctx->mesh ? ctx->H.N : 0; }
+int64_t hgks_steps_done(const hgks_ctx* ctx) { return ctx ? ctx->n_steps.load(std::memory_order_relaxed) : 0; }
 int64_t hgks_n_faces(const hgks_ctx* ctx) { return ctx && ctx->mesh ? ctx->H.F : 0; }
 
 hgks_status hgks_kernel_times(hgks_ctx* ctx, const char** names, double* ms, int32_t* n, int32_t cap) {

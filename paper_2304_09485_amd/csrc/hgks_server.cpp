@@ -44,6 +44,7 @@ struct Job {
   hgks_result result{};
   std::vector<double> Q;  // final state
   std::thread worker;
+  hgks_ctx* ctx = nullptr;  // while the request runs (set and cleared under the server lock)
 };
 
 }  // namespace
@@ -58,6 +59,7 @@ struct hgks_server {
   std::map<int64_t, std::unique_ptr<Job>> jobs;
   std::vector<std::thread> finished_workers;
   int64_t cell_evals = 0;
+  int64_t steps_finished = 0;  // implicit steps of finished requests
   int32_t n_done = 0;
   bool stopping = false;
   int device = 0;
@@ -75,6 +77,10 @@ void run_job(hgks_server* S, Job* J) {
   o.stream = nullptr;  // the context creates its own stream
   hgks_ctx* ctx = nullptr;
   hgks_status st = hgks_create(&o, &ctx);
+  if (st == HGKS_OK) {
+    std::lock_guard<std::mutex> lk(S->mu);
+    J->ctx = ctx;
+  }
   std::vector<double> Q;
   if (st == HGKS_OK)
     st = hgks_load_mesh(ctx, (int64_t)(J->xyz.size() / 3), J->xyz.data(), r.n_cells, J->tets.data(),
@@ -101,7 +107,14 @@ void run_job(hgks_server* S, Job* J) {
     r.n_resid_evals = si.n_resid_evals;
     hgks_get_state(ctx, Q.data(), nullptr);
   }
-  if (ctx) hgks_destroy(ctx);
+  if (ctx) {
+    {
+      std::lock_guard<std::mutex> lk(S->mu);
+      J->ctx = nullptr;
+      S->steps_finished += hgks_steps_done(ctx);
+    }
+    hgks_destroy(ctx);
+  }
   r.status = st;
   std::lock_guard<std::mutex> lk(S->mu);
   J->t_done = Clock::now();
@@ -119,8 +132,11 @@ void run_job(hgks_server* S, Job* J) {
   S->cv.notify_all();
 }
 
-// admission: arrival order; a later request may pass a waiting one when it
-// fits and the head has not waited more than 10 s
+// admission: of the queued requests that fit, the one with the smallest
+// footprint (the estimate of its size, so of its work per step) goes first,
+// ties in arrival order; once the oldest request has waited more than
+// STARVE_MS it goes next and no other request passes it
+constexpr double STARVE_MS = 60000.0;
 void dispatch_loop(hgks_server* S) {
   std::unique_lock<std::mutex> lk(S->mu);
   while (true) {
@@ -131,21 +147,23 @@ void dispatch_loop(hgks_server* S) {
     bool admitted = false;
     if (!S->stopping && S->active < S->max_slots && !S->queue.empty()) {
       Job* head = S->jobs[S->queue.front()].get();
-      bool head_starving = ms_between(head->t_submit, Clock::now()) > 10000.0;
+      const bool head_starving = ms_between(head->t_submit, Clock::now()) > STARVE_MS;
+      auto best = S->queue.end();
       for (auto it = S->queue.begin(); it != S->queue.end(); ++it) {
         Job* J = S->jobs[*it].get();
-        bool fits = S->in_use + J->footprint <= S->budget || S->active == 0;
-        if (fits) {
-          S->queue.erase(it);
-          J->admitted = true;
-          J->t_admit = Clock::now();
-          S->in_use += J->footprint;
-          S->active += 1;
-          J->worker = std::thread(run_job, S, J);
-          admitted = true;
-          break;
-        }
-        if (head_starving) break;
+        const bool fits = S->in_use + J->footprint <= S->budget || S->active == 0;
+        if (fits && (best == S->queue.end() || J->footprint < S->jobs[*best]->footprint)) best = it;
+        if (head_starving) break;  // only the head may go
+      }
+      if (best != S->queue.end()) {
+        Job* J = S->jobs[*best].get();
+        S->queue.erase(best);
+        J->admitted = true;
+        J->t_admit = Clock::now();
+        S->in_use += J->footprint;
+        S->active += 1;
+        J->worker = std::thread(run_job, S, J);
+        admitted = true;
       }
     }
     if (!admitted) S->cv.wait_for(lk, std::chrono::milliseconds(50));
@@ -268,6 +286,9 @@ hgks_status hgks_server_stats(hgks_server* S, hgks_server_info* out) {
   out->bytes_in_use = S->in_use;
   out->budget = S->budget;
   out->cell_resid_evals = S->cell_evals;
+  out->steps_done = S->steps_finished;
+  for (const auto& kv : S->jobs)
+    if (kv.second->ctx) out->steps_done += hgks_steps_done(kv.second->ctx);
   return HGKS_OK;
 }
 

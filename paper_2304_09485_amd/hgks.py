@@ -30,7 +30,7 @@ STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EMESH", -4: "ESTATE", -5: "E
 SYMBOLS = ["hgks_default_options", "hgks_create", "hgks_load_mesh", "hgks_load_hex_mesh", "hgks_set_freestream", "hgks_set_bc",
            "hgks_set_state", "hgks_get_state", "hgks_residual", "hgks_time_step", "hgks_jv", "hgks_precond",
            "hgks_implicit_step", "hgks_solve_steady", "hgks_residual_dev", "hgks_residual_dev_static",
-           "hgks_residual_static_bytes", "hgks_jv_dev", "hgks_n_cells",
+           "hgks_residual_static_bytes", "hgks_jv_dev", "hgks_n_cells", "hgks_steps_done",
            "hgks_n_faces", "hgks_kernel_times", "hgks_last_error", "hgks_destroy", "hgks_estimate_bytes",
            "hgks_checkpoint", "hgks_restore",
            "hgks_server_create", "hgks_server_submit", "hgks_server_poll", "hgks_server_wait",
@@ -116,7 +116,7 @@ class Result(ctypes.Structure):
 class ServerStats(ctypes.Structure):
     _fields_ = [("queued", ctypes.c_int32), ("active", ctypes.c_int32), ("done", ctypes.c_int32),
                 ("bytes_in_use", ctypes.c_size_t), ("budget", ctypes.c_size_t),
-                ("cell_resid_evals", ctypes.c_int64)]
+                ("cell_resid_evals", ctypes.c_int64), ("steps_done", ctypes.c_int64)]
 
 
 _lib = None
@@ -160,6 +160,7 @@ def load_library():
         "hgks_residual_static_bytes": (ctypes.c_size_t, [vp]),
         "hgks_jv_dev": (i32, [vp, vp, d, vp, vp]),
         "hgks_n_cells": (i64, [vp]),
+        "hgks_steps_done": (i64, [vp]),
         "hgks_n_faces": (i64, [vp]),
         "hgks_kernel_times": (i32, [vp, vp, vp, ctypes.POINTER(i32), i32]),
         "hgks_last_error": (ctypes.c_char_p, [vp]),
