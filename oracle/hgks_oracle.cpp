@@ -553,6 +553,24 @@ double beta_lin(const orc_ctx& C, int i, const double b[3]) {
 void fit_subs(const orc_ctx& C, int i, const std::vector<int>& big, const std::vector<std::vector<int>>& subs,
               const std::vector<V5>& qs, Poly P[5]);
 
+// Reading A36: a cell with two boundary faces whose planes meet at more than
+// 45 degrees (a cell on an edge or at a corner of the boundary) takes the
+// linear fit for P0.  With the quadratic fit there, the residual linearised
+// at a uniform stream in a box or a channel has eigenvalues with positive real
+// part, localised at those cells.
+static bool edge_cell(const orc_ctx& C, int i) {
+  const double c45 = std::sqrt(0.5);
+  for (int p = 0; p < C.nf; ++p) {
+    const Face& fp = C.faces[C.cf[i][p]];
+    if (fp.R >= 0) continue;
+    for (int q = 0; q < p; ++q) {
+      const Face& fq = C.faces[C.cf[i][q]];
+      if (fq.R < 0 && std::fabs(dot(fp.n, fq.n)) < c45) return true;
+    }
+  }
+  return false;
+}
+
 // Non-compact WENO fits (Sec. 3.2): q[e] are projected averages keyed by
 // position in the big stencil list.
 void fit_weno(const orc_ctx& C, int i, const std::vector<int>& big,
@@ -566,11 +584,11 @@ void fit_weno(const orc_ctx& C, int i, const std::vector<int>& big,
     for (int c = 0; c < 5; ++c) B[r * 5 + c] = qs[r + 1][c] - qs[0][c];
   }
   for (int c = 0; c < 5; ++c) P[c].q0 = qs[0][c];
-  if (full_rank(A, m, 9)) {
+  if (full_rank(A, m, 9) && !edge_cell(C, i)) {
     householder_lsq(A, B, m, 9, 5, X);
     for (int c = 0; c < 5; ++c)
       for (int k = 0; k < 9; ++k) P[c].a[k] = X[k * 5 + c];
-  } else {  // reading A17: linear LS on the big stencil
+  } else {  // readings A17 and A36: linear LS on the big stencil
     std::vector<double> A3(m * 3);
     for (int r = 0; r < m; ++r)
       for (int k = 0; k < 3; ++k) A3[r * 3 + k] = A[r * 9 + k];

@@ -374,6 +374,24 @@ int finish_mesh(HostMesh& H, const std::vector<Vec3>& cen, const std::vector<Sym
     for (int k = 0; k < 6; ++k)
       r[3 + k] = (mx[e].a[A[k]][B[k]] + comp(d, A[k]) * comp(d, B[k]) - mx[i].a[A[k]][B[k]]) / (hi * hi);
   };
+  // a cell with two boundary faces whose planes meet at more than 45 degrees
+  // (on an edge or at a corner of the boundary) is fitted linearly: the
+  // quadratic fit has growing modes there
+  auto at_edge = [&](int i) {
+    const double c45 = std::sqrt(0.5);
+    for (int p = 0; p < nf; ++p) {
+      if (nbr[i][p] < N) continue;
+      const int fa = H.gface[nbr[i][p] - N];
+      for (int q = 0; q < p; ++q) {
+        if (nbr[i][q] < N) continue;
+        const int fb = H.gface[nbr[i][q] - N];
+        double d = 0.0;
+        for (int k = 0; k < 3; ++k) d += H.fn[(size_t)k * F + fa] * H.fn[(size_t)k * F + fb];
+        if (std::fabs(d) < c45) return true;
+      }
+    }
+    return false;
+  };
   int64_t nfb = 0, nsd = 0;
 #pragma omp parallel for schedule(dynamic, 256) reduction(+ : nfb, nsd)
   for (int i = 0; i < N; ++i) {
@@ -385,12 +403,13 @@ int finish_mesh(HostMesh& H, const std::vector<Vec3>& cen, const std::vector<Sym
     // P0 operator
     std::vector<double> A((size_t)m * 9), X((size_t)9 * m);
     for (int r = 0; r < m; ++r) row9(i, big[r], &A[(size_t)r * 9]);
-    if (m >= 9 && gram_cond_ratio(A.data(), m, 9) > 1e-20) {
+    if (m >= 9 && gram_cond_ratio(A.data(), m, 9) > 1e-20 && !at_edge(i)) {
       pinv_mgs(A.data(), m, 9, X.data());
       for (int k = 0; k < 9; ++k)
         for (int r = 0; r < m; ++r) H.opA[(size_t)(k * nbig + r) * N + i] = X[(size_t)k * m + r];
     } else {
-      // rank-deficient big stencil: linear least squares on it
+      // rank-deficient big stencil, or a cell on a boundary edge: linear
+      // least squares on the big stencil
       ++nfb;
       std::vector<double> A3((size_t)m * 3), X3((size_t)3 * m);
       for (int r = 0; r < m; ++r)
