@@ -327,7 +327,7 @@ def main():
     ap.add_argument("--no-secondary", action="store_true", help="skip the other workloads")
     ap.add_argument("--no-solve", action="store_true", help="skip the time-to-1e-8 solves and the variants")
     ap.add_argument("--solve-steps", type=int, default=400, help="step cap of each time-to-1e-8 solve")
-    ap.add_argument("--drop-steps", type=int, default=40,
+    ap.add_argument("--drop-steps", type=int, default=400,
                     help="step cap of the headline workload's own runs towards a 1e-8 drop")
     ap.add_argument("--serving", action="store_true",
                     help="run the served request stream instead of the implicit-step throughput")
