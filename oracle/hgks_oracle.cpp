@@ -890,6 +890,7 @@ static void gks_point(const orc_ctx& C, const V5& Wl, const V5 dWl[3], const V5&
   M0.init(z.U, z.V, z.W, z.lam, K, 0);
   // slopes of the initial distributions in the three local directions
   V5 al[3], ar[3], ab[3];
+  V5 dWn{0, 0, 0, 0, 0};  // normal derivative of the interface state (for the heat flux)
   for (int d = 0; d < 3; ++d) {
     V5 bl, br;
     for (int k = 0; k < 5; ++k) {
@@ -901,6 +902,8 @@ static void gks_point(const orc_ctx& C, const V5& Wl, const V5 dWl[3], const V5&
     // equilibrium slopes from kinetic-weighted derivatives of Q0 (reading A6)
     V5 ql = Mlh.apsi(al[d], 0, 0, 0), qr = Mrh.apsi(ar[d], 0, 0, 0), b0;
     for (int k = 0; k < 5; ++k) b0[k] = (l.rho * ql[k] + r.rho * qr[k]) / z.rho;
+    if (d == 0)
+      for (int k = 0; k < 5; ++k) dWn[k] = l.rho * ql[k] + r.rho * qr[k];
     ab[d] = slope_solve(M0, b0);
   }
   // time derivatives from <a_1 u + a_2 v + a_3 w + A> = 0
@@ -947,13 +950,13 @@ static void gks_point(const orc_ctx& C, const V5& Wl, const V5 dWl[3], const V5&
   double Tav[6] = {T1 / dt, T2 / dt, T3 / dt, T4 / dt, T5 / dt, T6 / dt};
   F = fmoment(1, Tav);
   if (C.o.physics == 1) {
-    // heat flux relative to U0 carried by the time-averaged f; energy flux
-    // corrected by (1/Pr - 1) q (reading A19)
-    V5 Ph = fmoment(0, Tav);
-    V3 U0{z.U, z.V, z.W};
-    double u2 = dot(U0, U0);
-    double q = F[4] - (F[1] * U0[0] + F[2] * U0[1] + F[3] * U0[2]) + 0.5 * u2 * F[0] -
-               U0[0] * (Ph[4] - (Ph[1] * U0[0] + Ph[2] * U0[1] + Ph[3] * U0[2]) + 0.5 * u2 * Ph[0]);
+    // Prandtl correction (reading A19): the BGK flux carries the heat flux of
+    // Pr = 1, -mu c_p dT/dn; add (1/Pr - 1) times that Fourier flux, formed
+    // from the normal derivative of the interface state (T = p / rho)
+    const double u2 = z.U * z.U + z.V * z.V + z.W * z.W;
+    const double dp = (g - 1.0) * (dWn[4] - (z.U * dWn[1] + z.V * dWn[2] + z.W * dWn[3]) + 0.5 * u2 * dWn[0]);
+    const double dT = dp / z.rho - z.p * dWn[0] / (z.rho * z.rho);
+    const double q = -C.o.mu * g / (g - 1.0) * dT;
     F[4] += (1.0 / C.o.prandtl - 1.0) * q;
   }
   if (QG) {

@@ -212,12 +212,12 @@ struct FluxParams {
 // the flux moments, u-table uf of its full space for the time derivative)
 // times [c_e + c_s (u a_n.psi + v a_t1.psi + w a_t2.psi) + c_A A.psi], where
 // A solves <a_n u + a_t1 v + a_t2 w + A> = 0.  Accumulates rho x the
-// flux moments (k = 1) into F, density moments (k = 0) into Ph (NS) and the
-// point-value moments with the second coefficient set into QG.
-template <typename T, bool NS, bool QG>
+// flux moments (k = 1) into F and the point-value moments with the second
+// coefficient set into QG.
+template <typename T, bool QG>
 HGKS_HD void term(const VWX<T>& M, const T uh[8], const T uf[8], T rho, T U, T V, T W, T lam, T r, T K, T ik3,
                   const T an[5], const T at1[5], const T at2[5], T ce, T cs, T cA, T de, T ds, T dA, T F[5],
-                  T Ph[5], T Qg[5]) {
+                  T Qg[5]) {
   GSum<T> Ga;
   {
     T c[23];
@@ -254,7 +254,6 @@ HGKS_HD void term(const VWX<T>& M, const T uh[8], const T uf[8], T rho, T U, T V
   }
   gaxpy(Gt, cs, Ga);
   gmom<1>(uh, Gt, rho, F);
-  if (NS) gmom<0>(uh, Gt, rho, Ph);
 }
 
 // <psi a.psi> over a u-table: the moment of a single expansion (k = 0)
@@ -350,6 +349,7 @@ HGKS_HD void gks_flux(const T Wl[5], const T dWl[3][5], const T Wr[5], const T d
 
   // slopes of the initial distributions in the directions (n, t1, t2) and
   // the kinetic-weighted derivatives of Q0
+  T dTn = T(0);
   T(*al)[5] = reinterpret_cast<T(*)[5]>(sl);
   T(*ar)[5] = reinterpret_cast<T(*)[5]>(sl + 15);
   T(*ab)[5] = reinterpret_cast<T(*)[5]>(sl + 30);
@@ -382,6 +382,13 @@ HGKS_HD void gks_flux(const T Wl[5], const T dWl[3][5], const T Wr[5], const T d
     u_table(u, Ur, hr, ur0, ur1);
 #pragma unroll
     for (int d = 0; d < 3; ++d) apsi_mom(M, u, ar[d], rr, dq[d]);
+    if (P.physics) {
+      // normal derivative of the interface temperature p / rho, for the
+      // Prandtl correction below
+      const T u2 = U0 * U0 + V0 * V0 + W0 * W0;
+      const T dp = (g - T(1)) * (dq[0][4] - (U0 * dq[0][1] + V0 * dq[0][2] + W0 * dq[0][3]) + T(0.5) * u2 * dq[0][0]);
+      dTn = dp * i0 - p0 * dq[0][0] * i0 * i0;
+    }
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
 #pragma unroll
@@ -391,7 +398,6 @@ HGKS_HD void gks_flux(const T Wl[5], const T dWl[3][5], const T Wr[5], const T d
   }
 #pragma unroll
   for (int k = 0; k < 5; ++k) F[k] = T(0);
-  T Ph[5] = {0, 0, 0, 0, 0};
   T Qg[5] = {0, 0, 0, 0, 0};
   // initial-distribution terms: half-space moments of g_l (u > 0), g_r (u < 0)
   // (first, so that their slopes are dead before the equilibrium term)
@@ -401,12 +407,7 @@ HGKS_HD void gks_flux(const T Wl[5], const T dWl[3][5], const T Wr[5], const T d
     vwx_table(M, Vl, Wwl, hl, K);
     u_table(uh, Ul, hl, ul0, ul1);
     u_table(uf, Ul, hl, T(1), Ul);
-    if (P.physics)
-      term<T, true, want_qg>(M, uh, uf, rl, Ul, Vl, Wwl, ll, hl, K, ik3, al[0], al[1], al[2], c4, c5, c6, d4, d5, d6, F, Ph,
-                             Qg);
-    else
-      term<T, false, want_qg>(M, uh, uf, rl, Ul, Vl, Wwl, ll, hl, K, ik3, al[0], al[1], al[2], c4, c5, c6, d4, d5, d6, F, Ph,
-                              Qg);
+    term<T, want_qg>(M, uh, uf, rl, Ul, Vl, Wwl, ll, hl, K, ik3, al[0], al[1], al[2], c4, c5, c6, d4, d5, d6, F, Qg);
   }
   {
     VWX<T> M;
@@ -414,12 +415,7 @@ HGKS_HD void gks_flux(const T Wl[5], const T dWl[3][5], const T Wr[5], const T d
     vwx_table(M, Vr, Wwr, hr, K);
     u_table(uh, Ur, hr, ur0, ur1);
     u_table(uf, Ur, hr, T(1), Ur);
-    if (P.physics)
-      term<T, true, want_qg>(M, uh, uf, rr, Ur, Vr, Wwr, lr, hr, K, ik3, ar[0], ar[1], ar[2], c4, c5, c6, d4, d5, d6, F, Ph,
-                             Qg);
-    else
-      term<T, false, want_qg>(M, uh, uf, rr, Ur, Vr, Wwr, lr, hr, K, ik3, ar[0], ar[1], ar[2], c4, c5, c6, d4, d5, d6, F, Ph,
-                              Qg);
+    term<T, want_qg>(M, uh, uf, rr, Ur, Vr, Wwr, lr, hr, K, ik3, ar[0], ar[1], ar[2], c4, c5, c6, d4, d5, d6, F, Qg);
   }
   // equilibrium term: full-space moments of g0
   {
@@ -428,18 +424,11 @@ HGKS_HD void gks_flux(const T Wl[5], const T dWl[3][5], const T Wr[5], const T d
     vwx_table(M, V0, W0, h0, K);
     u_table(u, U0, h0, T(1), U0);
     // (no point-value contribution: its coefficients d1..d3 vanish at t^n)
-    if (P.physics)
-      term<T, true, false>(M, u, u, r0, U0, V0, W0, l0, h0, K, ik3, ab[0], ab[1], ab[2], c1, c2, c3, d1, d2, d3, F, Ph, Qg);
-    else
-      term<T, false, false>(M, u, u, r0, U0, V0, W0, l0, h0, K, ik3, ab[0], ab[1], ab[2], c1, c2, c3, d1, d2, d3, F, Ph, Qg);
+    term<T, false>(M, u, u, r0, U0, V0, W0, l0, h0, K, ik3, ab[0], ab[1], ab[2], c1, c2, c3, d1, d2, d3, F, Qg);
   }
-  if (P.physics) {
-    // heat flux relative to U0 carried by the time-averaged f, rescaled to Pr
-    T u2 = U0 * U0 + V0 * V0 + W0 * W0;
-    T q = F[4] - (F[1] * U0 + F[2] * V0 + F[3] * W0) + T(0.5) * u2 * F[0] -
-          U0 * (Ph[4] - (Ph[1] * U0 + Ph[2] * V0 + Ph[3] * W0) + T(0.5) * u2 * Ph[0]);
-    F[4] += (T(1) / P.prandtl - T(1)) * q;
-  }
+  // Prandtl correction: the BGK flux carries the heat flux of Pr = 1,
+  // -mu c_p dT/dn; add (1/Pr - 1) times that Fourier flux
+  if (P.physics) F[4] += (T(1) / P.prandtl - T(1)) * (-P.mu * g / (g - T(1)) * dTn);
   if (want_qg)
 #pragma unroll
     for (int k = 0; k < 5; ++k) QG[k] = Qg[k];

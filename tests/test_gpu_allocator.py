@@ -11,7 +11,10 @@ FAR, SLIP = 0, 1
 
 
 @pytest.mark.gpu
-@pytest.mark.parametrize("opts", [{"scheme": 1}, {"scheme": 0, "precision": 1}])
+# (the FP32-inner case from a 1 % perturbed start on this coarse, 5 %-jittered
+# shell takes the update limit of impulsive starts: without it the third
+# FP32-inner step can leave the physical states, whichever allocator is used)
+@pytest.mark.parametrize("opts", [{"scheme": 1}, {"scheme": 0, "precision": 1, "max_update": 0.2}])
 def test_torch_allocator_context_matches_hipmalloc(opts):
     import gc
 
