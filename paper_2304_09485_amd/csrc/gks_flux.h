@@ -349,7 +349,6 @@ HGKS_HD void gks_flux(const T Wl[5], const T dWl[3][5], const T Wr[5], const T d
 
   // slopes of the initial distributions in the directions (n, t1, t2) and
   // the kinetic-weighted derivatives of Q0
-  T dTn = T(0);
   T(*al)[5] = reinterpret_cast<T(*)[5]>(sl);
   T(*ar)[5] = reinterpret_cast<T(*)[5]>(sl + 15);
   T(*ab)[5] = reinterpret_cast<T(*)[5]>(sl + 30);
@@ -382,13 +381,6 @@ HGKS_HD void gks_flux(const T Wl[5], const T dWl[3][5], const T Wr[5], const T d
     u_table(u, Ur, hr, ur0, ur1);
 #pragma unroll
     for (int d = 0; d < 3; ++d) apsi_mom(M, u, ar[d], rr, dq[d]);
-    if (P.physics) {
-      // normal derivative of the interface temperature p / rho, for the
-      // Prandtl correction below
-      const T u2 = U0 * U0 + V0 * V0 + W0 * W0;
-      const T dp = (g - T(1)) * (dq[0][4] - (U0 * dq[0][1] + V0 * dq[0][2] + W0 * dq[0][3]) + T(0.5) * u2 * dq[0][0]);
-      dTn = dp * i0 - p0 * dq[0][0] * i0 * i0;
-    }
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
 #pragma unroll
@@ -407,7 +399,10 @@ HGKS_HD void gks_flux(const T Wl[5], const T dWl[3][5], const T Wr[5], const T d
     vwx_table(M, Vl, Wwl, hl, K);
     u_table(uh, Ul, hl, ul0, ul1);
     u_table(uf, Ul, hl, T(1), Ul);
-    term<T, want_qg>(M, uh, uf, rl, Ul, Vl, Wwl, ll, hl, K, ik3, al[0], al[1], al[2], c4, c5, c6, d4, d5, d6, F, Qg);
+    if (P.physics)
+      term<T, want_qg>(M, uh, uf, rl, Ul, Vl, Wwl, ll, hl, K, ik3, al[0], al[1], al[2], c4, c5, c6, d4, d5, d6, F, Qg);
+    else
+      term<T, want_qg>(M, uh, uf, rl, Ul, Vl, Wwl, ll, hl, K, ik3, al[0], al[1], al[2], c4, c5, c6, d4, d5, d6, F, Qg);
   }
   {
     VWX<T> M;
@@ -415,7 +410,10 @@ HGKS_HD void gks_flux(const T Wl[5], const T dWl[3][5], const T Wr[5], const T d
     vwx_table(M, Vr, Wwr, hr, K);
     u_table(uh, Ur, hr, ur0, ur1);
     u_table(uf, Ur, hr, T(1), Ur);
-    term<T, want_qg>(M, uh, uf, rr, Ur, Vr, Wwr, lr, hr, K, ik3, ar[0], ar[1], ar[2], c4, c5, c6, d4, d5, d6, F, Qg);
+    if (P.physics)
+      term<T, want_qg>(M, uh, uf, rr, Ur, Vr, Wwr, lr, hr, K, ik3, ar[0], ar[1], ar[2], c4, c5, c6, d4, d5, d6, F, Qg);
+    else
+      term<T, want_qg>(M, uh, uf, rr, Ur, Vr, Wwr, lr, hr, K, ik3, ar[0], ar[1], ar[2], c4, c5, c6, d4, d5, d6, F, Qg);
   }
   // equilibrium term: full-space moments of g0
   {
@@ -424,11 +422,18 @@ HGKS_HD void gks_flux(const T Wl[5], const T dWl[3][5], const T Wr[5], const T d
     vwx_table(M, V0, W0, h0, K);
     u_table(u, U0, h0, T(1), U0);
     // (no point-value contribution: its coefficients d1..d3 vanish at t^n)
-    term<T, false>(M, u, u, r0, U0, V0, W0, l0, h0, K, ik3, ab[0], ab[1], ab[2], c1, c2, c3, d1, d2, d3, F, Qg);
+    if (P.physics)
+      term<T, false>(M, u, u, r0, U0, V0, W0, l0, h0, K, ik3, ab[0], ab[1], ab[2], c1, c2, c3, d1, d2, d3, F, Qg);
+    else
+      term<T, false>(M, u, u, r0, U0, V0, W0, l0, h0, K, ik3, ab[0], ab[1], ab[2], c1, c2, c3, d1, d2, d3, F, Qg);
   }
-  // Prandtl correction: the BGK flux carries the heat flux of Pr = 1,
-  // -mu c_p dT/dn; add (1/Pr - 1) times that Fourier flux
-  if (P.physics) F[4] += (T(1) / P.prandtl - T(1)) * (-P.mu * g / (g - T(1)) * dTn);
+  if (P.physics) {
+    // Prandtl correction: the BGK flux carries the heat flux of Pr = 1,
+    // -mu c_p dT/dn; the energy flux gets (1/Pr - 1) times that.  T = 1/(2
+    // lam), and the normal slope of the interface Maxwellian has the
+    // coefficient -2 dlam/dn on (u^2+v^2+w^2+xi^2)/2: dT/dn = ab[0][4] / (4 lam0^2)
+    F[4] += (T(1) / P.prandtl - T(1)) * (-P.mu * g / (g - T(1)) * ab[0][4] / (T(4) * l0 * l0));
+  }
   if (want_qg)
 #pragma unroll
     for (int k = 0; k < 5; ++k) QG[k] = Qg[k];
