@@ -89,8 +89,14 @@ typedef struct {
   double gamma_lin;      /* 0.025, linear weights gamma_m, Sec. 3.4 */
   double weno_eps;       /* 1e-5, epsilon of the nonlinear weights (Sec. 3.4 leaves it open) */
   double mu;             /* dynamic viscosity (NS) */
-  double prandtl;        /* Prandtl number (NS), 1 = plain BGK */
-  double fd_sigma;       /* FD step of Eq. (frechet); 0 = sqrt(eps) max(1,rms Q)/rms v */
+  double prandtl;        /* Prandtl number (NS), 1 = plain BGK; otherwise the energy flux
+                            gets (1/Pr - 1) times the Fourier heat flux -mu c_p dT/dn of
+                            the interface state */
+  double fd_sigma;       /* FD step of Eq. (frechet); 0 = sqrt(eps) max(1,rms Q)/rms v with
+                            eps = 2^-52 (FP64 products) or 2^-23 (FP32 inner products; then
+                            capped so that no cell's density, momentum or energy moves by
+                            more than 1 %, and at the step that balances the FD truncation
+                            against the measured FP32 rounding of the base residual) */
   double cfl_flux;       /* CFL number of the time interval the flux is averaged over
                             (Sec. 4.1); default 1; 0 = the implicit step's cfl */
   double cfl_start;      /* hgks_solve_steady only: CFL of its first step, multiplied by
