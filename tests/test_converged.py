@@ -99,8 +99,9 @@ def test_fp32_inner_product_matches_fp64_at_fixed_step():
 
 
 def test_boxes_with_edges_converge():
-    """Meshes whose boundary has edges (reading A36): the configuration-1
-    cube (far field, Mach 0.3, 1 % perturbation) and a flat Mach 2 channel
+    """Meshes whose boundary has edges (cells with two boundary faces on
+    perpendicular planes take the linear P0 fit): the 3,072-tet unit cube
+    (far field, Mach 0.3, 1 % perturbation) and a flat Mach 2 channel
     with slip walls (1 % perturbation) reach a 1e-8 drop on the GPU (26 and
     23 steps measured); with the quadratic P0 fit on the edge cells such
     boxes sat in a period-2 limit cycle (the cube near 1e-5, a larger flat
