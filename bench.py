@@ -547,7 +547,8 @@ def time_to_drop(hgks, mesh, kinds, prim, max_steps):
              ("non-compact WENO, linear weights, FP64", dict(scheme=hgks.WENO, weights=hgks.WEIGHTS_LINEAR)),
              ("non-compact WENO, linear weights, FP32 inner / FP64 outer",
               dict(scheme=hgks.WENO, weights=hgks.WEIGHTS_LINEAR, precision=hgks.FP32_INNER)),
-             ("compact HWENO, FP64", dict(scheme=hgks.HWENO))]
+             ("compact HWENO, FP64", dict(scheme=hgks.HWENO)),
+             ("compact HWENO, gradient update relaxed (omega 0.7), FP64", dict(scheme=hgks.HWENO, grad_relax=0.7))]
     out = []
     for name, opts in forms:
         t0 = time.perf_counter()

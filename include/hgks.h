@@ -108,6 +108,11 @@ typedef struct {
                             density and pressure change by at most theta of their old values
                             (a runtime policy for impulsive starts, e.g. 0.2; a steady state
                             is a fixed point either way) */
+  double grad_relax;     /* compact HWENO: the gradients after a step are G + omega (G_new - G)
+                            with omega = grad_relax in (0, 1]; 1 (default) takes G_new of
+                            Sec. 4.2 as it is.  The steady state (Q, G) is the same for every
+                            omega; omega < 1 damps the step-to-step alternation of the
+                            gradient fixed-point iteration */
   void* stream;          /* hipStream_t to run on; NULL = library-owned stream */
   /* Device allocator hook: every device buffer of a context (mesh data,
    * state, work space, Krylov basis), and so of every served request, comes

@@ -56,7 +56,7 @@ class Options(ctypes.Structure):
                 ("weno_eps", ctypes.c_double), ("mu", ctypes.c_double), ("prandtl", ctypes.c_double),
                 ("fd_sigma", ctypes.c_double), ("cfl_flux", ctypes.c_double), ("jv_mode", ctypes.c_int32),
                 ("first_order", ctypes.c_int32), ("solver", ctypes.c_int32), ("compact_subs", ctypes.c_int32),
-                ("max_update", ctypes.c_double)]
+                ("max_update", ctypes.c_double), ("grad_relax", ctypes.c_double)]
 
 
 class StepInfo(ctypes.Structure):
@@ -141,7 +141,7 @@ def default_options(**kw) -> Options:
     o = Options(scheme=WENO, physics=EULER, weights=0, krylov_dim=10, restarts=3, jacobi_sweeps=2,
                 gamma=1.4, cfl=10.0, tau_eps=0.1, tau_C=1.0, gamma_lin=0.025, weno_eps=1e-5,
                 mu=0.0, prandtl=1.0, fd_sigma=0.0, cfl_flux=1.0, jv_mode=0, first_order=0, solver=0,
-                compact_subs=0, max_update=0.0)
+                compact_subs=0, max_update=0.0, grad_relax=1.0)
     for k, v in kw.items():
         setattr(o, k, v)
     return o

@@ -1717,6 +1717,13 @@ static int64_t apply_update(const orc_ctx& C, double* Q, const double* dQ) {
 // ---------------------------------------------------------------------------
 // GMRES (Algorithm 1): left-preconditioned, restarted, MGS Arnoldi, Givens QR
 // ---------------------------------------------------------------------------
+// the gradients after a step: G_new of Sec. 4.2, or with grad_relax = omega < 1
+// the relaxed G + omega (G_new - G) (the same fixed point)
+static void relax_gradients(const orc_ctx& C, const std::vector<double>& Gn, double* G) {
+  const double w = C.o.grad_relax;
+  for (size_t k = 0; k < Gn.size(); ++k) G[k] = w >= 1.0 ? Gn[k] : G[k] + w * (Gn[k] - G[k]);
+}
+
 static int implicit_step(const orc_ctx& C, double* Q, double* G, orc_step_info* info) {
   int N = C.N;
   size_t n = (size_t)5 * N;
@@ -1731,7 +1738,7 @@ static int implicit_step(const orc_ctx& C, double* Q, double* G, orc_step_info* 
     std::vector<double> dQ(n);
     lusgs(C, Q, dt.data(), b.data(), dQ.data());
     info->n_limited = apply_update(C, Q, dQ.data());
-    if (C.o.scheme == 1) std::copy(Gn.begin(), Gn.end(), G);
+    if (C.o.scheme == 1) relax_gradients(C, Gn, G);
     info->gmres_rel = 0.0;
     info->n_resid_evals = evals;
     info->n_fallbacks = fb;
@@ -1822,7 +1829,7 @@ static int implicit_step(const orc_ctx& C, double* Q, double* G, orc_step_info* 
     last = std::fabs(gvec[jdone]);
   }
   info->n_limited = apply_update(C, Q, dQ.data());
-  if (C.o.scheme == 1) std::copy(Gn.begin(), Gn.end(), G);
+  if (C.o.scheme == 1) relax_gradients(C, Gn, G);
   info->gmres_rel = beta0 > 0 ? last / beta0 : 0.0;
   info->n_resid_evals = evals;
   info->n_fallbacks = fb;

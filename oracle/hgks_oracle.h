@@ -53,6 +53,8 @@ typedef struct {
                             by the largest 2^-k (k <= 20) for which its density and pressure
                             change by at most theta of their old values (a runtime policy of
                             the library for impulsive starts; steady states are unchanged) */
+  double grad_relax;     /* compact scheme: G <- G + omega (G_new - G), omega in (0, 1]; 1: G_new
+                            (Sec. 4.2); the steady state is the same for every omega */
 } orc_options;
 
 /* boundary kinds */

@@ -500,6 +500,7 @@ void hgks_default_options(hgks_options* o) {
   o->cfl_flux = 1.0;
   o->cfl_start = 0.0;
   o->cfl_growth = 1.5;
+  o->grad_relax = 1.0;
   o->stream = nullptr;
 }
 
@@ -507,7 +508,8 @@ hgks_status hgks_create(const hgks_options* opts, hgks_ctx** out) {
   if (!opts || !out) return HGKS_EINVAL;
   *out = nullptr;
   if (opts->krylov_dim < 1 || opts->krylov_dim > MAXM || opts->restarts < 1 || opts->jacobi_sweeps < 0 ||
-      !(opts->gamma > 1.0) || !(opts->cfl > 0.0) || !(opts->max_update >= 0.0) || opts->scheme < 0 || opts->scheme > 2 || opts->physics < 0 ||
+      !(opts->gamma > 1.0) || !(opts->cfl > 0.0) || !(opts->max_update >= 0.0) ||
+      !(opts->grad_relax > 0.0 && opts->grad_relax <= 1.0) || opts->scheme < 0 || opts->scheme > 2 || opts->physics < 0 ||
       opts->physics > 1 || opts->precision < 0 || opts->precision > 1 || opts->jv_mode < 0 || opts->jv_mode > 1 ||
       opts->solver < HGKS_SOLVER_GMRES || opts->solver > HGKS_SOLVER_LUSGS || opts->compact_subs < 0 ||
       opts->compact_subs > HGKS_SUBS_HEX_WENO ||
@@ -876,9 +878,13 @@ hgks_status hgks_implicit_step(hgks_ctx* ctx, hgks_step_info* info) {
     launch_axpy_dev(ctx->dQ, ctx->Qc, n, ctx->sc + 4, 1.0, s);  // sc[4] = 1
   if (hw) {
     const int NX = N + ctx->H.Nb;
-    for (int k = 0; k < 15; ++k)
-      HIPCHK(hipMemcpyAsync(ctx->Gc + (size_t)k * NX, ctx->Gnew + (size_t)k * N, (size_t)N * sizeof(double),
-                            hipMemcpyDeviceToDevice, s));
+    if (ctx->o.grad_relax < 1.0) {
+      launch_relax_grad(ctx->Gc, ctx->Gnew, N, NX, ctx->o.grad_relax, s);  // G += omega (G_new - G)
+    } else {
+      for (int k = 0; k < 15; ++k)
+        HIPCHK(hipMemcpyAsync(ctx->Gc + (size_t)k * NX, ctx->Gnew + (size_t)k * N, (size_t)N * sizeof(double),
+                              hipMemcpyDeviceToDevice, s));
+    }
     TRY(refresh_gradients(ctx, s));
   }
   int flags[3] = {0, 0, 0};

@@ -74,6 +74,8 @@ void launch_sigma(const double* vpart, const double* qq, double n, double eps, d
 void launch_diff_norm(const double* x, const double* y, size_t n, double* part, double* out, hipStream_t);
 // out[0] = |x| / den[0] (0 if den[0] is 0)
 void launch_norm_ratio(const double* x, size_t n, const double* den, double* part, double* out, hipStream_t);
+// G[k][i] += w (Gnew[k][i] - G[k][i]) for the 15 gradient rows (G: leading dimension NX, Gnew: N)
+void launch_relax_grad(double* G, const double* Gnew, int N, int NX, double w, hipStream_t);
 // block maxima of max(|v_rho| / rho, |v_m| / sqrt(rho E), |v_E| / E) over the cells into part[REDUCE_PARTS]
 void launch_ratio_part(const double* Q, const double* v, int N, double* part, hipStream_t);
 

@@ -1163,6 +1163,16 @@ __global__ void __launch_bounds__(RB) k_sigma(const double* __restrict__ vpart, 
   sigma[0] = sg;
 }
 
+// relaxed gradient update of the compact scheme: G += w (Gnew - G), 15 rows
+__global__ void __launch_bounds__(256) k_relax_grad(double* __restrict__ G, const double* __restrict__ Gnew, int N,
+                                                    int NX, double w) {
+  const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (size_t)15 * N) return;
+  const size_t k = t / N, i = t - k * N;
+  double* g = G + k * NX + i;
+  *g += w * (Gnew[t] - *g);
+}
+
 template <typename T>
 __global__ void __launch_bounds__(256) k_check(const T* __restrict__ Qx, int N, int NX, double gamma,
                                                int* __restrict__ bad) {
@@ -1381,6 +1391,9 @@ void launch_diff_norm(const double* x, const double* y, size_t n, double* part, 
 void launch_norm_ratio(const double* x, size_t n, const double* den, double* part, double* out, hipStream_t s) {
   hipLaunchKernelGGL(k_reduce_part<0>, dim3(RGRID), dim3(RB), 0, s, x, x, n, part);
   hipLaunchKernelGGL(k_reduce_norm_ratio, dim3(1), dim3(RB), 0, s, part, den, out);
+}
+void launch_relax_grad(double* G, const double* Gnew, int N, int NX, double w, hipStream_t s) {
+  if (N > 0) hipLaunchKernelGGL(k_relax_grad, dim3(nblk((size_t)15 * N, 256)), dim3(256), 0, s, G, Gnew, N, NX, w);
 }
 void launch_ratio_part(const double* Q, const double* v, int N, double* part, hipStream_t s) {
   hipLaunchKernelGGL(k_ratio_part, dim3(RGRID), dim3(RB), 0, s, Q, v, N, part);

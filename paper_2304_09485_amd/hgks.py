@@ -51,7 +51,7 @@ class Options(ctypes.Structure):
                 ("tau_C", ctypes.c_double), ("gamma_lin", ctypes.c_double), ("weno_eps", ctypes.c_double),
                 ("mu", ctypes.c_double), ("prandtl", ctypes.c_double), ("fd_sigma", ctypes.c_double),
                 ("cfl_flux", ctypes.c_double), ("cfl_start", ctypes.c_double), ("cfl_growth", ctypes.c_double),
-                ("max_update", ctypes.c_double),
+                ("max_update", ctypes.c_double), ("grad_relax", ctypes.c_double),
                 ("stream", ctypes.c_void_p), ("dev_alloc", ctypes.c_void_p), ("dev_free", ctypes.c_void_p),
                 ("alloc_user", ctypes.c_void_p)]
 

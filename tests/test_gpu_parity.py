@@ -123,18 +123,19 @@ def test_approximate_matrix_parity(oracle_lib, case):
     np.testing.assert_allclose(ag, ao, rtol=1e-12, atol=1e-12 * np.abs(ao).max())
 
 
-@pytest.mark.parametrize("case", ["c1_weno", "cube_jit_hweno"])
-def test_implicit_steps_approximate_matrix(oracle_lib, case):
+@pytest.mark.parametrize("case,relax", [("c1_weno", 1.0), ("cube_jit_hweno", 1.0), ("cube_jit_hweno", 0.5)])
+def test_implicit_steps_approximate_matrix(oracle_lib, case, relax):
     """Implicit steps with the paper's operator: GMRES is then a linear solve
     whose only difference between the two sides is reduction order, and one
     high-order residual is evaluated per step.  Each GPU step is compared with
-    the oracle's step from the same state: 1e-10 relative."""
+    the oracle's step from the same state: 1e-10 relative.  The compact case
+    also runs with the relaxed gradient update (G + 0.5 (G_new - G))."""
     from paper_2304_09485_amd import hgks
     mk, kinds, mach, opts = C.CASES[case]
     m = mk()
     prim = freestream_prim(mach)
-    o = oracle_lib.Oracle(m, kinds, prim, jv_mode=1, **opts)
-    s = hgks.Solver(m, kinds, prim, jv_mode=hgks.JV_APPROX, **opts)
+    o = oracle_lib.Oracle(m, kinds, prim, jv_mode=1, grad_relax=relax, **opts)
+    s = hgks.Solver(m, kinds, prim, jv_mode=hgks.JV_APPROX, grad_relax=relax, **opts)
     G0 = _grads(case, o.N)
     s.set_state(perturbed_state(o.N, prim, seed=1), G0)
     for k in range(5):
