@@ -317,3 +317,27 @@ def test_update_limit(oracle_lib):
     big = Q0.copy()
     oracle_lib.Oracle(m, kinds, prim, cfl=10.0, jv_mode=1, max_update=1e6).implicit_step(big)
     assert np.array_equal(big, full)
+
+
+def test_relaxed_gradient_update(oracle_lib):
+    """grad_relax = omega (compact scheme): the step's state update does not
+    depend on omega (the gradient update is formed from the base residual at
+    the old state), and the gradients after the step are G + omega (G_1 - G),
+    G_1 being the gradients after the paper's step (omega = 1) from the same
+    (Q, G); omega = 1 is the default."""
+    m = cube_mesh(3, jitter=0.05, seed=5)
+    prim = freestream_prim(0.3)
+    Q0 = perturbed_state(m.n_cells, prim, amp=0.02, seed=6)
+    _, G0, _ = oracle_lib.Oracle(m, ALL_FAR, prim, scheme=1).residual(Q0, np.zeros((15, m.n_cells)), want_grad=True)
+    out = {}
+    for w in (None, 1.0, 0.3):
+        Q, G = Q0.copy(), G0.copy()
+        kw = {} if w is None else {"grad_relax": w}
+        st, _ = oracle_lib.Oracle(m, ALL_FAR, prim, scheme=1, **kw).implicit_step(Q, G)
+        assert st == 0
+        out[w] = (Q, G)
+    assert np.array_equal(out[None][0], out[1.0][0]) and np.array_equal(out[None][1], out[1.0][1])
+    assert np.array_equal(out[0.3][0], out[1.0][0])
+    G1 = out[1.0][1]
+    assert np.abs(G1 - G0).max() > 1e-3 * np.abs(G0).max()
+    np.testing.assert_allclose(out[0.3][1], G0 + 0.3 * (G1 - G0), rtol=0, atol=1e-14 * np.abs(G1).max())
