@@ -281,7 +281,6 @@ struct orc_ctx {
   double rhoinf, pinf;
   int N = 0;
   std::vector<double> vol, hcell, hdt;
-  std::vector<char> stretched;  // tetrahedra past the shape limit of reading A37
   std::vector<V3> cen;
   std::vector<M33> m2;
   std::vector<Face> faces;
@@ -572,14 +571,6 @@ static bool edge_cell(const orc_ctx& C, int i) {
   return false;
 }
 
-// Reading A37: a stretched tetrahedron (longest edge cubed over 6 sqrt(2)
-// times its volume above 20; a regular tetrahedron has 1, the six
-// tetrahedra of a cube 3.7) takes the linear fit for P0 as well.  On the
-// thin cells of a boundary layer the quadratic fit gives the residual,
-// linearised at rest, eigenvalues with positive real part of the order of
-// c/h; with the linear fit there are none.
-static bool stretched_cell(const orc_ctx& C, int i) { return !C.stretched.empty() && C.stretched[i]; }
-
 // Non-compact WENO fits (Sec. 3.2): q[e] are projected averages keyed by
 // position in the big stencil list.
 void fit_weno(const orc_ctx& C, int i, const std::vector<int>& big,
@@ -593,11 +584,11 @@ void fit_weno(const orc_ctx& C, int i, const std::vector<int>& big,
     for (int c = 0; c < 5; ++c) B[r * 5 + c] = qs[r + 1][c] - qs[0][c];
   }
   for (int c = 0; c < 5; ++c) P[c].q0 = qs[0][c];
-  if (full_rank(A, m, 9) && !edge_cell(C, i) && !stretched_cell(C, i)) {
+  if (full_rank(A, m, 9) && !edge_cell(C, i)) {
     householder_lsq(A, B, m, 9, 5, X);
     for (int c = 0; c < 5; ++c)
       for (int k = 0; k < 9; ++k) P[c].a[k] = X[k * 5 + c];
-  } else {  // readings A17, A36 and A37: linear LS on the big stencil
+  } else {  // readings A17 and A36: linear LS on the big stencil
     std::vector<double> A3(m * 3);
     for (int r = 0; r < m; ++r)
       for (int k = 0; k < 3; ++k) A3[r * 3 + k] = A[r * 9 + k];
@@ -1868,22 +1859,6 @@ orc_ctx* orc_create(int64_t n_nodes, const double* xyz, int64_t n_tets, const in
   if (!build(*C, n_nodes, xyz, n_tets, tets, n_bf, bf, btag, n_tags, kind_of_tag)) {
     delete C;
     return nullptr;
-  }
-  // reading A37
-  C->stretched.assign(C->N, 0);
-  for (int i = 0; i < C->N; ++i) {
-    V3 x[4];
-    for (int k = 0; k < 4; ++k) {
-      const int32_t nd = tets[4 * (int64_t)i + k];
-      x[k] = {xyz[3 * (int64_t)nd], xyz[3 * (int64_t)nd + 1], xyz[3 * (int64_t)nd + 2]};
-    }
-    double lmax = 0.0;
-    for (int a = 0; a < 4; ++a)
-      for (int b = a + 1; b < 4; ++b) {
-        V3 e = sub(x[b], x[a]);
-        lmax = std::max(lmax, std::sqrt(dot(e, e)));
-      }
-    C->stretched[i] = lmax * lmax * lmax > 20.0 * 6.0 * std::sqrt(2.0) * C->vol[i];
   }
   return C;
 }

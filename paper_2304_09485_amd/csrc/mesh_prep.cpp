@@ -403,14 +403,13 @@ int finish_mesh(HostMesh& H, const std::vector<Vec3>& cen, const std::vector<Sym
     // P0 operator
     std::vector<double> A((size_t)m * 9), X((size_t)9 * m);
     for (int r = 0; r < m; ++r) row9(i, big[r], &A[(size_t)r * 9]);
-    const bool thin = !H.thin.empty() && H.thin[i];
-    if (m >= 9 && gram_cond_ratio(A.data(), m, 9) > 1e-20 && !at_edge(i) && !thin) {
+    if (m >= 9 && gram_cond_ratio(A.data(), m, 9) > 1e-20 && !at_edge(i)) {
       pinv_mgs(A.data(), m, 9, X.data());
       for (int k = 0; k < 9; ++k)
         for (int r = 0; r < m; ++r) H.opA[(size_t)(k * nbig + r) * N + i] = X[(size_t)k * m + r];
     } else {
-      // rank-deficient big stencil, a cell on a boundary edge or a thin
-      // tetrahedron: linear least squares on the big stencil
+      // rank-deficient big stencil, or a cell on a boundary edge: linear
+      // least squares on the big stencil
       ++nfb;
       std::vector<double> A3((size_t)m * 3), X3((size_t)3 * m);
       for (int r = 0; r < m; ++r)
@@ -533,7 +532,6 @@ int build_host_mesh(HostMesh& H, int64_t n_nodes, const double* xyz, int64_t n_t
   std::vector<Vec3> cen(N);
   std::vector<Sym3> m2(N);
   H.vol.resize(N);
-  H.thin.assign(N, 0);
   for (int i = 0; i < N; ++i) {
     Vec3 v[4];
     for (int k = 0; k < 4; ++k) {
@@ -550,17 +548,6 @@ int build_host_mesh(HostMesh& H, int64_t n_nodes, const double* xyz, int64_t n_t
       return -3;
     }
     H.vol[i] = d6 / 6.0;
-    // a thin tetrahedron (its longest edge cubed over 6 sqrt(2) times its
-    // volume above 20; 1 for a regular one, 3.7 for the six of a cube, near
-    // 100 in a boundary layer) takes the linear fit for P0: the quadratic
-    // fit on such cells gives the residual growing modes of the order of c/h
-    double l2 = 0.0;
-    for (int a = 0; a < 4; ++a)
-      for (int b = a + 1; b < 4; ++b) {
-        const Vec3 e = v[b] - v[a];
-        l2 = std::max(l2, dotp(e, e));
-      }
-    H.thin[i] = l2 * std::sqrt(l2) > 20.0 * std::sqrt(2.0) * d6;
     Vec3 c = 0.25 * (((v[0] + v[1]) + v[2]) + v[3]);
     cen[i] = c;
     Sym3 s;

@@ -18,7 +18,6 @@ struct HostMesh {
   // cells
   std::vector<double> vol, h, hdt, m2s;  // m2s [6][N]
   std::vector<double> cen;               // [3][N]
-  std::vector<char> thin;                // [N] tetrahedra fitted linearly for their shape (empty: none)
   // faces
   std::vector<int> fL, fR, ftag;         // ftag: boundary tag or -1
   std::vector<double> fn, fS, fxiL, fxiR;// fn [3][F], fxi [3 ng][F]
