@@ -1,5 +1,6 @@
 """Host logic of bench.py (CPU): the one-GPU guard, the algorithmic byte
-counts the roofline uses, and the traffic lookup keyed by the kernel sources."""
+counts the roofline uses, the traffic lookup keyed by the kernel sources, and
+the forms and step caps of the time-to-1e-8 record."""
 import os
 import subprocess
 import sys
@@ -60,3 +61,46 @@ def test_method_bytes_follow_the_scheme_table():
     assert bench.method_bytes_per_cell(1, True) == 2208
     # an implicit step of 33 evaluations: the base one and 32 FD products
     assert bench.step_method_bytes(0, 10, 33) == 10 * (2256 + 32 * 2336) / 33
+
+
+def test_time_to_drop_forms_and_step_caps():
+    """The time-to-1e-8 record runs every form on one mesh from the uniform
+    stream, the compact forms with zero gradients, each with the common step
+    cap except the relaxed compact form (1,600 steps at least), and reports
+    each form's solve (a stand-in library records the calls)."""
+    import types
+    import numpy as np
+    import bench
+    from inputs import freestream_prim
+    calls = []
+
+    class Info:
+        steps, converged, drop, t_ms = 7, 1, 5e-9, 12.0
+
+    class Solver:
+        def __init__(self, mesh, kinds, prim, **opts):
+            self.N, self.opts = 10, opts
+
+        def set_state(self, Q, G=None):
+            calls.append(("state", Q.shape, None if G is None else (G.shape, float(np.abs(G).max()))))
+
+        def solve_steady(self, drop, max_steps):
+            calls.append(("solve", dict(self.opts), drop, max_steps))
+            return Info()
+
+        def close(self):
+            pass
+
+    lib = types.SimpleNamespace(WENO=0, HWENO=1, FP32_INNER=1, WEIGHTS_LINEAR=1, Solver=Solver)
+    out = bench.time_to_drop(lib, None, {}, freestream_prim(0.5), 400)
+    solves = [c for c in calls if c[0] == "solve"]
+    states = [c for c in calls if c[0] == "state"]
+    assert len(out) == len(solves) == len(states) == 6
+    assert all(c[2] == 1e-8 for c in solves)
+    for (_, opts, _, cap), (_, qshape, g) in zip(solves, states):
+        assert qshape == (5, 10)
+        assert (g is not None) == (opts["scheme"] == 1)
+        if g is not None:
+            assert g == ((15, 10), 0.0)
+        assert cap == (1600 if opts.get("grad_relax", 1.0) < 1.0 else 400)
+    assert [o["steps"] for o in out] == [7] * 6 and all(o["converged"] for o in out)
