@@ -540,7 +540,7 @@ def time_to_drop(hgks, mesh, kinds, prim, max_steps):
     """Wall time of solve_steady from a uniform free-stream start to a 1e-8
     drop of the density residual, per form, on the same mesh (context set-up
     reported apart).  A form that has not reached the drop after max_steps
-    (the relaxed compact form: 1,600 steps, about 1,400 on the shell)
+    (the relaxed compact form: 1,600 steps, about 1,250 on the shell)
     reports the drop it reached."""
     from inputs import uniform_state
     forms = [("non-compact WENO, FP64", dict(scheme=hgks.WENO), max_steps),
@@ -551,7 +551,7 @@ def time_to_drop(hgks, mesh, kinds, prim, max_steps):
              ("non-compact WENO, linear weights, FP32 inner / FP64 outer",
               dict(scheme=hgks.WENO, weights=hgks.WEIGHTS_LINEAR, precision=hgks.FP32_INNER), max_steps),
              ("compact HWENO, FP64", dict(scheme=hgks.HWENO), max_steps),
-             ("compact HWENO, gradient update relaxed (omega 0.7), FP64", dict(scheme=hgks.HWENO, grad_relax=0.7),
+             ("compact HWENO, gradient update relaxed (omega 0.8), FP64", dict(scheme=hgks.HWENO, grad_relax=0.8),
               max(max_steps, 1600))]
     out = []
     for name, opts, cap in forms:

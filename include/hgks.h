@@ -113,7 +113,8 @@ typedef struct {
                             Sec. 4.2 as it is.  The steady state (Q, G) is the same for every
                             omega; omega < 1 damps the step-to-step alternation of the
                             gradient fixed-point iteration (a mesh-dependent choice: 0.7
-                            on the 202,752-tet sphere shell, 0.5 on a 3,456-tet one).
+                            to 0.8 on the 202,752-tet sphere shell, 0.5 on a 3,456-tet
+                            one).
                             Values outside (0, 1]: HGKS_EINVAL from hgks_create */
   void* stream;          /* hipStream_t to run on; NULL = library-owned stream */
   /* Device allocator hook: every device buffer of a context (mesh data,
